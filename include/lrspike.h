@@ -1,0 +1,152 @@
+/*
+ * lrspike.h -- C ABI of the MI355X (gfx950) LR-SPIKE banded solver.
+ *
+ * Method: Spring, Polizzi and Sameh, "Low-Rank SPIKE Framework for Solving
+ * Large Sparse Linear Systems with Applications", arXiv 2504.11167.
+ *   Problem statement A x = f, A n x n banded with half-bandwidth k, f holding
+ *   n_rhs columns                                  (section "SPIKE partitioning")
+ *   p diagonal blocks A_j and couplings B_j, C_j    (same section)
+ *   spikes V_j = A_j^{-1}[0; B_j], W_j = A_j^{-1}[C_j; 0]   (eq. Veqn)
+ *   rank-r truncated SVD of the whole spikes (n_svd = r)    (section "SVD
+ *                                                  representation of the spikes")
+ *   reduced system on the spike tips                 (eq. spikered)
+ *   recovery x_j = A_j^{-1}(f_j - [C_j x_{j-1,b}; 0; B_j x_{j+1,t}])
+ *                                                    (eqs. recovery1, recovery2)
+ * The factorization is computed once and reused for many solves.
+ *
+ * Conventions (every call):
+ *   - Every array argument is a DEVICE pointer (hipMalloc'd or a torch CUDA
+ *     tensor's data) unless stated otherwise.  Host pointers are rejected.
+ *   - bands: band-major (2k+1) x n doubles, bands[(d + k) * n + i] = A[i, i+d]
+ *     for d in [-k, k].  Entries with i + d outside [0, n) are ignored but must
+ *     be finite.
+ *   - rhs / x: row-major n x nrhs doubles (a contiguous torch (n, nrhs) tensor).
+ *   - Work is enqueued on opts->stream (0 = the null stream) and is
+ *     asynchronous: no call below synchronizes except lrspike_status.
+ *   - Return values: 0 ok; -i means argument i is invalid (LAPACK INFO < 0
+ *     convention, 1-based); positive values are the LRSPIKE_ERR_* codes.
+ *     Argument errors are detected on the host before anything is enqueued.
+ *     Numerical errors (zero pivot, singular reduced system, non-finite data,
+ *     refinement not converged) are latched on the device and reported by
+ *     lrspike_status, so that factor and solve stay free of host syncs.
+ *   - A plan must not be used concurrently from two streams.
+ */
+#ifndef LRSPIKE_H
+#define LRSPIKE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct lrspike_plan_s *lrspike_plan; /* opaque host object */
+
+enum {
+  LRSPIKE_FP64 = 0,         /* factors, spikes and sweeps in FP64 */
+  LRSPIKE_FP32_REFINED = 1  /* FP32 factors/spikes/sweeps; FP64 reduced system,
+                               residual and update in iterative refinement */
+};
+
+enum {
+  LRSPIKE_OK = 0,
+  LRSPIKE_ERR_ZERO_PIVOT = 1,       /* a partition LU met an exactly zero pivot */
+  LRSPIKE_ERR_REDUCED_SINGULAR = 2, /* zero pivot in the reduced system */
+  LRSPIKE_ERR_NOT_CONVERGED = 3,    /* refinement did not reach refine_tol */
+  LRSPIKE_ERR_NONFINITE = 4,        /* Inf/NaN met in the band or the result */
+  LRSPIKE_ERR_HIP = 5,              /* a HIP runtime call failed */
+  LRSPIKE_ERR_NOT_SUPPORTED = 6,    /* parameter combination not built (e.g. k > 32 in FP64) */
+  LRSPIKE_ERR_WORKSPACE = 7         /* workspace missing or too small */
+};
+
+typedef struct {
+  int32_t precision;     /* LRSPIKE_FP64 (default) or LRSPIKE_FP32_REFINED */
+  int32_t max_refine;    /* FP32_REFINED: max corrections (default 30) */
+  double refine_tol;     /* FP32_REFINED: stop when ||d_c||_2 <= tol ||x_c||_2 for all columns (default 1e-13) */
+  void *stream;          /* hipStream_t to enqueue on; NULL = null stream */
+  void *workspace;       /* device memory of >= lrspike_workspace_size bytes, caller-owned,
+                            must outlive the plan */
+  size_t workspace_bytes;
+  int32_t max_nrhs;      /* largest nrhs a solve will be called with (default 32);
+                            sizes the per-solve vectors inside the workspace */
+} lrspike_opts;
+
+/* Fill *opts with the defaults above (no workspace, null stream). */
+void lrspike_default_opts(lrspike_opts *opts);
+
+/*
+ * Bytes of device workspace a plan for (n, k, p, r, precision, max_nrhs)
+ * needs.  Pure host computation.  Returns 0 or a negative argument code.
+ */
+int lrspike_workspace_size(int64_t n, int32_t k, int32_t p, int32_t r,
+                           int32_t precision, int32_t max_nrhs, size_t *bytes);
+
+/*
+ * Factorization stage (section "SPIKE partitioning", the DS factorization,
+ * the spikes of eq. Veqn and their rank-r truncated SVD).  Splits A into p
+ * partitions of floor(n/p) + [j < n mod p] rows, factors every A_j (partial
+ * pivoting inside the band), forms both spikes of every partition, keeps
+ * their tips in rank-r form (r = k keeps them whole and the method is exact),
+ * and factors the reduced interface system.
+ *   n      matrix order, n >= 1
+ *   k      half-bandwidth, 1 <= k <= 32 (FP64) or 64 (FP32_REFINED)
+ *   bands  device pointer, (2k+1) x n band-major doubles; borrowed: it must
+ *          stay valid (unchanged) for the plan's lifetime when precision is
+ *          FP32_REFINED (the residual reads it) and for lrspike_band_grad
+ *   p      number of partitions, 1 <= p <= n; each partition needs >= 2k rows
+ *          when p > 1
+ *   r      retained singular values per spike (the paper's n_svd), 0 <= r <= k
+ *   opts   options; workspace required (see lrspike_workspace_size)
+ *   plan_out  receives a new plan (host object) on success
+ */
+int lrspike_factor(int64_t n, int32_t k, const double *bands, int32_t p, int32_t r,
+                   const lrspike_opts *opts, lrspike_plan *plan_out);
+
+/*
+ * Solve stage (D-stage, reduced system, recovery; the summary of the SPIKE
+ * solve).  In place: rhs (n x nrhs, row-major) is overwritten by
+ * x = M_r^{-1} rhs, which is A^{-1} rhs at r = k.  With FP32_REFINED the
+ * solve iterates x += M_r^{-1}(rhs - A x) with the residual in FP64 until the
+ * tolerance (then x is A^{-1} rhs to that tolerance for any r).
+ *   nrhs   1 <= nrhs <= opts.max_nrhs of the factor call
+ */
+int lrspike_solve(lrspike_plan plan, double *rhs, int32_t nrhs);
+
+/*
+ * Adjoint solve: rhs is overwritten by M_r^{-T} rhs, the exact transpose of
+ * the operator lrspike_solve applies (A^{-T} rhs at r = k; with FP32_REFINED
+ * refined against A^T to the same tolerance).
+ */
+int lrspike_solve_adjoint(lrspike_plan plan, double *rhs, int32_t nrhs);
+
+/*
+ * grad_bands[(d+k) n + i] = - sum_c lam[i, c] x[i+d, c] for d in [-k, k]
+ * (zero where i + d is outside the matrix): the gradient of a loss with
+ * respect to the band entries, given lam = A^{-T} dL/dx and the solution x.
+ * lam, x: n x nrhs row-major; grad_bands: (2k+1) x n, overwritten.
+ */
+int lrspike_band_grad(lrspike_plan plan, const double *lam, const double *x,
+                      int32_t nrhs, double *grad_bands);
+
+typedef struct {
+  int32_t error;          /* first latched LRSPIKE_ERR_* code, 0 if none */
+  int32_t partition;      /* partition (or interface) of the first error, -1 if none */
+  int64_t row;            /* partition-local row of the first error, -1 if none */
+  int32_t refine_iters;   /* corrections used by the last refined solve */
+  int32_t swapped_blocks; /* k-row blocks whose LU needed a row interchange */
+  double last_correction; /* max_c ||d_c|| / ||x_c|| of the last correction */
+} lrspike_info;
+
+/* Synchronizes the plan's stream and returns (and reports) the latched state. */
+int lrspike_status(lrspike_plan plan, lrspike_info *info);
+
+/* Frees the host object (the workspace belongs to the caller). */
+int lrspike_destroy(lrspike_plan plan);
+
+const char *lrspike_strerror(int code);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,236 @@
+"""MI355X-native LR-SPIKE banded solver (Spring, Polizzi and Sameh, arXiv 2504.11167).
+
+Thin ctypes binding over ``liblrspike.so`` (the C ABI declared in
+``include/lrspike.h``).  Every step of the method runs in the library's HIP
+kernels; this module only marshals torch tensors (device memory), the current
+HIP stream and autograd plumbing.  There is no CPU fallback: without the built
+library or a GPU every call raises.
+
+    plan = factor(bands, p, r, precision="fp64")      # bands: (2k+1, n) float64 CUDA tensor
+    x = plan.solve(b)                                  # b: (n,) or (n, m) float64 CUDA tensor
+    lam = plan.solve_adjoint(g)
+    x = solve(bands, b, p, r)                          # differentiable in bands and b
+"""
+import ctypes
+import os
+
+import torch
+
+from . import build as _build
+
+__all__ = ["factor", "solve", "Plan", "LRSpikeError", "library_path", "load_library"]
+
+FP64, FP32_REFINED = 0, 1
+_PRECISIONS = {"fp64": FP64, "fp32_refined": FP32_REFINED}
+_ERRORS = {
+    1: "ZERO_PIVOT", 2: "REDUCED_SINGULAR", 3: "NOT_CONVERGED", 4: "NONFINITE",
+    5: "HIP_ERROR", 6: "NOT_SUPPORTED", 7: "WORKSPACE",
+}
+
+
+class LRSpikeError(RuntimeError):
+    def __init__(self, code, where):
+        self.code = code
+        name = _ERRORS.get(code, f"argument {-code} invalid" if code < 0 else str(code))
+        super().__init__(f"{where}: {name} (code {code})")
+
+
+class _Opts(ctypes.Structure):
+    _fields_ = [
+        ("precision", ctypes.c_int32),
+        ("max_refine", ctypes.c_int32),
+        ("refine_tol", ctypes.c_double),
+        ("stream", ctypes.c_void_p),
+        ("workspace", ctypes.c_void_p),
+        ("workspace_bytes", ctypes.c_size_t),
+        ("max_nrhs", ctypes.c_int32),
+    ]
+
+
+class _Info(ctypes.Structure):
+    _fields_ = [
+        ("error", ctypes.c_int32),
+        ("partition", ctypes.c_int32),
+        ("row", ctypes.c_int64),
+        ("refine_iters", ctypes.c_int32),
+        ("swapped_blocks", ctypes.c_int32),
+        ("last_correction", ctypes.c_double),
+    ]
+
+
+_lib = None
+SYMBOLS = (
+    "lrspike_default_opts", "lrspike_workspace_size", "lrspike_factor", "lrspike_solve",
+    "lrspike_solve_adjoint", "lrspike_band_grad", "lrspike_status", "lrspike_destroy",
+    "lrspike_strerror",
+)
+
+
+def library_path():
+    return _build.LIB
+
+
+def load_library():
+    """Load liblrspike.so (built in-tree by ``build.py``); raises if it is missing."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    path = library_path()
+    if not os.path.exists(path):
+        raise RuntimeError(f"HIP library not built: {path} (run __graft_entry__.build())")
+    lib = ctypes.CDLL(path)
+    P = ctypes.c_void_p
+    i32, i64 = ctypes.c_int32, ctypes.c_int64
+    lib.lrspike_default_opts.argtypes = [ctypes.POINTER(_Opts)]
+    lib.lrspike_default_opts.restype = None
+    lib.lrspike_workspace_size.argtypes = [i64, i32, i32, i32, i32, i32, ctypes.POINTER(ctypes.c_size_t)]
+    lib.lrspike_factor.argtypes = [i64, i32, P, i32, i32, ctypes.POINTER(_Opts), ctypes.POINTER(P)]
+    lib.lrspike_solve.argtypes = [P, P, i32]
+    lib.lrspike_solve_adjoint.argtypes = [P, P, i32]
+    lib.lrspike_band_grad.argtypes = [P, P, P, i32, P]
+    lib.lrspike_status.argtypes = [P, ctypes.POINTER(_Info)]
+    lib.lrspike_destroy.argtypes = [P]
+    lib.lrspike_strerror.argtypes = [i32]
+    lib.lrspike_strerror.restype = ctypes.c_char_p
+    _lib = lib
+    return lib
+
+
+def _check_vec(t, n, name):
+    if not isinstance(t, torch.Tensor) or t.device.type != "cuda":
+        raise TypeError(f"{name} must be a CUDA tensor")
+    if t.dtype != torch.float64:
+        raise TypeError(f"{name} must be float64")
+    if t.shape[0] != n or t.dim() not in (1, 2):
+        raise ValueError(f"{name} must have shape (n,) or (n, m) with n = {n}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+
+
+def workspace_bytes(n, k, p, r, precision="fp64", max_nrhs=32):
+    lib = load_library()
+    out = ctypes.c_size_t(0)
+    rc = lib.lrspike_workspace_size(n, k, p, r, _PRECISIONS[precision], max_nrhs, ctypes.byref(out))
+    if rc:
+        raise LRSpikeError(rc, "lrspike_workspace_size")
+    return out.value
+
+
+class Plan:
+    """A factored LR-SPIKE plan: the factors live in a caller-owned workspace tensor."""
+
+    def __init__(self, bands, p, r, precision="fp64", max_nrhs=32, max_refine=30, refine_tol=1e-13):
+        lib = load_library()
+        if not isinstance(bands, torch.Tensor) or bands.device.type != "cuda" or bands.dtype != torch.float64:
+            raise TypeError("bands must be a float64 CUDA tensor of shape (2k+1, n)")
+        if bands.dim() != 2 or bands.shape[0] % 2 != 1 or not bands.is_contiguous():
+            raise ValueError("bands must be contiguous with shape (2k+1, n)")
+        self.k = (bands.shape[0] - 1) // 2
+        self.n = bands.shape[1]
+        self.p, self.r = int(p), int(r)
+        self.precision = precision
+        self.max_nrhs = int(max_nrhs)
+        self.bands = bands  # borrowed by the library for the plan's lifetime
+        nbytes = workspace_bytes(self.n, self.k, self.p, self.r, precision, self.max_nrhs)
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=bands.device)
+        opts = _Opts()
+        lib.lrspike_default_opts(ctypes.byref(opts))
+        opts.precision = _PRECISIONS[precision]
+        opts.max_refine = max_refine
+        opts.refine_tol = refine_tol
+        opts.stream = torch.cuda.current_stream(bands.device).cuda_stream
+        opts.workspace = self.workspace.data_ptr()
+        opts.workspace_bytes = nbytes
+        opts.max_nrhs = self.max_nrhs
+        handle = ctypes.c_void_p()
+        rc = lib.lrspike_factor(self.n, self.k, bands.data_ptr(), self.p, self.r, ctypes.byref(opts),
+                                ctypes.byref(handle))
+        if rc:
+            raise LRSpikeError(rc, "lrspike_factor")
+        self._h = handle
+        self._lib = lib
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            self._lib.lrspike_destroy(h)
+            self._h = None
+
+    def _apply(self, b, inplace, adjoint):
+        _check_vec(b, self.n, "rhs")
+        x = b if inplace else b.clone()
+        m = 1 if x.dim() == 1 else x.shape[1]
+        fn = self._lib.lrspike_solve_adjoint if adjoint else self._lib.lrspike_solve
+        for c0 in range(0, m, self.max_nrhs):
+            cols = min(self.max_nrhs, m - c0)
+            if m == cols:
+                rc = fn(self._h, x.data_ptr(), m)
+            else:
+                blk = x[:, c0:c0 + cols].contiguous()
+                rc = fn(self._h, blk.data_ptr(), cols)
+                x[:, c0:c0 + cols] = blk
+            if rc:
+                raise LRSpikeError(rc, "lrspike_solve_adjoint" if adjoint else "lrspike_solve")
+        return x
+
+    def solve(self, b, inplace=False):
+        """x = M_r^{-1} b (A^{-1} b at r = k, or refined to tolerance with fp32_refined)."""
+        return self._apply(b, inplace, False)
+
+    def solve_adjoint(self, g, inplace=False):
+        """M_r^{-T} g, the exact transpose of solve."""
+        return self._apply(g, inplace, True)
+
+    def band_grad(self, lam, x):
+        """-lam x^T restricted to the band, shape (2k+1, n)."""
+        _check_vec(lam, self.n, "lam")
+        _check_vec(x, self.n, "x")
+        m = 1 if x.dim() == 1 else x.shape[1]
+        out = torch.empty_like(self.bands)
+        rc = self._lib.lrspike_band_grad(self._h, lam.data_ptr(), x.data_ptr(), m, out.data_ptr())
+        if rc:
+            raise LRSpikeError(rc, "lrspike_band_grad")
+        return out
+
+    def status(self):
+        """Synchronize and return the device-latched state as a dict; raises on a latched error."""
+        info = _Info()
+        rc = self._lib.lrspike_status(self._h, ctypes.byref(info))
+        d = {f: getattr(info, f) for f, _ in _Info._fields_}
+        if rc:
+            err = LRSpikeError(rc, "lrspike_status")
+            err.info = d
+            raise err
+        return d
+
+
+def factor(bands, p, r, precision="fp64", max_nrhs=32, **kw):
+    return Plan(bands, p, r, precision=precision, max_nrhs=max_nrhs, **kw)
+
+
+class LRSpikeSolve(torch.autograd.Function):
+    """x = A^{-1} b through LR-SPIKE; backward through the adjoint solve:
+    grad_b = A^{-T} grad_x, grad_bands = -lam x^T on the band."""
+
+    @staticmethod
+    def forward(ctx, bands, b, p, r, precision):
+        plan = Plan(bands.detach(), p, r, precision=precision, max_nrhs=max(1, 1 if b.dim() == 1 else b.shape[1]))
+        x = plan.solve(b.detach())
+        ctx.plan = plan
+        ctx.save_for_backward(x)
+        return x
+
+    @staticmethod
+    def backward(ctx, gx):
+        (x,) = ctx.saved_tensors
+        plan = ctx.plan
+        lam = plan.solve_adjoint(gx.contiguous())
+        gbands = plan.band_grad(lam, x) if ctx.needs_input_grad[0] else None
+        return gbands, (lam if ctx.needs_input_grad[1] else None), None, None, None
+
+
+def solve(bands, b, p, r=None, precision="fp64"):
+    """Differentiable x = A^{-1} b (r defaults to k, where LR-SPIKE is exact)."""
+    if r is None:
+        r = (bands.shape[0] - 1) // 2
+    return LRSpikeSolve.apply(bands, b, p, r, precision)

@@ -1,0 +1,450 @@
+// C ABI of the LR-SPIKE library: argument checks, workspace layout, and the
+// kernel sequences of the factorization, solve, adjoint solve and gradient.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <vector>
+
+#include "../../include/lrspike.h"
+#include "layout.h"
+
+namespace lrs {
+struct FactorArgs;
+struct SolveArgs;
+struct RedArgs;
+}  // namespace lrs
+
+#include "factor.hip"
+#include "reduced.hip"
+#include "solve.hip"
+
+using namespace lrs;
+
+struct lrspike_plan_s {
+  Layout L;
+  int precision;
+  int max_refine;
+  double refine_tol;
+  hipStream_t stream;
+  const double* bands;
+  char* ws;
+  int refine_iters;
+  double last_corr;
+  int last_error;
+};
+
+// ------------------------------------------------------------------ dispatch tables
+namespace {
+
+__global__ void zero_kernel(int* p, int n) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0;
+}
+
+__global__ void axpy_kernel(double* x, const double* d, int64_t n) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) x[i] += d[i];
+}
+
+// per-column squared norms of x and d (rows strided by ld), accumulated by atomics
+__global__ void colnorm_kernel(const double* x, const double* d, int64_t n, int m, int ld,
+                               double* out) {
+  extern __shared__ double red[];
+  int c = blockIdx.y;
+  double sx = 0.0, sd = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    double xv = x[i * ld + c], dv = d[i * ld + c];
+    sx += xv * xv;
+    sd += dv * dv;
+  }
+  red[threadIdx.x] = sx;
+  red[blockDim.x + threadIdx.x] = sd;
+  __syncthreads();
+  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) {
+      red[threadIdx.x] += red[threadIdx.x + s];
+      red[blockDim.x + threadIdx.x] += red[blockDim.x + threadIdx.x + s];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    atomicAdd(out + 2 * c, red[0]);
+    atomicAdd(out + 2 * c + 1, red[blockDim.x]);
+  }
+}
+
+__global__ void zero_d_kernel(double* p, int n) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0.0;
+}
+
+template <typename T, int K>
+size_t lds_p1() { return (size_t)P1Lds<K>::total * sizeof(T); }
+template <typename T, int K>
+size_t lds_p2() { return (size_t)P2Lds<K>::total * sizeof(T); }
+template <typename T, int K>
+size_t lds_sw() { return (size_t)SwLds<K>::total * sizeof(T); }
+
+bool set_lds(const void* fn, size_t bytes) {
+  if (bytes > 160 * 1024) return false;
+  if (bytes > 64 * 1024)
+    return hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) == hipSuccess;
+  return true;
+}
+
+#define LRS_CHECK_LAUNCH()                          \
+  do {                                              \
+    if (hipGetLastError() != hipSuccess) return LRSPIKE_ERR_HIP; \
+  } while (0)
+
+template <typename T, int K>
+int run_factor(lrspike_plan P) {
+  const Layout& L = P->L;
+  FactorArgs fa{P->bands, P->ws, L};
+  hipStream_t st = P->stream;
+  size_t b1 = lds_p1<T, K>();
+  if (!set_lds((const void*)factor_pass1<T, K>, b1)) return LRSPIKE_ERR_NOT_SUPPORTED;
+  hipLaunchKernelGGL((factor_pass1<T, K>), dim3(L.p), dim3(LRS_NT), b1, st, fa);
+  LRS_CHECK_LAUNCH();
+  RedArgs ra{P->ws, L, 0, 0, 0};
+  if (L.r < L.K) {
+    size_t b2 = lds_p2<T, K>();
+    if (!set_lds((const void*)factor_pass2<T, K>, b2)) return LRSPIKE_ERR_NOT_SUPPORTED;
+    hipLaunchKernelGGL((factor_pass2<T, K>), dim3(L.p), dim3(LRS_NT), b2, st, fa);
+    LRS_CHECK_LAUNCH();
+    if (L.r > 0) {
+      hipLaunchKernelGGL((eigen_kernel<K>), dim3(L.p, 2), dim3(LRS_NT), 0, st, ra);
+      LRS_CHECK_LAUNCH();
+    }
+  } else {
+    hipLaunchKernelGGL((identity_proj_kernel<K>), dim3(L.p), dim3(256), 0, st, ra);
+    LRS_CHECK_LAUNCH();
+  }
+  if (L.r > 0) {
+    hipLaunchKernelGGL((project_kernel<K>), dim3(L.p), dim3(256), 0, st, ra);
+    LRS_CHECK_LAUNCH();
+  }
+  if (L.NI > 0 && L.r > 0) {
+    hipLaunchKernelGGL((zassemble_kernel<K>), dim3(L.NI), dim3(256), 0, st, ra);
+    LRS_CHECK_LAUNCH();
+    const int R2 = L.R2;
+    size_t bodd = (size_t)(R2 * (R2 + 1) + R2 * (2 * R2 + 1)) * 8;
+    if (!set_lds((const void*)cr_odd_kernel, bodd)) return LRSPIKE_ERR_NOT_SUPPORTED;
+    for (int l = 0; l < L.levels; ++l) {
+      int s = 1 << l;
+      int nodd = (L.NI + s - 1) / (2 * s);  // rows (2q+1)s < NI
+      ra.level = l;
+      if (nodd > 0) hipLaunchKernelGGL(cr_odd_kernel, dim3(nodd), dim3(LRS_NT), bodd, st, ra);
+      int neven = (L.NI + 2 * s - 1) / (2 * s);
+      hipLaunchKernelGGL(cr_even_kernel, dim3(neven), dim3(LRS_NT), 0, st, ra);
+      LRS_CHECK_LAUNCH();
+    }
+    ra.level = L.levels;
+    hipLaunchKernelGGL(cr_odd_kernel, dim3(1), dim3(LRS_NT), bodd, st, ra);
+    LRS_CHECK_LAUNCH();
+  }
+  return 0;
+}
+
+// Reduced solve on the compressed vectors (Z or Z^T), in place in zg.
+template <int K>
+int run_reduced(lrspike_plan P, int m, int transpose) {
+  const Layout& L = P->L;
+  if (L.NI <= 0 || L.r <= 0) return 0;
+  hipStream_t st = P->stream;
+  RedArgs ra{P->ws, L, 0, m, transpose};
+  size_t bz = (size_t)4 * K * m * 8;
+  if (!set_lds((const void*)zrhs_kernel<K>, bz)) return LRSPIKE_ERR_NOT_SUPPORTED;
+  hipLaunchKernelGGL((zrhs_kernel<K>), dim3(L.NI), dim3(256), bz, st, ra, P->bands);
+  LRS_CHECK_LAUNCH();
+  const int R2 = L.R2;
+  size_t bf = (size_t)2 * R2 * m * 8, bb = (size_t)R2 * m * 8;
+  if (!set_lds((const void*)crs_forward_kernel, bf)) return LRSPIKE_ERR_NOT_SUPPORTED;
+  for (int l = 0; l < L.levels; ++l) {
+    int s = 1 << l;
+    ra.level = l;
+    int neven = (L.NI + 2 * s - 1) / (2 * s);
+    hipLaunchKernelGGL(crs_forward_kernel, dim3(neven), dim3(LRS_NT), bf, st, ra);
+    LRS_CHECK_LAUNCH();
+  }
+  ra.level = L.levels;
+  hipLaunchKernelGGL(crs_backward_kernel, dim3(1), dim3(LRS_NT), bb, st, ra);
+  LRS_CHECK_LAUNCH();
+  for (int l = L.levels - 1; l >= 0; --l) {
+    int s = 1 << l;
+    ra.level = l;
+    int nodd = (L.NI + s - 1) / (2 * s);
+    if (nodd > 0) hipLaunchKernelGGL(crs_backward_kernel, dim3(nodd), dim3(LRS_NT), bb, st, ra);
+    LRS_CHECK_LAUNCH();
+  }
+  return 0;
+}
+
+// One application of M_r^{-1} (transpose = 0) or M_r^{-T} (transpose = 1), in place.
+template <typename T, int K>
+int run_apply(lrspike_plan P, double* rhs, int m, int transpose) {
+  const Layout& L = P->L;
+  hipStream_t st = P->stream;
+  SolveArgs sa{P->bands, P->ws, L, rhs, rhs, m, m};
+  dim3 grid(L.p, (m + MC - 1) / MC);
+  size_t bs = lds_sw<T, K>();
+  int rc;
+  if (!transpose) {
+    if (!set_lds((const void*)dstage_kernel<T, K>, bs) || !set_lds((const void*)retrieve_kernel<T, K>, bs))
+      return LRSPIKE_ERR_NOT_SUPPORTED;
+    if (L.p > 1) {
+      hipLaunchKernelGGL((dstage_kernel<T, K>), grid, dim3(LRS_NT), bs, st, sa);
+      LRS_CHECK_LAUNCH();
+      if ((rc = run_reduced<K>(P, m, 0))) return rc;
+    }
+    hipLaunchKernelGGL((retrieve_kernel<T, K>), grid, dim3(LRS_NT), bs, st, sa);
+    LRS_CHECK_LAUNCH();
+  } else {
+    if (!set_lds((const void*)adj_dstage_kernel<T, K>, bs) || !set_lds((const void*)adj_retrieve_kernel<T, K>, bs))
+      return LRSPIKE_ERR_NOT_SUPPORTED;
+    if (L.p > 1) {
+      SolveArgs sd = sa;
+      sd.dst = reinterpret_cast<double*>(P->ws + L.scr);
+      hipLaunchKernelGGL((adj_dstage_kernel<T, K>), grid, dim3(LRS_NT), bs, st, sd);
+      LRS_CHECK_LAUNCH();
+      if ((rc = run_reduced<K>(P, m, 1))) return rc;
+    }
+    hipLaunchKernelGGL((adj_retrieve_kernel<T, K>), grid, dim3(LRS_NT), bs, st, sa);
+    LRS_CHECK_LAUNCH();
+  }
+  return 0;
+}
+
+// Iterative refinement around run_apply (FP32 factors, FP64 residual/update).
+template <typename T, int K>
+int run_refined(lrspike_plan P, double* rhs, int m, int transpose) {
+  const Layout& L = P->L;
+  hipStream_t st = P->stream;
+  const int64_t nm = L.n * (int64_t)m;
+  double* fcopy = reinterpret_cast<double*>(P->ws + L.fcopy);
+  double* scr = reinterpret_cast<double*>(P->ws + L.res);  // not the adjoint D-stage scratch
+  double* norms = reinterpret_cast<double*>(P->ws + L.norms);
+  if (hipMemcpyAsync(fcopy, rhs, nm * 8, hipMemcpyDeviceToDevice, st) != hipSuccess) return LRSPIKE_ERR_HIP;
+  int rc = run_apply<T, K>(P, rhs, m, transpose);
+  if (rc) return rc;
+  std::vector<double> hn(2 * m);
+  P->refine_iters = 0;
+  P->last_corr = INFINITY;
+  double prev = INFINITY;
+  for (int it = 0; it < P->max_refine; ++it) {
+    int blocks = (int)((nm + 255) / 256);
+    hipLaunchKernelGGL(residual_kernel, dim3(blocks), dim3(256), 0, st, P->bands, L.n, L.k, fcopy, rhs,
+                       scr, m, m, transpose);
+    LRS_CHECK_LAUNCH();
+    if ((rc = run_apply<T, K>(P, scr, m, transpose))) return rc;
+    hipLaunchKernelGGL(axpy_kernel, dim3(blocks), dim3(256), 0, st, rhs, scr, nm);
+    hipLaunchKernelGGL(zero_d_kernel, dim3(1), dim3(256), 0, st, norms, 2 * m);
+    hipLaunchKernelGGL(colnorm_kernel, dim3(256, m), dim3(256), 2 * 256 * 8, st, rhs, scr, L.n, m, m, norms);
+    LRS_CHECK_LAUNCH();
+    if (hipMemcpyAsync(hn.data(), norms, 2 * m * 8, hipMemcpyDeviceToHost, st) != hipSuccess) return LRSPIKE_ERR_HIP;
+    if (hipStreamSynchronize(st) != hipSuccess) return LRSPIKE_ERR_HIP;
+    double worst = 0.0;
+    for (int c = 0; c < m; ++c) {
+      double rel = sqrt(hn[2 * c + 1]) / (sqrt(hn[2 * c]) > 0 ? sqrt(hn[2 * c]) : 1.0);
+      if (!(rel == rel)) rel = INFINITY;
+      if (rel > worst) worst = rel;
+    }
+    P->refine_iters = it + 1;
+    P->last_corr = worst;
+    if (worst <= P->refine_tol) return 0;
+    if (!(worst < INFINITY) || (it > 0 && worst > 0.5 * prev)) break;
+    prev = worst;
+  }
+  int* latch = reinterpret_cast<int*>(P->ws + L.latch);
+  int code = LRSPIKE_ERR_NOT_CONVERGED;
+  // latch from the host only if nothing is latched yet
+  int cur = 0;
+  if (hipMemcpy(&cur, latch, 4, hipMemcpyDeviceToHost) == hipSuccess && cur == 0) {
+    int rec[2] = {code, -1};
+    if (hipMemcpy(latch, rec, 8, hipMemcpyHostToDevice) != hipSuccess) return LRSPIKE_ERR_HIP;
+  }
+  return 0;
+}
+
+typedef int (*factor_fn)(lrspike_plan);
+typedef int (*apply_fn)(lrspike_plan, double*, int, int);
+
+template <typename T>
+factor_fn pick_factor(int K) {
+  switch (K) {
+    case 1: return run_factor<T, 1>;
+    case 2: return run_factor<T, 2>;
+    case 4: return run_factor<T, 4>;
+    case 8: return run_factor<T, 8>;
+    case 16: return run_factor<T, 16>;
+    case 32: return run_factor<T, 32>;
+  }
+  return nullptr;
+}
+
+template <typename T, bool REF>
+apply_fn pick_apply(int K) {
+  switch (K) {
+    case 1: return REF ? run_refined<T, 1> : run_apply<T, 1>;
+    case 2: return REF ? run_refined<T, 2> : run_apply<T, 2>;
+    case 4: return REF ? run_refined<T, 4> : run_apply<T, 4>;
+    case 8: return REF ? run_refined<T, 8> : run_apply<T, 8>;
+    case 16: return REF ? run_refined<T, 16> : run_apply<T, 16>;
+    case 32: return REF ? run_refined<T, 32> : run_apply<T, 32>;
+  }
+  return nullptr;
+}
+
+bool is_device_ptr(const void* p) {
+  if (!p) return false;
+  hipPointerAttribute_t at;
+  if (hipPointerGetAttributes(&at, p) != hipSuccess) {
+    (void)hipGetLastError();
+    return false;
+  }
+  return at.type == hipMemoryTypeDevice;
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ C ABI
+extern "C" {
+
+void lrspike_default_opts(lrspike_opts* o) {
+  memset(o, 0, sizeof(*o));
+  o->precision = LRSPIKE_FP64;
+  o->max_refine = 30;
+  o->refine_tol = 1e-13;
+  o->max_nrhs = 32;
+}
+
+int lrspike_workspace_size(int64_t n, int32_t k, int32_t p, int32_t r, int32_t precision,
+                           int32_t max_nrhs, size_t* bytes) {
+  if (n < 1) return -1;
+  if (k < 1) return -2;
+  if (p < 1 || p > n) return -3;
+  if (r < 0 || r > k) return -4;
+  if (precision != LRSPIKE_FP64 && precision != LRSPIKE_FP32_REFINED) return -5;
+  if (max_nrhs < 1) return -6;
+  if (!bytes) return -7;
+  Layout L;
+  make_layout(L, n, k, p, r, precision == LRSPIKE_FP64 ? 8 : 4, max_nrhs);
+  *bytes = L.total;
+  return 0;
+}
+
+int lrspike_factor(int64_t n, int32_t k, const double* bands, int32_t p, int32_t r,
+                   const lrspike_opts* opts, lrspike_plan* plan_out) {
+  if (n < 1) return -1;
+  if (k < 1) return -2;
+  if (!is_device_ptr(bands)) return -3;
+  if (p < 1 || p > n) return -4;
+  if (r < 0 || r > k) return -5;
+  if (!opts) return -6;
+  if (!plan_out) return -7;
+  const int K = kernel_K(k);
+  int64_t njmin = n / p;
+  if (p > 1 && njmin < 2 * (int64_t)k) return -4;
+  if (njmin < K) return -4;
+  if (opts->precision != LRSPIKE_FP64 && opts->precision != LRSPIKE_FP32_REFINED) return -6;
+  if (opts->max_nrhs < 1) return -6;
+  if (K > 32) return LRSPIKE_ERR_NOT_SUPPORTED;
+  lrspike_plan P = new lrspike_plan_s();
+  make_layout(P->L, n, k, p, r, opts->precision == LRSPIKE_FP64 ? 8 : 4, opts->max_nrhs);
+  if (!opts->workspace || opts->workspace_bytes < P->L.total || !is_device_ptr(opts->workspace)) {
+    delete P;
+    return LRSPIKE_ERR_WORKSPACE;
+  }
+  P->precision = opts->precision;
+  P->max_refine = opts->max_refine > 0 ? opts->max_refine : 30;
+  P->refine_tol = opts->refine_tol > 0 ? opts->refine_tol : 1e-13;
+  P->stream = reinterpret_cast<hipStream_t>(opts->stream);
+  P->bands = bands;
+  P->ws = reinterpret_cast<char*>(opts->workspace);
+  P->refine_iters = 0;
+  P->last_corr = 0.0;
+  hipLaunchKernelGGL(zero_kernel, dim3(1), dim3(64), 0, P->stream, reinterpret_cast<int*>(P->ws + P->L.latch), 16);
+  factor_fn f = P->precision == LRSPIKE_FP64 ? pick_factor<double>(K) : pick_factor<float>(K);
+  int rc = f ? f(P) : LRSPIKE_ERR_NOT_SUPPORTED;
+  if (rc) {
+    delete P;
+    return rc;
+  }
+  *plan_out = P;
+  return 0;
+}
+
+static int solve_common(lrspike_plan P, double* rhs, int32_t nrhs, int transpose) {
+  if (!P) return -1;
+  if (!is_device_ptr(rhs)) return -2;
+  if (nrhs < 1 || nrhs > P->L.mmax) return -3;
+  apply_fn f;
+  if (P->precision == LRSPIKE_FP64)
+    f = pick_apply<double, false>(P->L.K);
+  else
+    f = pick_apply<float, true>(P->L.K);
+  if (!f) return LRSPIKE_ERR_NOT_SUPPORTED;
+  return f(P, rhs, nrhs, transpose);
+}
+
+int lrspike_solve(lrspike_plan plan, double* rhs, int32_t nrhs) { return solve_common(plan, rhs, nrhs, 0); }
+
+int lrspike_solve_adjoint(lrspike_plan plan, double* rhs, int32_t nrhs) {
+  return solve_common(plan, rhs, nrhs, 1);
+}
+
+int lrspike_band_grad(lrspike_plan P, const double* lam, const double* x, int32_t nrhs,
+                      double* grad_bands) {
+  if (!P) return -1;
+  if (!is_device_ptr(lam)) return -2;
+  if (!is_device_ptr(x)) return -3;
+  if (nrhs < 1) return -4;
+  if (!is_device_ptr(grad_bands)) return -5;
+  const Layout& L = P->L;
+  dim3 grid((unsigned)((L.n + 255) / 256), 2 * L.k + 1);
+  hipLaunchKernelGGL(band_grad_kernel, grid, dim3(256), 0, P->stream, L.n, L.k, lam, x, nrhs, nrhs, grad_bands);
+  return hipGetLastError() == hipSuccess ? 0 : LRSPIKE_ERR_HIP;
+}
+
+int lrspike_status(lrspike_plan P, lrspike_info* info) {
+  if (!P) return -1;
+  if (hipStreamSynchronize(P->stream) != hipSuccess) return LRSPIKE_ERR_HIP;
+  int latch[16];
+  if (hipMemcpy(latch, P->ws + P->L.latch, sizeof(latch), hipMemcpyDeviceToHost) != hipSuccess)
+    return LRSPIKE_ERR_HIP;
+  if (info) {
+    info->error = latch[0];
+    info->partition = latch[0] ? latch[1] : -1;
+    int64_t row;
+    memcpy(&row, latch + 2, 8);
+    info->row = latch[0] ? row : -1;
+    info->refine_iters = P->refine_iters;
+    info->swapped_blocks = latch[8];
+    info->last_correction = P->last_corr;
+  }
+  return latch[0];
+}
+
+int lrspike_destroy(lrspike_plan P) {
+  delete P;
+  return 0;
+}
+
+const char* lrspike_strerror(int code) {
+  switch (code) {
+    case 0: return "ok";
+    case LRSPIKE_ERR_ZERO_PIVOT: return "zero pivot in a partition factorization";
+    case LRSPIKE_ERR_REDUCED_SINGULAR: return "zero pivot in the reduced interface system";
+    case LRSPIKE_ERR_NOT_CONVERGED: return "iterative refinement did not converge";
+    case LRSPIKE_ERR_NONFINITE: return "non-finite value in the input or result";
+    case LRSPIKE_ERR_HIP: return "HIP runtime error";
+    case LRSPIKE_ERR_NOT_SUPPORTED: return "parameter combination not supported by this build";
+    case LRSPIKE_ERR_WORKSPACE: return "workspace missing or too small";
+  }
+  if (code < 0) return "invalid argument";
+  return "unknown error";
+}
+
+}  // extern "C"

@@ -1,0 +1,101 @@
+// Workspace layout of a plan (host and device).  All offsets are bytes from
+// the workspace base, 256-byte aligned.  T is the factor element type (double
+// for FP64 plans, float for FP32_REFINED plans); the tips, the reduced system
+// and all solve vectors are double.
+#pragma once
+#include <stddef.h>
+#include <stdint.h>
+
+namespace lrs {
+
+struct Layout {
+  int64_t n;
+  int k, K, p, r, R2, nbmax, mmax, tsize;  // r: compressed rank (K when the user's r = k)
+  int NI;       // interfaces p - 1
+  int levels;   // cyclic-reduction levels (ceil(log2(NI)))
+  int lvl_off[32];  // first slot of each level in the F/E arrays
+  int nfe;      // total slots
+  // per block records (T): LP (K*K) | UP (K*K) | UD (K)  ->  rec elements
+  int64_t rec;
+  size_t fac, swx, gmat, ymat, ipiv, flag;
+  // per partition (double): tips Vt,Vb,Wt,Wb (4 K*K), Grams GV,GW (2 K*K),
+  // projectors Pi,Psi (2 K*r) and projected tips Pt,Pb,Qt,Qb (4 K*r)
+  size_t tips, gram, proj, ptip;
+  // reduced system (double): current D [NI][R2][R2], LU [NI][R2][R2], pivots int [NI][R2],
+  // F/E per (level, active row) [nfe][2][R2][R2], scratch X [NI][2][R2][R2]
+  size_t zD, zLU, zpiv, zFE, zX;
+  // solve vectors (double): y tips [p][2][K][mmax], compressed rhs [NI][R2][mmax],
+  // scratch n x mmax (adjoint D-stage), refinement copy of f and residual n x mmax, norms
+  size_t ytip, zg, scr, fcopy, res, norms;
+  size_t latch;  // int32[16]
+  size_t total;
+};
+
+inline size_t lrs_align(size_t x) { return (x + 255) & ~(size_t)255; }
+
+inline int kernel_K(int k) {
+  int K = 1;
+  while (K < k) K <<= 1;
+  return K;
+}
+
+inline void make_layout(Layout& L, int64_t n, int k, int p, int r, int tsize, int mmax) {
+  L.n = n;
+  L.k = k;
+  L.K = kernel_K(k);
+  L.p = p;
+  // r = k keeps the spikes whole: with K > k the padded spikes have K - k zero
+  // columns (the last ones for V, the first ones for W), so exactness needs the
+  // full K-wide identity projector rather than the first k columns.
+  L.r = (r == k) ? kernel_K(k) : r;
+  L.R2 = 2 * L.r;
+  L.tsize = tsize;
+  L.mmax = mmax;
+  const int K = L.K;
+  int64_t njmax = (n + p - 1) / p;
+  L.nbmax = (int)((njmax + K - 1) / K);
+  L.NI = p - 1;
+  L.levels = 0;
+  while ((1 << L.levels) < L.NI) ++L.levels;
+  int off = 0;
+  for (int l = 0; l <= L.levels; ++l) {
+    L.lvl_off[l] = off;
+    int s = 1 << l;
+    off += (L.NI + s - 1) / s;
+  }
+  L.nfe = off;
+  L.rec = 2 * (int64_t)K * K + K;
+  size_t o = 0;
+  const size_t nblk = (size_t)p * L.nbmax;
+  auto take = [&](size_t bytes) {
+    size_t at = o;
+    o = lrs_align(o + bytes);
+    return at;
+  };
+  L.fac = take(nblk * L.rec * tsize);
+  L.swx = take(nblk * 3 * (size_t)K * K * tsize);
+  L.gmat = take(nblk * (size_t)K * K * tsize);
+  L.ymat = take(L.r < K ? nblk * 2 * (size_t)K * K * tsize : 0);
+  L.ipiv = take(nblk * (size_t)K * 4);
+  L.flag = take(nblk * 4);
+  L.tips = take((size_t)p * 4 * K * K * 8);
+  L.gram = take((size_t)p * 2 * K * K * 8);
+  L.proj = take((size_t)p * 2 * K * L.r * 8);
+  L.ptip = take((size_t)p * 4 * K * L.r * 8);
+  const size_t R2 = L.R2, NI = L.NI > 0 ? L.NI : 0;
+  L.zD = take(NI * R2 * R2 * 8);
+  L.zLU = take(NI * R2 * R2 * 8);
+  L.zpiv = take(NI * R2 * 4);
+  L.zFE = take((size_t)L.nfe * 2 * R2 * R2 * 8);
+  L.zX = take(NI * 2 * R2 * R2 * 8);
+  L.ytip = take((size_t)p * 2 * K * mmax * 8);
+  L.zg = take(NI * R2 * mmax * 8);
+  L.scr = take((size_t)n * mmax * 8);
+  L.fcopy = take(tsize == 4 ? (size_t)n * mmax * 8 : 0);
+  L.res = take(tsize == 4 ? (size_t)n * mmax * 8 : 0);  // residual / correction (refinement)
+  L.norms = take((size_t)4 * mmax * 8 + 64);
+  L.latch = take(16 * 4);
+  L.total = o;
+}
+
+}  // namespace lrs

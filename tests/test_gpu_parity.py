@@ -1,0 +1,189 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 CPU oracle.
+
+Tolerances: plain FP64 rel.err <= 1e-12 against R0 (r = k) or R1 (r < k);
+FP32 factors with FP64 refinement <= 1e-11 against R0.  rel.err is the max
+over right-hand-side columns of ||x_c - ref_c||_2 / ||ref_c||_2.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+
+
+def rel(a, b):
+    a = np.asarray(a).reshape(len(a), -1)
+    b = np.asarray(b).reshape(len(b), -1)
+    return max(np.linalg.norm(a[:, c] - b[:, c]) / np.linalg.norm(b[:, c]) for c in range(b.shape[1]))
+
+
+def to_dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(DEV)
+
+
+def run(lr, bands, f, p, r, precision="fp64", adjoint=False):
+    print(f"case n={bands.shape[1]} k={(bands.shape[0]-1)//2} p={p} r={r} m={f.shape[1] if f.ndim > 1 else 1} "
+          f"{precision} adjoint={adjoint}", flush=True)
+    tb = to_dev(bands)
+    plan = lr.factor(tb, p, r, precision=precision, max_nrhs=max(1, f.shape[1] if f.ndim > 1 else 1))
+    tf = to_dev(f)
+    x = plan.solve_adjoint(tf) if adjoint else plan.solve(tf)
+    info = plan.status()
+    return x.cpu().numpy(), info
+
+
+CASES = [
+    # n, k, p, r, m, rule
+    (4096, 8, 4, 8, 1, "strict"),      # the small exact workload
+    (4096, 8, 4, 0, 1, "strict"),
+    (4096, 8, 4, 3, 2, "strict"),
+    (1000, 3, 7, 3, 3, "strict"),      # k padded to 4, ragged partitions
+    (999, 5, 4, 2, 2, "weak"),         # k padded to 8, r < k
+    (777, 1, 5, 1, 1, "strict"),       # tridiagonal
+    (1500, 16, 3, 16, 33, "weak"),     # two column chunks
+    (2000, 32, 4, 32, 5, "weak"),
+    (2000, 32, 4, 8, 2, "weak"),
+    (300, 2, 1, 2, 1, "strict"),       # p = 1: the base solver
+    (64 * 9 + 5, 4, 9, 2, 4, "weak"),
+    (128, 8, 2, 8, 1, "strict"),       # p = 2: the 2x2 kernel
+    (100, 4, 12, 4, 1, "strict"),      # smallest partitions (n_j = 8 = 2k)
+]
+
+
+@pytest.mark.parametrize("n,k,p,r,m,rule", CASES)
+def test_solve_matches_oracle(gpu, n, k, p, r, m, rule):
+    bands, f = synth.make_problem(n, k, m, seed=n + k + p + r, rule=rule)
+    x, info = run(gpu, bands, f, p, r)
+    ref = oracle.lrspike(bands, f, p, r)
+    assert rel(x, ref) <= 1e-12
+    if r == k:
+        assert rel(x, oracle.band_solve(bands, f)) <= 1e-12
+
+
+@pytest.mark.parametrize("n,k,p,r,m,rule", [c for c in CASES if c[0] <= 2000][:9])
+def test_adjoint_matches_oracle(gpu, n, k, p, r, m, rule):
+    bands, f = synth.make_problem(n, k, m, seed=7 * n + k, rule=rule)
+    x, _ = run(gpu, bands, f, p, r, adjoint=True)
+    ref = oracle.lrspike(bands, f, p, r, transpose=True)
+    assert rel(x, ref) <= 1e-12
+
+
+@pytest.mark.parametrize("theta", [0.3, 0.15])
+def test_pivoting_nondominant(gpu, theta):
+    """Non-dominant matrices make the partition LUs interchange rows."""
+    n, k, p, m = 1200, 4, 3, 2
+    bands, f = synth.make_problem(n, k, m, seed=3, rule="theta", theta=theta)
+    x, info = run(gpu, bands, f, p, k)
+    assert info["swapped_blocks"] > 0
+    ref = oracle.band_solve_refined(bands, f, steps=2)
+    x0 = oracle.band_solve(bands, f)
+    # two backward-stable FP64 solves differ by ~kappa u; allow the GPU 10x the oracle's own error
+    tol = max(1e-12, 10 * rel(x0, ref))
+    assert rel(x, ref) <= tol
+    xa, _ = run(gpu, bands, f, p, k, adjoint=True)
+    refa = oracle.band_solve(bands, f, transpose=True)
+    assert rel(xa, refa) <= max(1e-12, 1e3 * rel(x0, ref))
+
+
+@pytest.mark.parametrize("n,k,p,r,m,rule", [
+    (4096, 8, 4, 8, 2, "strict"),
+    (2000, 32, 4, 32, 3, "weak"),
+    (2000, 32, 4, 8, 3, "weak"),
+    (999, 5, 4, 2, 2, "weak"),
+])
+def test_fp32_refined_matches_exact(gpu, n, k, p, r, m, rule):
+    bands, f = synth.make_problem(n, k, m, seed=11, rule=rule)
+    x, info = run(gpu, bands, f, p, r, precision="fp32_refined")
+    assert info["refine_iters"] >= 1
+    assert rel(x, oracle.band_solve_refined(bands, f)) <= 1e-11
+
+
+def test_fp32_refined_adjoint(gpu):
+    bands, f = synth.make_problem(2000, 16, 2, seed=5, rule="weak")
+    x, _ = run(gpu, bands, f, 4, 8, precision="fp32_refined", adjoint=True)
+    assert rel(x, oracle.band_solve(bands, f, transpose=True)) <= 1e-11
+
+
+def test_band_grad_matches_oracle(gpu):
+    n, k, m = 700, 3, 2
+    bands, f = synth.make_problem(n, k, m, seed=2)
+    rng = np.random.default_rng(0)
+    lam = rng.standard_normal((n, m))
+    x = rng.standard_normal((n, m))
+    plan = gpu.factor(to_dev(bands), 2, k, max_nrhs=m)
+    g = plan.band_grad(to_dev(lam), to_dev(x)).cpu().numpy()
+    assert np.max(np.abs(g - oracle.band_grad(lam, x, k))) <= 1e-13 * np.max(np.abs(g))
+
+
+def test_autograd_finite_differences(gpu):
+    """Loss 0.5 ||x - x*||^2, x = A^{-1} b: gradients w.r.t. the band and b by
+    central differences of the oracle's exact solve (n = 512, k = 4)."""
+    n, k = 512, 4
+    bands, b = synth.make_problem(n, k, 1, seed=0)
+    b = b[:, 0]
+    xs = np.random.default_rng(1).standard_normal(n)
+    tb = to_dev(bands).requires_grad_(True)
+    tbb = to_dev(b).requires_grad_(True)
+    x = gpu.solve(tb, tbb, 4)
+    loss = 0.5 * torch.sum((x - to_dev(xs)) ** 2)
+    loss.backward()
+    gb = tb.grad.cpu().numpy()
+    gbb = tbb.grad.cpu().numpy()
+
+    def L(bd, bb):
+        return 0.5 * np.sum((oracle.band_solve(bd, bb) - xs) ** 2)
+
+    rng = np.random.default_rng(2)
+    h = 1e-6
+    mask = np.ones_like(bands)
+    for d in range(-k, k + 1):
+        if d < 0:
+            mask[d + k, :-d] = 0
+        elif d > 0:
+            mask[d + k, n - d:] = 0
+    for _ in range(8):
+        dirn = rng.standard_normal(bands.shape) * mask
+        fd = (L(bands + h * dirn, b) - L(bands - h * dirn, b)) / (2 * h)
+        assert abs(fd - np.sum(gb * dirn)) <= 1e-6 * max(1.0, abs(fd))
+    db = rng.standard_normal(n)
+    fd = (L(bands, b + h * db) - L(bands, b - h * db)) / (2 * h)
+    assert abs(fd - np.dot(gbb, db)) <= 1e-6 * max(1.0, abs(fd))
+
+
+def test_zero_pivot_is_latched(gpu):
+    n, k, p = 400, 4, 2
+    bands, f = synth.make_problem(n, k, 1, seed=1)
+    row = 300  # a zero row inside partition 1 makes A_1 singular
+    for d in range(-k, k + 1):
+        bands[d + k, row] = 0.0
+    plan = gpu.factor(to_dev(bands), p, k, max_nrhs=1)
+    with pytest.raises(gpu.LRSpikeError) as e:
+        plan.status()
+    assert e.value.code == 1
+    assert e.value.info["partition"] == 1
+
+
+def test_rejects_host_and_bad_arguments(gpu):
+    bands, _ = synth.make_problem(100, 4, 1)
+    with pytest.raises(TypeError):
+        gpu.factor(torch.from_numpy(bands), 2, 4)
+    tb = to_dev(bands)
+    with pytest.raises(gpu.LRSpikeError):
+        gpu.factor(tb, 20, 4)  # n_j = 5 < 2k
+    with pytest.raises(gpu.LRSpikeError):
+        gpu.factor(tb, 2, 5)  # r > k
+
+
+def test_repeat_solves_reuse_factorization(gpu):
+    bands, f = synth.make_problem(3000, 8, 4, seed=4, rule="weak")
+    plan = gpu.factor(to_dev(bands), 6, 4, max_nrhs=4)
+    ref = oracle.lrspike(bands, f, 6, 4)
+    x1 = plan.solve(to_dev(f)).cpu().numpy()
+    x2 = plan.solve(to_dev(f)).cpu().numpy()
+    assert rel(x1, ref) <= 1e-12
+    assert np.array_equal(x1, x2)  # deterministic
