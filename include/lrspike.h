@@ -70,6 +70,8 @@ typedef struct {
   size_t workspace_bytes;
   int32_t max_nrhs;      /* largest nrhs a solve will be called with (default 32);
                             sizes the per-solve vectors inside the workspace */
+  int32_t profile;       /* nonzero: time every kernel launch of this plan with a HIP
+                            event pair on the plan's stream (see lrspike_profile_read) */
 } lrspike_opts;
 
 /* Fill *opts with the defaults above (no workspace, null stream). */
@@ -140,6 +142,20 @@ typedef struct {
 
 /* Synchronizes the plan's stream and returns (and reports) the latched state. */
 int lrspike_status(lrspike_plan plan, lrspike_info *info);
+
+/*
+ * Per-kernel timing (instrumentation, not part of the method).  While enabled,
+ * every kernel the plan enqueues is bracketed by a HIP event pair on the
+ * plan's stream.  lrspike_profile_read synchronizes the stream, sums the
+ * elapsed times per kernel name over all launches recorded since the last
+ * read, and clears the record.
+ *   names     max x 32 chars (NUL-terminated names), may be NULL
+ *   total_ms  max doubles, may be NULL;  launches  max ints, may be NULL
+ *   count     receives the number of distinct kernels (may exceed max)
+ */
+int lrspike_profile(lrspike_plan plan, int32_t enable);
+int lrspike_profile_read(lrspike_plan plan, int32_t max, char *names, double *total_ms,
+                         int32_t *launches, int32_t *count);
 
 /* Frees the host object (the workspace belongs to the caller). */
 int lrspike_destroy(lrspike_plan plan);

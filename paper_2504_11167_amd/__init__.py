@@ -44,6 +44,7 @@ class _Opts(ctypes.Structure):
         ("workspace", ctypes.c_void_p),
         ("workspace_bytes", ctypes.c_size_t),
         ("max_nrhs", ctypes.c_int32),
+        ("profile", ctypes.c_int32),
     ]
 
 
@@ -62,7 +63,7 @@ _lib = None
 SYMBOLS = (
     "lrspike_default_opts", "lrspike_workspace_size", "lrspike_factor", "lrspike_solve",
     "lrspike_solve_adjoint", "lrspike_band_grad", "lrspike_status", "lrspike_destroy",
-    "lrspike_strerror",
+    "lrspike_strerror", "lrspike_profile", "lrspike_profile_read",
 )
 
 
@@ -90,6 +91,9 @@ def load_library():
     lib.lrspike_band_grad.argtypes = [P, P, P, i32, P]
     lib.lrspike_status.argtypes = [P, ctypes.POINTER(_Info)]
     lib.lrspike_destroy.argtypes = [P]
+    lib.lrspike_profile.argtypes = [P, i32]
+    lib.lrspike_profile_read.argtypes = [P, i32, ctypes.c_char_p, ctypes.POINTER(ctypes.c_double),
+                                         ctypes.POINTER(i32), ctypes.POINTER(i32)]
     lib.lrspike_strerror.argtypes = [i32]
     lib.lrspike_strerror.restype = ctypes.c_char_p
     _lib = lib
@@ -119,7 +123,8 @@ def workspace_bytes(n, k, p, r, precision="fp64", max_nrhs=32):
 class Plan:
     """A factored LR-SPIKE plan: the factors live in a caller-owned workspace tensor."""
 
-    def __init__(self, bands, p, r, precision="fp64", max_nrhs=32, max_refine=30, refine_tol=1e-13):
+    def __init__(self, bands, p, r, precision="fp64", max_nrhs=32, max_refine=30, refine_tol=1e-13,
+                 workspace=None, profile=False):
         lib = load_library()
         if not isinstance(bands, torch.Tensor) or bands.device.type != "cuda" or bands.dtype != torch.float64:
             raise TypeError("bands must be a float64 CUDA tensor of shape (2k+1, n)")
@@ -132,7 +137,11 @@ class Plan:
         self.max_nrhs = int(max_nrhs)
         self.bands = bands  # borrowed by the library for the plan's lifetime
         nbytes = workspace_bytes(self.n, self.k, self.p, self.r, precision, self.max_nrhs)
-        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=bands.device)
+        if workspace is None:
+            workspace = torch.empty(nbytes, dtype=torch.uint8, device=bands.device)
+        elif workspace.dtype != torch.uint8 or workspace.numel() < nbytes or workspace.device != bands.device:
+            raise ValueError(f"workspace must be a uint8 tensor of >= {nbytes} bytes on {bands.device}")
+        self.workspace = workspace
         opts = _Opts()
         lib.lrspike_default_opts(ctypes.byref(opts))
         opts.precision = _PRECISIONS[precision]
@@ -142,6 +151,7 @@ class Plan:
         opts.workspace = self.workspace.data_ptr()
         opts.workspace_bytes = nbytes
         opts.max_nrhs = self.max_nrhs
+        opts.profile = 1 if profile else 0
         handle = ctypes.c_void_p()
         rc = lib.lrspike_factor(self.n, self.k, bands.data_ptr(), self.p, self.r, ctypes.byref(opts),
                                 ctypes.byref(handle))
@@ -190,6 +200,27 @@ class Plan:
         rc = self._lib.lrspike_band_grad(self._h, lam.data_ptr(), x.data_ptr(), m, out.data_ptr())
         if rc:
             raise LRSpikeError(rc, "lrspike_band_grad")
+        return out
+
+    def profile(self, enable=True):
+        rc = self._lib.lrspike_profile(self._h, 1 if enable else 0)
+        if rc:
+            raise LRSpikeError(rc, "lrspike_profile")
+
+    def profile_read(self):
+        """{kernel name: (total ms, launches)} since the last read (synchronizes)."""
+        mx = 64
+        names = ctypes.create_string_buffer(32 * mx)
+        ms = (ctypes.c_double * mx)()
+        cnt = (ctypes.c_int32 * mx)()
+        count = ctypes.c_int32(0)
+        rc = self._lib.lrspike_profile_read(self._h, mx, names, ms, cnt, ctypes.byref(count))
+        if rc:
+            raise LRSpikeError(rc, "lrspike_profile_read")
+        out = {}
+        for i in range(min(mx, count.value)):
+            nm = names.raw[32 * i:32 * i + 32].split(b"\0", 1)[0].decode()
+            out[nm] = (ms[i], cnt[i])
         return out
 
     def status(self):

@@ -33,6 +33,9 @@ struct lrspike_plan_s {
   int refine_iters;
   double last_corr;
   int last_error;
+  // opt-in per-launch timing: an event pair around every kernel on the plan's stream
+  int profiling;
+  std::vector<std::pair<const char*, std::pair<hipEvent_t, hipEvent_t>>> prof;
 };
 
 // ------------------------------------------------------------------ dispatch tables
@@ -99,6 +102,30 @@ bool set_lds(const void* fn, size_t bytes) {
     if (hipGetLastError() != hipSuccess) return LRSPIKE_ERR_HIP; \
   } while (0)
 
+// Launch on the plan's stream; with profiling on, bracket it with an event pair.
+template <typename... KArgs, typename... Args>
+int launch(lrspike_plan P, const char* name, void (*kern)(KArgs...), dim3 grid, dim3 block, size_t lds,
+           Args... args) {
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (P->profiling) {
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return LRSPIKE_ERR_HIP;
+    if (hipEventRecord(e0, P->stream) != hipSuccess) return LRSPIKE_ERR_HIP;
+  }
+  hipLaunchKernelGGL(kern, grid, block, lds, P->stream, args...);
+  if (hipGetLastError() != hipSuccess) return LRSPIKE_ERR_HIP;
+  if (P->profiling) {
+    if (hipEventRecord(e1, P->stream) != hipSuccess) return LRSPIKE_ERR_HIP;
+    P->prof.push_back({name, {e0, e1}});
+  }
+  return 0;
+}
+
+#define LRS_LAUNCH(name, kern, grid, block, lds, ...)                     \
+  do {                                                                    \
+    int rc_ = launch(P, name, kern, grid, block, lds, __VA_ARGS__);       \
+    if (rc_) return rc_;                                                  \
+  } while (0)
+
 template <typename T, int K>
 int run_factor(lrspike_plan P) {
   const Layout& L = P->L;
@@ -106,29 +133,23 @@ int run_factor(lrspike_plan P) {
   hipStream_t st = P->stream;
   size_t b1 = lds_p1<T, K>();
   if (!set_lds((const void*)factor_pass1<T, K>, b1)) return LRSPIKE_ERR_NOT_SUPPORTED;
-  hipLaunchKernelGGL((factor_pass1<T, K>), dim3(L.p), dim3(LRS_NT), b1, st, fa);
-  LRS_CHECK_LAUNCH();
+  LRS_LAUNCH("factor_pass1", factor_pass1<T, K>, dim3(L.p), dim3(LRS_NT), b1, fa);
   RedArgs ra{P->ws, L, 0, 0, 0};
   if (L.r < L.K) {
     size_t b2 = lds_p2<T, K>();
     if (!set_lds((const void*)factor_pass2<T, K>, b2)) return LRSPIKE_ERR_NOT_SUPPORTED;
-    hipLaunchKernelGGL((factor_pass2<T, K>), dim3(L.p), dim3(LRS_NT), b2, st, fa);
-    LRS_CHECK_LAUNCH();
+    LRS_LAUNCH("factor_pass2", factor_pass2<T, K>, dim3(L.p), dim3(LRS_NT), b2, fa);
     if (L.r > 0) {
-      hipLaunchKernelGGL((eigen_kernel<K>), dim3(L.p, 2), dim3(LRS_NT), 0, st, ra);
-      LRS_CHECK_LAUNCH();
-    }
+      LRS_LAUNCH("eigen_kernel", eigen_kernel<K>, dim3(L.p, 2), dim3(LRS_NT), 0, ra);
+      }
   } else {
-    hipLaunchKernelGGL((identity_proj_kernel<K>), dim3(L.p), dim3(256), 0, st, ra);
-    LRS_CHECK_LAUNCH();
+    LRS_LAUNCH("identity_proj_kernel", identity_proj_kernel<K>, dim3(L.p), dim3(256), 0, ra);
   }
   if (L.r > 0) {
-    hipLaunchKernelGGL((project_kernel<K>), dim3(L.p), dim3(256), 0, st, ra);
-    LRS_CHECK_LAUNCH();
+    LRS_LAUNCH("project_kernel", project_kernel<K>, dim3(L.p), dim3(256), 0, ra);
   }
   if (L.NI > 0 && L.r > 0) {
-    hipLaunchKernelGGL((zassemble_kernel<K>), dim3(L.NI), dim3(256), 0, st, ra);
-    LRS_CHECK_LAUNCH();
+    LRS_LAUNCH("zassemble_kernel", zassemble_kernel<K>, dim3(L.NI), dim3(256), 0, ra);
     const int R2 = L.R2;
     size_t bodd = (size_t)(R2 * (R2 + 1) + R2 * (2 * R2 + 1)) * 8;
     if (!set_lds((const void*)cr_odd_kernel, bodd)) return LRSPIKE_ERR_NOT_SUPPORTED;
@@ -136,14 +157,12 @@ int run_factor(lrspike_plan P) {
       int s = 1 << l;
       int nodd = (L.NI + s - 1) / (2 * s);  // rows (2q+1)s < NI
       ra.level = l;
-      if (nodd > 0) hipLaunchKernelGGL(cr_odd_kernel, dim3(nodd), dim3(LRS_NT), bodd, st, ra);
+      if (nodd > 0) LRS_LAUNCH("cr_odd_kernel", cr_odd_kernel, dim3(nodd), dim3(LRS_NT), bodd, ra);
       int neven = (L.NI + 2 * s - 1) / (2 * s);
-      hipLaunchKernelGGL(cr_even_kernel, dim3(neven), dim3(LRS_NT), 0, st, ra);
-      LRS_CHECK_LAUNCH();
-    }
+      LRS_LAUNCH("cr_even_kernel", cr_even_kernel, dim3(neven), dim3(LRS_NT), 0, ra);
+      }
     ra.level = L.levels;
-    hipLaunchKernelGGL(cr_odd_kernel, dim3(1), dim3(LRS_NT), bodd, st, ra);
-    LRS_CHECK_LAUNCH();
+    LRS_LAUNCH("cr_odd_kernel", cr_odd_kernel, dim3(1), dim3(LRS_NT), bodd, ra);
   }
   return 0;
 }
@@ -157,8 +176,7 @@ int run_reduced(lrspike_plan P, int m, int transpose) {
   RedArgs ra{P->ws, L, 0, m, transpose};
   size_t bz = (size_t)4 * K * m * 8;
   if (!set_lds((const void*)zrhs_kernel<K>, bz)) return LRSPIKE_ERR_NOT_SUPPORTED;
-  hipLaunchKernelGGL((zrhs_kernel<K>), dim3(L.NI), dim3(256), bz, st, ra, P->bands);
-  LRS_CHECK_LAUNCH();
+  LRS_LAUNCH("zrhs_kernel", zrhs_kernel<K>, dim3(L.NI), dim3(256), bz, ra, P->bands);
   const int R2 = L.R2;
   size_t bf = (size_t)2 * R2 * m * 8, bb = (size_t)R2 * m * 8;
   if (!set_lds((const void*)crs_forward_kernel, bf)) return LRSPIKE_ERR_NOT_SUPPORTED;
@@ -166,18 +184,15 @@ int run_reduced(lrspike_plan P, int m, int transpose) {
     int s = 1 << l;
     ra.level = l;
     int neven = (L.NI + 2 * s - 1) / (2 * s);
-    hipLaunchKernelGGL(crs_forward_kernel, dim3(neven), dim3(LRS_NT), bf, st, ra);
-    LRS_CHECK_LAUNCH();
+    LRS_LAUNCH("crs_forward_kernel", crs_forward_kernel, dim3(neven), dim3(LRS_NT), bf, ra);
   }
   ra.level = L.levels;
-  hipLaunchKernelGGL(crs_backward_kernel, dim3(1), dim3(LRS_NT), bb, st, ra);
-  LRS_CHECK_LAUNCH();
+  LRS_LAUNCH("crs_backward_kernel", crs_backward_kernel, dim3(1), dim3(LRS_NT), bb, ra);
   for (int l = L.levels - 1; l >= 0; --l) {
     int s = 1 << l;
     ra.level = l;
     int nodd = (L.NI + s - 1) / (2 * s);
-    if (nodd > 0) hipLaunchKernelGGL(crs_backward_kernel, dim3(nodd), dim3(LRS_NT), bb, st, ra);
-    LRS_CHECK_LAUNCH();
+    if (nodd > 0) LRS_LAUNCH("crs_backward_kernel", crs_backward_kernel, dim3(nodd), dim3(LRS_NT), bb, ra);
   }
   return 0;
 }
@@ -195,24 +210,20 @@ int run_apply(lrspike_plan P, double* rhs, int m, int transpose) {
     if (!set_lds((const void*)dstage_kernel<T, K>, bs) || !set_lds((const void*)retrieve_kernel<T, K>, bs))
       return LRSPIKE_ERR_NOT_SUPPORTED;
     if (L.p > 1) {
-      hipLaunchKernelGGL((dstage_kernel<T, K>), grid, dim3(LRS_NT), bs, st, sa);
-      LRS_CHECK_LAUNCH();
-      if ((rc = run_reduced<K>(P, m, 0))) return rc;
+      LRS_LAUNCH("dstage_kernel", dstage_kernel<T, K>, grid, dim3(LRS_NT), bs, sa);
+        if ((rc = run_reduced<K>(P, m, 0))) return rc;
     }
-    hipLaunchKernelGGL((retrieve_kernel<T, K>), grid, dim3(LRS_NT), bs, st, sa);
-    LRS_CHECK_LAUNCH();
+    LRS_LAUNCH("retrieve_kernel", retrieve_kernel<T, K>, grid, dim3(LRS_NT), bs, sa);
   } else {
     if (!set_lds((const void*)adj_dstage_kernel<T, K>, bs) || !set_lds((const void*)adj_retrieve_kernel<T, K>, bs))
       return LRSPIKE_ERR_NOT_SUPPORTED;
     if (L.p > 1) {
       SolveArgs sd = sa;
       sd.dst = reinterpret_cast<double*>(P->ws + L.scr);
-      hipLaunchKernelGGL((adj_dstage_kernel<T, K>), grid, dim3(LRS_NT), bs, st, sd);
-      LRS_CHECK_LAUNCH();
-      if ((rc = run_reduced<K>(P, m, 1))) return rc;
+      LRS_LAUNCH("adj_dstage_kernel", adj_dstage_kernel<T, K>, grid, dim3(LRS_NT), bs, sd);
+        if ((rc = run_reduced<K>(P, m, 1))) return rc;
     }
-    hipLaunchKernelGGL((adj_retrieve_kernel<T, K>), grid, dim3(LRS_NT), bs, st, sa);
-    LRS_CHECK_LAUNCH();
+    LRS_LAUNCH("adj_retrieve_kernel", adj_retrieve_kernel<T, K>, grid, dim3(LRS_NT), bs, sa);
   }
   return 0;
 }
@@ -235,14 +246,11 @@ int run_refined(lrspike_plan P, double* rhs, int m, int transpose) {
   double prev = INFINITY;
   for (int it = 0; it < P->max_refine; ++it) {
     int blocks = (int)((nm + 255) / 256);
-    hipLaunchKernelGGL(residual_kernel, dim3(blocks), dim3(256), 0, st, P->bands, L.n, L.k, fcopy, rhs,
-                       scr, m, m, transpose);
-    LRS_CHECK_LAUNCH();
+    LRS_LAUNCH("residual_kernel", residual_kernel, dim3(blocks), dim3(256), 0, P->bands, L.n, L.k, fcopy, rhs, scr, m, m, transpose);
     if ((rc = run_apply<T, K>(P, scr, m, transpose))) return rc;
-    hipLaunchKernelGGL(axpy_kernel, dim3(blocks), dim3(256), 0, st, rhs, scr, nm);
-    hipLaunchKernelGGL(zero_d_kernel, dim3(1), dim3(256), 0, st, norms, 2 * m);
-    hipLaunchKernelGGL(colnorm_kernel, dim3(256, m), dim3(256), 2 * 256 * 8, st, rhs, scr, L.n, m, m, norms);
-    LRS_CHECK_LAUNCH();
+    LRS_LAUNCH("axpy_kernel", axpy_kernel, dim3(blocks), dim3(256), 0, rhs, scr, nm);
+    LRS_LAUNCH("zero_d_kernel", zero_d_kernel, dim3(1), dim3(256), 0, norms, 2 * m);
+    LRS_LAUNCH("colnorm_kernel", colnorm_kernel, dim3(256, m), dim3(256), 2 * 256 * 8, rhs, scr, L.n, m, m, norms);
     if (hipMemcpyAsync(hn.data(), norms, 2 * m * 8, hipMemcpyDeviceToHost, st) != hipSuccess) return LRSPIKE_ERR_HIP;
     if (hipStreamSynchronize(st) != hipSuccess) return LRSPIKE_ERR_HIP;
     double worst = 0.0;
@@ -365,7 +373,8 @@ int lrspike_factor(int64_t n, int32_t k, const double* bands, int32_t p, int32_t
   P->ws = reinterpret_cast<char*>(opts->workspace);
   P->refine_iters = 0;
   P->last_corr = 0.0;
-  hipLaunchKernelGGL(zero_kernel, dim3(1), dim3(64), 0, P->stream, reinterpret_cast<int*>(P->ws + P->L.latch), 16);
+  P->profiling = opts->profile ? 1 : 0;
+  LRS_LAUNCH("zero_kernel", zero_kernel, dim3(1), dim3(64), 0, reinterpret_cast<int*>(P->ws + P->L.latch), 16);
   factor_fn f = P->precision == LRSPIKE_FP64 ? pick_factor<double>(K) : pick_factor<float>(K);
   int rc = f ? f(P) : LRSPIKE_ERR_NOT_SUPPORTED;
   if (rc) {
@@ -404,7 +413,7 @@ int lrspike_band_grad(lrspike_plan P, const double* lam, const double* x, int32_
   if (!is_device_ptr(grad_bands)) return -5;
   const Layout& L = P->L;
   dim3 grid((unsigned)((L.n + 255) / 256), 2 * L.k + 1);
-  hipLaunchKernelGGL(band_grad_kernel, grid, dim3(256), 0, P->stream, L.n, L.k, lam, x, nrhs, nrhs, grad_bands);
+  LRS_LAUNCH("band_grad_kernel", band_grad_kernel, grid, dim3(256), 0, L.n, L.k, lam, x, nrhs, nrhs, grad_bands);
   return hipGetLastError() == hipSuccess ? 0 : LRSPIKE_ERR_HIP;
 }
 
@@ -427,7 +436,57 @@ int lrspike_status(lrspike_plan P, lrspike_info* info) {
   return latch[0];
 }
 
+static void prof_clear(lrspike_plan P) {
+  for (auto& e : P->prof) {
+    (void)hipEventDestroy(e.second.first);
+    (void)hipEventDestroy(e.second.second);
+  }
+  P->prof.clear();
+}
+
+int lrspike_profile(lrspike_plan P, int32_t enable) {
+  if (!P) return -1;
+  P->profiling = enable ? 1 : 0;
+  return 0;
+}
+
+int lrspike_profile_read(lrspike_plan P, int32_t max, char* names, double* total_ms, int32_t* launches,
+                         int32_t* count) {
+  if (!P) return -1;
+  if (max < 0) return -2;
+  if (!count) return -6;
+  if (hipStreamSynchronize(P->stream) != hipSuccess) return LRSPIKE_ERR_HIP;
+  std::vector<const char*> keys;
+  std::vector<double> ms;
+  std::vector<int> cnt;
+  for (auto& e : P->prof) {
+    float t = 0.f;
+    if (hipEventElapsedTime(&t, e.second.first, e.second.second) != hipSuccess) return LRSPIKE_ERR_HIP;
+    size_t i = 0;
+    while (i < keys.size() && strcmp(keys[i], e.first) != 0) ++i;
+    if (i == keys.size()) {
+      keys.push_back(e.first);
+      ms.push_back(0.0);
+      cnt.push_back(0);
+    }
+    ms[i] += t;
+    cnt[i] += 1;
+  }
+  prof_clear(P);
+  *count = (int32_t)keys.size();
+  for (int i = 0; i < (int)keys.size() && i < max; ++i) {
+    if (names) {
+      strncpy(names + 32 * i, keys[i], 31);
+      names[32 * i + 31] = 0;
+    }
+    if (total_ms) total_ms[i] = ms[i];
+    if (launches) launches[i] = cnt[i];
+  }
+  return 0;
+}
+
 int lrspike_destroy(lrspike_plan P) {
+  if (P) prof_clear(P);
   delete P;
   return 0;
 }
