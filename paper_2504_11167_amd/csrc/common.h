@@ -67,14 +67,105 @@ __device__ inline void latch_error(int* latch, int code, int part, int64_t row) 
 // C must not alias A or B.  No barrier inside; the caller synchronizes.
 // ------------------------------------------------------------------------
 template <typename T, bool TA>
-__device__ inline void gemm(int M, int N, int KD, T alpha, const T* A, int lda,
-                            const T* B, int ldb, T beta, T* C, int ldc) {
+__device__ inline void gemm_valu(int M, int N, int KD, T alpha, const T* A, int lda,
+                                 const T* B, int ldb, T beta, T* C, int ldc) {
   for (int o = threadIdx.x; o < M * N; o += blockDim.x) {
     int i = o / N, j = o - (o / N) * N;
     T acc = 0;
     for (int l = 0; l < KD; ++l) acc += (TA ? A[l * lda + i] : A[i * lda + l]) * B[l * ldb + j];
     C[i * ldc + j] = (beta == T(0) ? T(0) : beta * C[i * ldc + j]) + alpha * acc;
   }
+}
+
+// Matrix-core tile product for 16 x 16 output tiles (M, N multiples of 16,
+// KD a multiple of 4).  Lane layouts of the 16x16x4 instructions (checked on
+// gfx950): A fragment lane l = A(l%16, l/16), B fragment = B(l/16, l%16);
+// the f64 accumulator holds D(l/16 + 4v, l%16), the f32 one D(4(l/16) + v, l%16).
+// Output columns >= nvalid are computed but not stored (B may hold garbage there).
+typedef double lrs_d4 __attribute__((ext_vector_type(4)));
+typedef float lrs_f4 __attribute__((ext_vector_type(4)));
+
+template <typename T, bool TA>
+__device__ inline void gemm_mfma(int M, int N, int KD, T alpha, const T* A, int lda, const T* B,
+                                 int ldb, T beta, T* C, int ldc, int nvalid) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  const int tm = M >> 4, tn = N >> 4;
+  const int li = lane & 15, lk = lane >> 4;
+  for (int t = wave; t < tm * tn; t += nw) {
+    const int i0 = (t / tn) << 4, j0 = (t % tn) << 4;
+    if constexpr (sizeof(T) == 8) {
+      lrs_d4 acc;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        int i = i0 + lk + 4 * v, j = j0 + li;
+        acc[v] = (beta == T(0) || j >= nvalid) ? 0.0 : (double)(beta * C[i * ldc + j]);
+      }
+      for (int k0 = 0; k0 < KD; k0 += 4) {
+        int kk = k0 + lk;
+        double av = alpha * (TA ? A[kk * lda + i0 + li] : A[(i0 + li) * lda + kk]);
+        double bv = B[kk * ldb + j0 + li];
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
+      }
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        int i = i0 + lk + 4 * v, j = j0 + li;
+        if (j < nvalid) C[i * ldc + j] = (T)acc[v];
+      }
+    } else {
+      lrs_f4 acc;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        int i = i0 + 4 * lk + v, j = j0 + li;
+        acc[v] = (beta == T(0) || j >= nvalid) ? 0.0f : (float)(beta * C[i * ldc + j]);
+      }
+      for (int k0 = 0; k0 < KD; k0 += 4) {
+        int kk = k0 + lk;
+        float av = alpha * (TA ? A[kk * lda + i0 + li] : A[(i0 + li) * lda + kk]);
+        float bv = B[kk * ldb + j0 + li];
+        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, acc, 0, 0, 0);
+      }
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        int i = i0 + 4 * lk + v, j = j0 + li;
+        if (j < nvalid) C[i * ldc + j] = (T)acc[v];
+      }
+    }
+  }
+}
+
+// One 16x16x4 matrix-core step on a register accumulator tile, and the row
+// of accumulator element v held by a lane (column = lane % 16).
+template <typename T>
+struct AccVec;
+template <>
+struct AccVec<double> {
+  typedef lrs_d4 type;
+};
+template <>
+struct AccVec<float> {
+  typedef lrs_f4 type;
+};
+__device__ __forceinline__ lrs_d4 mfma_step(double a, double b, lrs_d4 c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ lrs_f4 mfma_step(float a, float b, lrs_f4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+template <typename T>
+__device__ __forceinline__ int acc_row(int lane, int v) {
+  return sizeof(T) == 8 ? (lane >> 4) + 4 * v : 4 * (lane >> 4) + v;
+}
+
+// C[M x N] = beta C + alpha op(A) B on LDS tiles.  Uses the matrix cores when
+// M and KD allow it; N is padded up to a multiple of 16 (the caller's tiles
+// must have room for the padded columns, whose values are ignored).
+template <typename T, bool TA>
+__device__ inline void gemm(int M, int N, int KD, T alpha, const T* A, int lda,
+                            const T* B, int ldb, T beta, T* C, int ldc) {
+  if ((M & 15) == 0 && (KD & 3) == 0 && N >= 8)
+    gemm_mfma<T, TA>(M, (N + 15) & ~15, KD, alpha, A, lda, B, ldb, beta, C, ldc, N);
+  else
+    gemm_valu<T, TA>(M, N, KD, alpha, A, lda, B, ldb, beta, C, ldc);
 }
 
 // ------------------------------------------------------------------------
@@ -143,6 +234,191 @@ __device__ inline bool panel_lu(T* P, int ld, int nr, int ncols, T* X, int ldx, 
     __syncthreads();
   }
   return *s_flag != 0;
+}
+
+// Broadcast lane `l`'s value of v to the whole wave (uniform result).
+__device__ __forceinline__ double bcast(double v, int l) {
+  int lo = __builtin_amdgcn_readlane(__double2loint(v), l);
+  int hi = __builtin_amdgcn_readlane(__double2hiint(v), l);
+  return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ float bcast(float v, int l) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
+}
+
+// One column step of the register-resident panel LU; C is a compile-time
+// column index so that every register of a[] is addressed statically.
+template <typename T, int K, int C>
+struct PanelCol {
+  static __device__ __forceinline__ void run(T (&a)[K], int lane, bool act, T* P, int ld, int ncols,
+                                             T* X, int ldx, int ncx, int* ipiv, int* latch, int part,
+                                             int64_t row0, bool& any_swap) {
+    if constexpr (C < K) {
+      T d = bcast(a[C], C);
+      const bool beats = act && lane > C && fabs(a[C]) > fabs(d);
+      int piv = C;
+      if (__any(beats)) {
+        // full argmax (first maximum) over rows C .. nr-1
+        T bv = (act && lane >= C) ? fabs(a[C]) : T(-1);
+        int bi = lane;
+        for (int off = 32; off >= 1; off >>= 1) {
+          T ov = __shfl_xor(bv, off);
+          int oi = __shfl_xor(bi, off);
+          if (ov > bv || (ov == bv && oi < bi)) {
+            bv = ov;
+            bi = oi;
+          }
+        }
+        piv = __builtin_amdgcn_readfirstlane(bi);
+      }
+      if (lane == 0) ipiv[C] = piv;
+      if (piv != C) {
+        any_swap = true;
+#pragma unroll
+        for (int jj = 0; jj < K; ++jj) {
+          T vc = bcast(a[jj], C), vp = bcast(a[jj], piv);
+          if (lane == C) a[jj] = vp;
+          if (lane == piv) a[jj] = vc;
+        }
+        for (int col = K + lane; col < ncols; col += 64) {
+          T t = P[C * ld + col];
+          P[C * ld + col] = P[piv * ld + col];
+          P[piv * ld + col] = t;
+        }
+        for (int col = lane; col < ncx; col += 64) {
+          T t = X[C * ldx + col];
+          X[C * ldx + col] = X[piv * ldx + col];
+          X[piv * ldx + col] = t;
+        }
+        d = bcast(a[C], C);
+      }
+      if (d == T(0) && lane == 0) latch_error(latch, 1, part, row0 + C);
+      const bool below = act && lane > C;
+      const T inv = T(1) / d;
+      const T l = a[C] * inv;
+      if (below) a[C] = l;
+#pragma unroll
+      for (int jj = C + 1; jj < K; ++jj) {
+        const T pj = bcast(a[jj], C);
+        if (below) a[jj] -= l * pj;
+      }
+      PanelCol<T, K, C + 1>::run(a, lane, act, P, ld, ncols, X, ldx, ncx, ipiv, latch, part, row0, any_swap);
+    }
+  }
+};
+
+// Register-resident partial-pivoting LU of an nr x K panel (nr <= 64) by ONE
+// wave (call from all lanes of a single wave; no workgroup barrier inside).
+// Lane q holds panel row q.  The pivot of column c is the first row of
+// largest magnitude among rows c .. nr-1; the common case (no row beats the
+// diagonal) is detected with one vote and costs no reduction.  Interchanges
+// move the panel registers and, in LDS, columns K..ncols-1 of P and the first
+// ncx columns of X.  On exit the panel (unit L strictly below the diagonal,
+// U on and above) is written back to P.  Multipliers are formed as a * (1/d).
+// Branch-free elimination step without interchanges (compile-time column C);
+// records the largest multiplier magnitude of the lane in mx.
+template <typename T, int K, int C>
+struct PanelColNoPiv {
+  static __device__ __forceinline__ void run(T (&a)[K], int lane, bool act, T& mx, T& dmin) {
+    if constexpr (C < K) {
+      const T d = bcast(a[C], C);
+      const T inv = T(1) / d;
+      const bool below = act && lane > C;
+      const T l = below ? a[C] * inv : T(0);
+      mx = fmax(mx, fabs(l));
+      dmin = fmin(dmin, fabs(d));
+      if (below) a[C] = l;
+#pragma unroll
+      for (int jj = C + 1; jj < K; ++jj) a[jj] -= l * bcast(a[jj], C);
+      PanelColNoPiv<T, K, C + 1>::run(a, lane, act, mx, dmin);
+    }
+  }
+};
+
+template <typename T, int K>
+__device__ inline bool panel_lu_wave(T* P, int ld, int nr, int ncols, T* X, int ldx, int ncx,
+                                     int* ipiv, int* latch, int part, int64_t row0) {
+  const int lane = threadIdx.x & 63;
+  const bool act = lane < nr;
+  T a[K];
+#pragma unroll
+  for (int c = 0; c < K; ++c) a[c] = act ? P[lane * ld + c] : T(0);
+  // Optimistic pass: elimination without interchanges.  Partial pivoting
+  // interchanges at column c exactly when some row below has |a_rc| > |a_cc|,
+  // i.e. when a multiplier exceeds 1 in magnitude; if none does, this IS the
+  // partial-pivoting factorization (same operations, same order).
+  T mx = T(0), dmin = T(1);
+  PanelColNoPiv<T, K, 0>::run(a, lane, act, mx, dmin);
+  const bool ok = !__any(!(mx <= T(1))) && __all(dmin > T(0));
+  if (ok) {
+    if (lane < K) ipiv[lane] = lane;
+#pragma unroll
+    for (int c = 0; c < K; ++c)
+      if (act) P[lane * ld + c] = a[c];
+    return false;
+  }
+#pragma unroll
+  for (int c = 0; c < K; ++c) a[c] = act ? P[lane * ld + c] : T(0);
+  bool any_swap = false;
+  PanelCol<T, K, 0>::run(a, lane, act, P, ld, ncols, X, ldx, ncx, ipiv, latch, part, row0, any_swap);
+#pragma unroll
+  for (int c = 0; c < K; ++c)
+    if (act) P[lane * ld + c] = a[c];
+  return any_swap;
+}
+
+// Register-resident triangular inverses by single waves: lane j computes
+// column j, column-oriented (each step's updates are independent):
+//   lower:  x = e_j;  for l: x_i -= L[i][l] x_l  (i > l)            -> (unit L)^{-1} e_j
+//   upper:  x = e_j;  for l desc: x_l /= U[l][l]; x_i -= U[i][l] x_l (i < l) -> U^{-1} e_j
+template <typename T, int K, int Lc>
+struct InvLowerCol {
+  static __device__ __forceinline__ void run(const T* L, int ldl, T (&x)[K]) {
+    if constexpr (Lc < K) {
+#pragma unroll
+      for (int i = Lc + 1; i < K; ++i) x[i] -= L[i * ldl + Lc] * x[Lc];
+      InvLowerCol<T, K, Lc + 1>::run(L, ldl, x);
+    }
+  }
+};
+template <typename T, int K, int Lc>
+struct InvUpperCol {  // Lc counts down
+  static __device__ __forceinline__ void run(const T* U, int ldu, T (&x)[K], const T* dinv) {
+    if constexpr (Lc >= 0) {
+      x[Lc] *= dinv[Lc];
+#pragma unroll
+      for (int i = 0; i < Lc; ++i) x[i] -= U[i * ldu + Lc] * x[Lc];
+      InvUpperCol<T, K, Lc - 1>::run(U, ldu, x, dinv);
+    }
+  }
+};
+
+template <typename T, int K>
+__device__ inline void tri_inv_lower_wave(const T* L, int ldl, T* Li, int ldli) {
+  const int j = threadIdx.x & 63;
+  T x[K];
+#pragma unroll
+  for (int i = 0; i < K; ++i) x[i] = (i == j) ? T(1) : T(0);
+  InvLowerCol<T, K, 0>::run(L, ldl, x);
+  if (j < K)
+#pragma unroll
+    for (int i = 0; i < K; ++i) Li[i * ldli + j] = x[i];
+}
+
+// dinv: K reciprocals of the diagonal of U (LDS or registers visible to the wave)
+template <typename T, int K>
+__device__ inline void tri_inv_upper_wave(const T* U, int ldu, T* Ui, int ldui, T* dinv) {
+  const int j = threadIdx.x & 63;
+  if (j < K) dinv[j] = T(1) / U[j * ldu + j];
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  T x[K];
+#pragma unroll
+  for (int i = 0; i < K; ++i) x[i] = (i == j) ? T(1) : T(0);
+  InvUpperCol<T, K, K - 1>::run(U, ldu, x, dinv);
+  if (j < K)
+#pragma unroll
+    for (int i = 0; i < K; ++i) Ui[i * ldui + j] = x[i];
 }
 
 // Inverse of the unit lower triangle of L (K x K, pitch ldl) into Li (strictly

@@ -62,6 +62,7 @@ __global__ __launch_bounds__(LRS_NT) void factor_pass1(FactorArgs a) {
   T* lds = reinterpret_cast<T*>(lds_raw);
   __shared__ int s_ipiv[K];
   __shared__ int s_flag;
+  __shared__ T s_dinv[K];
   T* Wn = lds + LD::oWn;
   T* T1 = lds + LD::oT1;
   T* Li = lds + LD::oLi;
@@ -88,30 +89,85 @@ __global__ __launch_bounds__(LRS_NT) void factor_pass1(FactorArgs a) {
   int* flg = wsT<int>(a.ws, L.flag) + (size_t)j * L.nbmax;
   double* tips = wsT<double>(a.ws, L.tips) + (size_t)j * 4 * K * K;  // Vt, Vb, Wt, Wb
 
-  // accumulated top tips [W_t | V_t] = sum_b G_b^T Y_b, thread-owned entries
-  constexpr int NACC = (2 * K * K + LRS_NT - 1) / LRS_NT;
+  // accumulated top tips [W_t | V_t] = sum_b G_b^T Y_b: matrix-core tiles held
+  // in registers by their owning wave (K >= 16), else thread-owned entries
+  constexpr bool MF = (K >= 16);
+  constexpr int NACC = MF ? 1 : (2 * K * K + LRS_NT - 1) / LRS_NT;
   double tacc[NACC];
 #pragma unroll
   for (int t = 0; t < NACC; ++t) tacc[t] = 0.0;
+  constexpr int TT = MF ? (K / 16) * (2 * K / 16) : 1;  // accumulator tiles
+  constexpr int TPW = (TT + 3) / 4;                     // tiles per wave
+  using AccV = typename AccVec<T>::type;
+  AccV macc[TPW];
+#pragma unroll
+  for (int t = 0; t < TPW; ++t) macc[t] = AccV{0, 0, 0, 0};
+  const int lane = tid & 63, wave = tid >> 6;
 
-  // load row block R (padded rows R K .. R K + K - 1) into window rows
-  // [row0, row0 + K), columns of block columns R-1 .. R+1 relative to colblk0
-  auto load_rowblock = [&](int R, int wrow0, int colblk0) {
-    for (int o = tid; o < K * 3 * K; o += LRS_NT) {
-      int i = o / (3 * K), c = o % (3 * K);
-      int q = R * K + i, col = colblk0 * K + c;
-      Wn[(wrow0 + i) * LDW + c] = (T)part_at(a.bands, L.n, k, g, q, col);
+  // Load row block R (padded rows R K .. R K + K - 1) into window rows
+  // [wrow0, wrow0 + K), window column = padded column - colbase, reading the
+  // band diagonal by diagonal so that consecutive lanes read consecutive rows.
+  // Band values of row block R, diagonal-major so that consecutive lanes read
+  // consecutive rows; issued one step ahead into registers (pre[]) and written
+  // into the window after the shift.
+  constexpr int NPRE = ((2 * K + 1) * K + LRS_NT - 1) / LRS_NT;
+  T pre[NPRE];
+  auto prefetch_rowblock = [&](int R) {
+#pragma unroll
+    for (int t = 0; t < NPRE; ++t) {
+      const int o = tid + t * LRS_NT;
+      T v = T(0);
+      if (o < (2 * k + 1) * K) {
+        const int d = o / K - k, i = o % K;
+        const int q = R * K + i, lr = q - g.pad;
+        if (lr < 0) {
+          v = (d == 0) ? T(1) : T(0);
+        } else if (lr < g.nj) {
+          const int lc = lr + d;
+          if (lc >= 0 && lc < g.nj) v = (T)a.bands[(int64_t)(d + k) * L.n + g.s + lr];
+        }
+      }
+      pre[t] = v;
+    }
+  };
+  // write the prefetched row block R into window rows K..2K-1 (zeroed first)
+  auto store_prefetched = [&](int R, int colbase) {
+#pragma unroll
+    for (int t = 0; t < NPRE; ++t) {
+      const int o = tid + t * LRS_NT;
+      if (o < (2 * k + 1) * K) {
+        const int d = o / K - k, i = o % K;
+        const int wc = R * K + i + d - colbase;
+        if (wc >= 0 && wc < 3 * K) Wn[(K + i) * LDW + wc] = pre[t];
+      }
+    }
+  };
+  auto load_rowblock = [&](int R, int wrow0, int colbase, int wcols) {
+    for (int o = tid; o < K * wcols; o += LRS_NT) Wn[(wrow0 + o / wcols) * LDW + o % wcols] = T(0);
+    __syncthreads();
+    for (int o = tid; o < (2 * k + 1) * K; o += LRS_NT) {
+      const int d = o / K - k, i = o % K;
+      const int q = R * K + i, lr = q - g.pad;
+      const int wc = q + d - colbase;
+      if (lr < 0) {
+        if (d == 0) Wn[(wrow0 + i) * LDW + wc] = T(1);
+      } else if (lr < g.nj) {
+        const int lc = lr + d;
+        if (lc >= 0 && lc < g.nj && wc >= 0 && wc < wcols)
+          Wn[(wrow0 + i) * LDW + wc] = (T)a.bands[(int64_t)(d + k) * L.n + g.s + lr];
+      }
     }
   };
   // spike right-hand sides of row block R into Wv rows [wrow0, wrow0 + K):
   // columns 0..K-1 = [C_j; 0] (first K real rows), K..2K-1 = [0; B_j] (last K real rows)
   auto load_spike_rhs = [&](int R, int wrow0) {
+    const int lr0 = R * K - g.pad;
+    const bool any = (lr0 < K) || (lr0 + K > g.nj - K);
     for (int o = tid; o < K * 2 * K; o += LRS_NT) {
       int i = o / (2 * K), c = o % (2 * K);
-      int q = R * K + i;
-      int lr = q - g.pad;  // partition-local row
+      int lr = lr0 + i;
       double v = 0.0;
-      if (lr >= 0 && lr < g.nj) {
+      if (any && lr >= 0 && lr < g.nj) {
         if (c < K) {
           if (lr < K) v = band_at(a.bands, L.n, k, g.s + lr, g.s - K + c);
         } else {
@@ -123,22 +179,20 @@ __global__ __launch_bounds__(LRS_NT) void factor_pass1(FactorArgs a) {
     }
   };
 
-  // initial window: row block 0 in rows 0..K-1 (its block columns 0,1 at window
-  // columns 0..2K-1; column block "-1" is outside the partition), row block 1 below
+  // initial window: row block 0 in rows 0..K-1 (block columns 0, 1), row block 1 below
   for (int o = tid; o < 2 * K * LDW; o += LRS_NT) Wn[o] = T(0);
-  for (int o = tid; o < 2 * K * LD2; o += LRS_NT) Wv[o] = T(0);
   for (int o = tid; o < K * LDK; o += LRS_NT) {
     Ga[o] = T(0);
     Gb2[o] = T(0);
   }
+  load_rowblock(0, 0, 0, 2 * K);
   __syncthreads();
-  for (int o = tid; o < K * 2 * K; o += LRS_NT) {
-    int i = o / (2 * K), c = o % (2 * K);
-    Wn[i * LDW + c] = (T)part_at(a.bands, L.n, k, g, i, c);
-  }
-  if (nb > 1) load_rowblock(1, K, 0);
+  if (nb > 1) load_rowblock(1, K, 0, 3 * K);
   load_spike_rhs(0, 0);
-  if (nb > 1) load_spike_rhs(1, K);
+  if (nb > 1)
+    load_spike_rhs(1, K);
+  else
+    for (int o = tid; o < K * LD2; o += LRS_NT) Wv[K * LD2 + o] = T(0);
   __syncthreads();
 
   T* Gcur = Ga;   // pending accumulator for block b
@@ -150,21 +204,35 @@ __global__ __launch_bounds__(LRS_NT) void factor_pass1(FactorArgs a) {
     const bool last = (b == nb - 1);
     const int nr = last ? K : 2 * K;
     const int64_t row0 = (int64_t)b * K - g.pad;
-    bool swapped = panel_lu<T, K>(Wn, LDW, nr, last ? K : 3 * K, Wv, LD2, 2 * K, s_ipiv, latch, j,
-                                  row0, &s_flag);
+    // spike columns in play: W always; V only once its right-hand side (the
+    // last block) is inside the window
+    const int ncs = (b >= nb - 2) ? 2 * K : K;
+    if (b + 2 < nb) prefetch_rowblock(b + 2);
+    if (tid < 64) {
+      bool sw = panel_lu_wave<T, K>(Wn, LDW, nr, last ? K : 3 * K, Wv, LD2, 2 * K, s_ipiv, latch, j, row0);
+      if (tid == 0) s_flag = sw ? 1 : 0;
+    }
+    __syncthreads();
+    const bool swapped = s_flag != 0;
     nswapped += swapped ? 1 : 0;
     const bool prev_swapped = prev_sw;
     prev_sw = swapped;
-    tri_inverses<T, K>(Wn, LDW, Wn, LDW, Li, LDK, Ui, LDK);
+    if (tid < 64)
+      tri_inv_lower_wave<T, K>(Wn, LDW, Li, LDK);
+    else if (tid < 128)
+      tri_inv_upper_wave<T, K>(Wn, LDW, Ui, LDK, s_dinv);
     __syncthreads();
 
     T* rec = fac + (size_t)b * L.rec;
     if (!last) {
-      // [U12 | U13] = L11^{-1} R1
-      gemm<T, false>(K, 2 * K, K, T(1), Li, LDK, Wn + K, LDW, T(0), T1, LD2);
+      // [U12 | U13] = L11^{-1} R1  (U13 = 0 unless this block interchanged rows)
+      const int nu = swapped ? 2 * K : K;
+      gemm<T, false>(K, nu, K, T(1), Li, LDK, Wn + K, LDW, T(0), T1, LD2);
+      if (!swapped)
+        for (int o = tid; o < K * K; o += LRS_NT) T1[(o / K) * LD2 + K + o % K] = T(0);
       __syncthreads();
       // trailing rows: R2 -= L21 [U12 | U13]
-      gemm<T, false>(K, 2 * K, K, T(-1), Wn + K * LDW, LDW, T1, LD2, T(1), Wn + K * LDW + K, LDW);
+      gemm<T, false>(K, nu, K, T(-1), Wn + K * LDW, LDW, T1, LD2, T(1), Wn + K * LDW + K, LDW);
     }
     // G step: g_b = U11^{-T} (e_b + pending)
     for (int i = tid; i < K; i += LRS_NT) {
@@ -208,18 +276,35 @@ __global__ __launch_bounds__(LRS_NT) void factor_pass1(FactorArgs a) {
     if (tid == 0) flg[b] = (swapped ? 1 : 0) | ((!last && (swapped || prev_swapped)) ? 2 : 0);
     __syncthreads();
     // spike forward step: Y_b = L11^{-1} Wv[0:K] (into T1); Wv[K:2K] -= L21 Y_b
-    gemm<T, false>(K, 2 * K, K, T(1), Li, LDK, Wv, LD2, T(0), T1, LD2);
+    gemm<T, false>(K, ncs, K, T(1), Li, LDK, Wv, LD2, T(0), T1, LD2);
+    if (ncs == K)
+      for (int o = tid; o < K * K; o += LRS_NT) T1[(o / K) * LD2 + K + o % K] = T(0);
     __syncthreads();
-    if (!last) gemm<T, false>(K, 2 * K, K, T(-1), Wn + K * LDW, LDW, T1, LD2, T(1), Wv + K * LD2, LD2);
-    // top tips accumulate G_b^T Y_b  (thread-owned entries, double)
+    if (!last) gemm<T, false>(K, ncs, K, T(-1), Wn + K * LDW, LDW, T1, LD2, T(1), Wv + K * LD2, LD2);
+    // top tips accumulate G_b^T Y_b
+    if constexpr (MF) {
 #pragma unroll
-    for (int t = 0; t < NACC; ++t) {
-      int o = tid + t * LRS_NT;
-      if (o < 2 * K * K) {
-        int i = o / (2 * K), c = o % (2 * K);
-        double s = 0.0;
-        for (int l = 0; l < K; ++l) s += (double)G[l * LDK + i] * (double)T1[l * LD2 + c];
-        tacc[t] += s;
+      for (int t = 0; t < TPW; ++t) {
+        const int tile = wave + 4 * t;
+        const int i0 = (tile / (2 * K / 16)) * 16, j0 = (tile % (2 * K / 16)) * 16;
+        if (tile < TT && j0 < ncs)
+#pragma unroll
+          for (int k0 = 0; k0 < K; k0 += 4)
+            macc[t] = mfma_step(G[(k0 + (lane >> 4)) * LDK + i0 + (lane & 15)],
+                                T1[(k0 + (lane >> 4)) * LD2 + j0 + (lane & 15)], macc[t]);
+      }
+    } else {
+#pragma unroll
+      for (int t = 0; t < NACC; ++t) {
+        int o = tid + t * LRS_NT;
+        if (o < 2 * K * K) {
+          int i = o / (2 * K), c = o % (2 * K);
+          if (c < ncs) {
+            double sacc = 0.0;
+            for (int l = 0; l < K; ++l) sacc += (double)G[l * LDK + i] * (double)T1[l * LD2 + c];
+            tacc[t] += sacc;
+          }
+        }
       }
     }
     if (ym)
@@ -228,12 +313,12 @@ __global__ __launch_bounds__(LRS_NT) void factor_pass1(FactorArgs a) {
       // bottom tips: [W_b | V_b] = U11^{-1} Y_last (the last block has nothing below)
       for (int o = tid; o < 2 * K * K; o += LRS_NT) {
         int i = o / (2 * K), c = o % (2 * K);
-        double s = 0.0;
-        for (int l = i; l < K; ++l) s += (double)Ui[i * LDK + l] * (double)T1[l * LD2 + c];
+        double sacc = 0.0;
+        for (int l = i; l < K; ++l) sacc += (double)Ui[i * LDK + l] * (double)T1[l * LD2 + c];
         if (c < K)
-          tips[3 * K * K + i * K + c] = (j > 0) ? s : 0.0;  // W_b
+          tips[3 * K * K + i * K + c] = (j > 0) ? sacc : 0.0;  // W_b
         else
-          tips[1 * K * K + i * K + (c - K)] = (j < L.p - 1) ? s : 0.0;  // V_b
+          tips[1 * K * K + i * K + (c - K)] = (j < L.p - 1) ? sacc : 0.0;  // V_b
       }
     }
     __syncthreads();
@@ -249,8 +334,10 @@ __global__ __launch_bounds__(LRS_NT) void factor_pass1(FactorArgs a) {
       }
       __syncthreads();
       if (b + 2 < nb) {
-        load_rowblock(b + 2, K, b + 1);
+        for (int o = tid; o < K * LDW; o += LRS_NT) Wn[K * LDW + o] = T(0);
         load_spike_rhs(b + 2, K);
+        __syncthreads();
+        store_prefetched(b + 2, (b + 1) * K);
       } else {
         for (int o = tid; o < K * LDW; o += LRS_NT) Wn[K * LDW + o] = T(0);
         for (int o = tid; o < K * LD2; o += LRS_NT) Wv[K * LD2 + o] = T(0);
@@ -262,15 +349,26 @@ __global__ __launch_bounds__(LRS_NT) void factor_pass1(FactorArgs a) {
     }
   }
   // top tips
+  auto put_top = [&](int i, int c, double v) {
+    if (c < K)
+      tips[2 * K * K + i * K + c] = (j > 0) ? v : 0.0;  // W_t
+    else
+      tips[0 * K * K + i * K + (c - K)] = (j < L.p - 1) ? v : 0.0;  // V_t
+  };
+  if constexpr (MF) {
 #pragma unroll
-  for (int t = 0; t < NACC; ++t) {
-    int o = tid + t * LRS_NT;
-    if (o < 2 * K * K) {
-      int i = o / (2 * K), c = o % (2 * K);
-      if (c < K)
-        tips[2 * K * K + i * K + c] = (j > 0) ? tacc[t] : 0.0;  // W_t
-      else
-        tips[0 * K * K + i * K + (c - K)] = (j < L.p - 1) ? tacc[t] : 0.0;  // V_t
+    for (int t = 0; t < TPW; ++t) {
+      const int tile = wave + 4 * t;
+      const int i0 = (tile / (2 * K / 16)) * 16, j0 = (tile % (2 * K / 16)) * 16;
+      if (tile < TT)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) put_top(i0 + acc_row<T>(lane, v), j0 + (lane & 15), (double)macc[t][v]);
+    }
+  } else {
+#pragma unroll
+    for (int t = 0; t < NACC; ++t) {
+      int o = tid + t * LRS_NT;
+      if (o < 2 * K * K) put_top(o / (2 * K), o % (2 * K), tacc[t]);
     }
   }
   if (tid == 0 && nswapped) atomicAdd(latch + 8, nswapped);
