@@ -19,6 +19,7 @@ struct RedArgs;
 #include "factor.hip"
 #include "reduced.hip"
 #include "solve.hip"
+#include "solve_wave.hip"
 
 using namespace lrs;
 
@@ -206,12 +207,31 @@ int run_apply(lrspike_plan P, double* rhs, int m, int transpose) {
   dim3 grid(L.p, (m + MC - 1) / MC);
   size_t bs = lds_sw<T, K>();
   int rc;
-  if (!transpose) {
+  if (!transpose && K >= 16) {
+    // matrix-core sweeps: one wave per partition and column chunk
+    if constexpr (K >= 16) {
+      const bool one = m <= 16;
+      dim3 gw(L.p, one ? 1 : (m + 31) / 32);
+      const size_t bw = one ? (size_t)WaveSweep<T, K, 1>::total * sizeof(T) + 2 * K * sizeof(int)
+                            : (size_t)WaveSweep<T, K, 2>::total * sizeof(T) + 2 * K * sizeof(int);
+      if (L.p > 1) {
+        if (one)
+          LRS_LAUNCH("dstage_kernel", dstage_wave_kernel<T, K, 1>, gw, dim3(64), bw, sa);
+        else
+          LRS_LAUNCH("dstage_kernel", dstage_wave_kernel<T, K, 2>, gw, dim3(64), bw, sa);
+        if ((rc = run_reduced<K>(P, m, 0))) return rc;
+      }
+      if (one)
+        LRS_LAUNCH("retrieve_kernel", retrieve_wave_kernel<T, K, 1>, gw, dim3(64), bw, sa);
+      else
+        LRS_LAUNCH("retrieve_kernel", retrieve_wave_kernel<T, K, 2>, gw, dim3(64), bw, sa);
+    }
+  } else if (!transpose) {
     if (!set_lds((const void*)dstage_kernel<T, K>, bs) || !set_lds((const void*)retrieve_kernel<T, K>, bs))
       return LRSPIKE_ERR_NOT_SUPPORTED;
     if (L.p > 1) {
       LRS_LAUNCH("dstage_kernel", dstage_kernel<T, K>, grid, dim3(LRS_NT), bs, sa);
-        if ((rc = run_reduced<K>(P, m, 0))) return rc;
+      if ((rc = run_reduced<K>(P, m, 0))) return rc;
     }
     LRS_LAUNCH("retrieve_kernel", retrieve_kernel<T, K>, grid, dim3(LRS_NT), bs, sa);
   } else {

@@ -50,6 +50,45 @@ __device__ inline double part_at(const double* __restrict__ bands, int64_t n, in
 }
 
 // ------------------------------------------------------------------------
+// Storage order of the K x K factor blocks.  For K >= 16 a block is stored in
+// the A-operand fragment order of the 16x16x4 matrix-core instructions, so
+// that one fragment (16 rows x 4 k-columns) is one contiguous 64-element run
+// and a wave loads it with one fully coalesced access.  Within each 16-wide
+// k chunk the k index is permuted so that the f64 (f32) accumulator layout of
+// a product can be fed back as the B operand without moving data between
+// lanes: f64 accumulator element v of lane group g holds row g + 4v, f32 holds
+// row 4g + v.  For K < 16 blocks are row-major.
+template <typename T, int K>
+__host__ __device__ constexpr int fidx(int i, int c) {
+  if constexpr (K >= 16) {
+    const int t = i >> 4, r = i & 15, cc = c >> 4, w = c & 15;
+    const int s = (sizeof(T) == 8) ? (w >> 2) : (w & 3);
+    const int gq = (sizeof(T) == 8) ? (w & 3) : (w >> 2);
+    return ((t * (K / 4) + cc * 4 + s) << 6) + r + 16 * gq;
+  } else {
+    return i * K + c;
+  }
+}
+// (row, column) of the element stored at position o of a K x K block
+template <typename T, int K>
+__host__ __device__ inline void fidx_inv(int o, int& i, int& c) {
+  if constexpr (K >= 16) {
+    const int lane = o & 63, frag = o >> 6;
+    const int t = frag / (K / 4), step = frag % (K / 4), gq = lane >> 4;
+    i = 16 * t + (lane & 15);
+    c = 16 * (step >> 2) + ((sizeof(T) == 8) ? 4 * (step & 3) + gq : 4 * gq + (step & 3));
+  } else {
+    i = o / K;
+    c = o % K;
+  }
+}
+// k index (within the K columns) of lane group gq at k-step `step`
+template <typename T>
+__host__ __device__ constexpr int frag_k(int step, int gq) {
+  return 16 * (step >> 2) + ((sizeof(T) == 8) ? 4 * (step & 3) + gq : 4 * gq + (step & 3));
+}
+
+// ------------------------------------------------------------------------
 // Device error latch: the first error wins (code, partition, row).
 // Layout: int32 [0] = code, [1] = partition, int64 at [2..3] = row.
 // ------------------------------------------------------------------------

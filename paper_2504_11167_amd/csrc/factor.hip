@@ -252,19 +252,21 @@ __global__ __launch_bounds__(LRS_NT) void factor_pass1(FactorArgs a) {
     }
     // store factors of this block
     for (int o = tid; o < K * K; o += LRS_NT) {
-      int i = o / K, c = o % K;
+      int i, c;
+      fidx_inv<T, K>(o, i, c);  // element (i, c) lives at storage position o
       T lp = (i > c) ? Li[i * LDK + c] : (last ? T(0) : Wn[(K + i) * LDW + c]);
       T up = (i <= c) ? Ui[i * LDK + c] : (last ? T(0) : T1[i * LD2 + c]);
-      rec[o] = lp;
-      rec[K * K + o] = up;
-      gm[(size_t)b * K * K + o] = G[o / K * LDK + o % K];
+      const int fo = o;
+      rec[fo] = lp;
+      rec[K * K + fo] = up;
+      gm[(size_t)b * K * K + o] = G[c * LDK + i];  // G^T in operand order
       if (!last && (swapped || prev_swapped)) {
         T* sx = swx + (size_t)b * 3 * K * K;
         if (swapped) {
-          sx[o] = Wn[(K + i) * LDW + c];
-          sx[2 * K * K + o] = T1[i * LD2 + K + c];
+          sx[fo] = Wn[(K + i) * LDW + c];
+          sx[2 * K * K + fo] = T1[i * LD2 + K + c];
         }
-        sx[K * K + o] = T1[i * LD2 + c];
+        sx[K * K + fo] = T1[i * LD2 + c];
       }
     }
     for (int i = tid; i < K; i += LRS_NT) {

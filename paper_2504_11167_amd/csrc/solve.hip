@@ -122,7 +122,7 @@ __device__ void forward_pass(const SolveArgs& a, const Geom& g, int j, int c0, i
     const T* rec = fac + (size_t)b * L.rec;
     load_lfac<T, K>(rec, swx + (size_t)b * 3 * K * K, fl, last, Li, L21);
     if (DSTAGE)
-      for (int o = tid; o < K * K; o += LRS_NT) Gt[o / K * LDK + o % K] = gm[(size_t)b * K * K + o];
+      for (int o = tid; o < K * K; o += LRS_NT) Gt[o / K * LDK + o % K] = gm[(size_t)b * K * K + fidx<T, K>(o % K, o / K)];
     if (sw) permute_rows<T, K>(Zw, LDM, last ? K : 2 * K, mc, ipv + (size_t)b * K, s_perm, Tmp);
     __syncthreads();
     gemm<T, false>(K, mc, K, T(1), Li, LDK, Zw, LDM, T(0), Zt, LDM);
@@ -153,7 +153,7 @@ __device__ void forward_pass(const SolveArgs& a, const Geom& g, int j, int c0, i
       for (int o = tid; o < K * mc; o += LRS_NT) {
         int i = o / mc, c = o % mc;
         double s = 0.0;
-        for (int l = i; l < K; ++l) s += (double)up[i * K + l] * (double)Zt[l * LDM + c];
+        for (int l = i; l < K; ++l) s += (double)up[fidx<T, K>(i, l)] * (double)Zt[l * LDM + c];
         yb[i * L.mmax + c0 + c] = s;
       }
     }

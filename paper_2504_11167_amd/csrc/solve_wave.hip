@@ -1,0 +1,431 @@
+// Matrix-core sweeps for K >= 16: one wave per (partition, chunk of up to
+// 16 * MCT right-hand-side columns), no workgroup barriers.
+//
+// The right-hand-side strip of a block (K rows x 16 columns per column tile)
+// lives in 16x16 accumulator tiles.  With the k permutation of fidx, the
+// accumulator element v of tile t is exactly the B operand of k-step 4t + v,
+// so a product's result feeds the next product without leaving registers.
+// The A operands (L11^{-1}, L21, G^T, U11^{-1}, U12, U13) are loaded as whole
+// fragments from the fragment-ordered factor records, one block ahead.
+//
+// D-stage  (eq. D-stage of the solve summary): forward L^{-1} P^T over f,
+//          y_t = G^T z accumulated, y_b = U11^{-1} z_last.
+// Recovery (eqs. recovery1/2): forward over f minus the interface
+//          corrections with z stored in x, then x_b = U11^{-1}(z_b - U12 x_{b+1} - U13 x_{b+2}).
+#include "sweep.h"
+
+namespace lrs {
+
+template <typename T, int K, int MCT>
+struct WaveSweep {
+  static constexpr int RT = K / 16;  // 16-row tiles per block
+  static constexpr int KS = K / 4;   // k-steps per block product
+  static constexpr int NC = 16 * MCT;
+  using V = typename AccVec<T>::type;
+  // LDS: row-major staging for interchanges (2K x NC), interface corrections
+  // (2 x K x NC), neighbour tip (K x NC), permutation (2K ints)
+  static constexpr int oStage = 0;
+  static constexpr int oCt = oStage + 2 * K * NC;
+  static constexpr int oCb = oCt + K * NC;
+  static constexpr int oXn = oCb + K * NC;
+  static constexpr int total = oXn + K * NC;
+};
+
+// Masked A-operand element for lane `lane` of fragment (t, step).
+//   kind 0: L11^{-1} from LP (strict lower + unit diagonal)
+//   kind 1: L21 from LP (upper incl. diagonal)
+//   kind 2: U11^{-1} from UP (upper incl. diagonal)
+//   kind 3: U12 from UP (strict lower) + its diagonal, passed per fragment in dg
+template <typename T, int kind>
+__device__ __forceinline__ T fmask(T v, int t, int step, int lane, T dg) {
+  const int i = 16 * t + (lane & 15);
+  const int kk = frag_k<T>(step, lane >> 4);
+  if constexpr (kind == 0) return i > kk ? v : (i == kk ? T(1) : T(0));
+  if constexpr (kind == 1) return i <= kk ? v : T(0);
+  if constexpr (kind == 2) return i <= kk ? v : T(0);
+  if constexpr (kind == 3) return i > kk ? v : dg;
+  return v;
+}
+
+// strip (K rows x NC columns) <-> global rows of the partition
+template <typename T, int K, int MCT>
+__device__ __forceinline__ void load_strip(typename WaveSweep<T, K, MCT>::V (&st)[K / 16][MCT],
+                                           const double* src, int64_t ld, const Geom& g, int R,
+                                           int c0, int m, const T* Ct, const T* Cb) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int t = 0; t < K / 16; ++t)
+#pragma unroll
+    for (int ct = 0; ct < MCT; ++ct)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int row = 16 * t + acc_row<T>(lane, v), col = 16 * ct + (lane & 15);
+        const int lr = R * K + row - g.pad;
+        T x = T(0);
+        if (lr >= 0 && lr < g.nj && c0 + col < m) {
+          x = (T)src[(g.s + lr) * ld + c0 + col];
+          if (Ct && lr < K) x -= Ct[lr * (16 * MCT) + col];
+          if (Cb && lr >= g.nj - K) x -= Cb[(lr - (g.nj - K)) * (16 * MCT) + col];
+        }
+        st[t][ct][v] = x;
+      }
+}
+
+template <typename T, int K, int MCT>
+__device__ __forceinline__ void store_strip(const typename WaveSweep<T, K, MCT>::V (&st)[K / 16][MCT],
+                                            double* dst, int64_t ld, const Geom& g, int R, int c0,
+                                            int m) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int t = 0; t < K / 16; ++t)
+#pragma unroll
+    for (int ct = 0; ct < MCT; ++ct)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int row = 16 * t + acc_row<T>(lane, v), col = 16 * ct + (lane & 15);
+        const int lr = R * K + row - g.pad;
+        if (lr >= 0 && c0 + col < m) dst[(g.s + lr) * ld + c0 + col] = (double)st[t][ct][v];
+      }
+}
+
+// Interchanges of a block applied to the window strips (rows of w0 then w1),
+// through LDS (rare: only blocks whose factorization interchanged rows).
+template <typename T, int K, int MCT>
+__device__ void permute_strips(typename WaveSweep<T, K, MCT>::V (&w0)[K / 16][MCT],
+                               typename WaveSweep<T, K, MCT>::V (&w1)[K / 16][MCT], bool two,
+                               const int* ipiv_g, T* stage, int* perm) {
+  constexpr int NC = 16 * MCT;
+  const int lane = threadIdx.x & 63;
+  const int nr = two ? 2 * K : K;
+  if (lane == 0) {
+    for (int q = 0; q < nr; ++q) perm[q] = q;
+    for (int c = 0; c < K; ++c) {
+      int pv = ipiv_g[c];
+      int t = perm[c];
+      perm[c] = perm[pv];
+      perm[pv] = t;
+    }
+  }
+#pragma unroll
+  for (int h = 0; h < 2; ++h)
+#pragma unroll
+    for (int t = 0; t < K / 16; ++t)
+#pragma unroll
+      for (int ct = 0; ct < MCT; ++ct)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int row = h * K + 16 * t + acc_row<T>(lane, v), col = 16 * ct + (lane & 15);
+          stage[row * NC + col] = h ? w1[t][ct][v] : w0[t][ct][v];
+        }
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+#pragma unroll
+  for (int h = 0; h < 2; ++h)
+#pragma unroll
+    for (int t = 0; t < K / 16; ++t)
+#pragma unroll
+      for (int ct = 0; ct < MCT; ++ct)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int row = h * K + 16 * t + acc_row<T>(lane, v), col = 16 * ct + (lane & 15);
+          if (row < nr) {
+            T x = stage[perm[row] * NC + col];
+            if (h)
+              w1[t][ct][v] = x;
+            else
+              w0[t][ct][v] = x;
+          }
+        }
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+
+// out[t][ct] (+)= sign * A(kind) * in  for one K x K block; A fragments from frag[].
+template <typename T, int K, int MCT, int kind>
+__device__ __forceinline__ void blk_mul(const T (&frag)[(K / 16) * (K / 4)], const T* dg, T sign,
+                                        const typename WaveSweep<T, K, MCT>::V (&in)[K / 16][MCT],
+                                        typename WaveSweep<T, K, MCT>::V (&out)[K / 16][MCT]) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int t = 0; t < K / 16; ++t)
+#pragma unroll
+    for (int step = 0; step < K / 4; ++step) {
+      const T av = sign * fmask<T, kind>(frag[t * (K / 4) + step], t, step, lane,
+                                         kind == 3 ? dg[t * (K / 4) + step] : T(0));
+#pragma unroll
+      for (int ct = 0; ct < MCT; ++ct) out[t][ct] = mfma_step(av, in[step >> 2][ct][step & 3], out[t][ct]);
+    }
+}
+
+template <typename T, int K>
+__device__ __forceinline__ void load_frags(T (&dst)[(K / 16) * (K / 4)], const T* src) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int f = 0; f < (K / 16) * (K / 4); ++f) dst[f] = src[(f << 6) + lane];
+}
+
+// Per-fragment diagonal entries of U12 (UD vector of the record): lane value
+// is UD[i] where the fragment element is on the diagonal, else 0.
+template <typename T, int K>
+__device__ __forceinline__ void load_diag(T (&dst)[(K / 16) * (K / 4)], const T* ud) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int f = 0; f < (K / 16) * (K / 4); ++f) {
+    const int t = f / (K / 4), step = f % (K / 4);
+    const int i = 16 * t + (lane & 15), kk = frag_k<T>(step, lane >> 4);
+    dst[f] = (i == kk) ? ud[i] : T(0);
+  }
+}
+
+template <typename T, int K, int MCT>
+__device__ __forceinline__ void zero_strip(typename WaveSweep<T, K, MCT>::V (&st)[K / 16][MCT]) {
+#pragma unroll
+  for (int t = 0; t < K / 16; ++t)
+#pragma unroll
+    for (int ct = 0; ct < MCT; ++ct) st[t][ct] = typename WaveSweep<T, K, MCT>::V{0, 0, 0, 0};
+}
+
+// Forward pass L^{-1} P^T over the partition (rhs minus optional corrections).
+// DSTAGE: accumulate y_t = G^T z and write y_b, y_t to the tip buffer;
+// otherwise z is written to a.dst.
+template <typename T, int K, int MCT, bool DSTAGE>
+__device__ void fwd_wave(const SolveArgs& a, const Geom& g, int j, int c0, T* lds, const T* Ct,
+                         const T* Cb) {
+  using W = WaveSweep<T, K, MCT>;
+  using V = typename W::V;
+  constexpr int NF = W::RT * W::KS;
+  const Layout& L = a.L;
+  const int lane = threadIdx.x & 63;
+  const T* fac = wsp<T>(a.ws, L.fac) + (size_t)j * L.nbmax * L.rec;
+  const T* swx = wsp<T>(a.ws, L.swx) + (size_t)j * L.nbmax * 3 * K * K;
+  const T* gm = wsp<T>(a.ws, L.gmat) + (size_t)j * L.nbmax * K * K;
+  const int* ipv = wsp<int>(a.ws, L.ipiv) + (size_t)j * L.nbmax * K;
+  const int* flg = wsp<int>(a.ws, L.flag) + (size_t)j * L.nbmax;
+  int* perm = reinterpret_cast<int*>(lds + W::total);
+  V w0[W::RT][MCT], w1[W::RT][MCT], z[W::RT][MCT], acc[W::RT][MCT], nx[W::RT][MCT];
+  zero_strip<T, K, MCT>(acc);
+  load_strip<T, K, MCT>(w0, a.src, a.ld, g, 0, c0, a.m, Ct, Cb);
+  if (g.nb > 1)
+    load_strip<T, K, MCT>(w1, a.src, a.ld, g, 1, c0, a.m, Ct, Cb);
+  else
+    zero_strip<T, K, MCT>(w1);
+  T lp[NF], gt[NF], lpn[NF], gtn[NF];
+  load_frags<T, K>(lp, fac);
+  if (DSTAGE) load_frags<T, K>(gt, gm);
+  int fl = flg[0];
+  for (int b = 0; b < g.nb; ++b) {
+    const bool last = (b == g.nb - 1);
+    int fln = 0;
+    // prefetch: next block's fragments and flag, rows of block b + 2
+    if (!last) {
+      load_frags<T, K>(lpn, fac + (size_t)(b + 1) * L.rec);
+      if (DSTAGE) load_frags<T, K>(gtn, gm + (size_t)(b + 1) * K * K);
+      fln = flg[b + 1];
+    }
+    if (b + 2 < g.nb)
+      load_strip<T, K, MCT>(nx, a.src, a.ld, g, b + 2, c0, a.m, Ct, Cb);
+    else
+      zero_strip<T, K, MCT>(nx);
+    if (fl & 1) permute_strips<T, K, MCT>(w0, w1, !last, ipv + (size_t)b * K, lds + W::oStage, perm);
+    zero_strip<T, K, MCT>(z);
+    blk_mul<T, K, MCT, 0>(lp, nullptr, T(1), w0, z);  // z_b = L11^{-1} r_b
+    if (!last) {
+      if (fl & 1) {
+        T l21[NF];
+        load_frags<T, K>(l21, swx + (size_t)b * 3 * K * K);
+        blk_mul<T, K, MCT, 9>(l21, nullptr, T(-1), z, w1);
+      } else {
+        blk_mul<T, K, MCT, 1>(lp, nullptr, T(-1), z, w1);  // r_{b+1} -= L21 z_b
+      }
+    }
+    if (DSTAGE) {
+      blk_mul<T, K, MCT, 9>(gt, nullptr, T(1), z, acc);  // y_t += G^T z_b
+      if (last) {
+        // y_b = U11^{-1} z_last
+        T up[NF];
+        load_frags<T, K>(up, fac + (size_t)b * L.rec + K * K);
+        V yb[W::RT][MCT];
+        zero_strip<T, K, MCT>(yb);
+        blk_mul<T, K, MCT, 2>(up, nullptr, T(1), z, yb);
+        double* yt = wsp<double>(a.ws, L.ytip) + (size_t)j * 2 * K * L.mmax;
+#pragma unroll
+        for (int t = 0; t < W::RT; ++t)
+#pragma unroll
+          for (int ct = 0; ct < MCT; ++ct)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+              const int row = 16 * t + acc_row<T>(lane, v), col = 16 * ct + (lane & 15);
+              if (c0 + col < a.m) {
+                yt[(size_t)row * L.mmax + c0 + col] = (double)acc[t][ct][v];
+                yt[(size_t)(K + row) * L.mmax + c0 + col] = (double)yb[t][ct][v];
+              }
+            }
+      }
+    } else {
+      store_strip<T, K, MCT>(z, a.dst, a.ld, g, b, c0, a.m);
+    }
+#pragma unroll
+    for (int t = 0; t < W::RT; ++t)
+#pragma unroll
+      for (int ct = 0; ct < MCT; ++ct) {
+        w0[t][ct] = w1[t][ct];
+        w1[t][ct] = nx[t][ct];
+      }
+    if (!last) {
+#pragma unroll
+      for (int f = 0; f < NF; ++f) {
+        lp[f] = lpn[f];
+        if (DSTAGE) gt[f] = gtn[f];
+      }
+      fl = fln;
+    }
+  }
+}
+
+// Backward pass x_b = U11^{-1}(z_b - U12 x_{b+1} - U13 x_{b+2}) over a.dst.
+template <typename T, int K, int MCT>
+__device__ void bwd_wave(const SolveArgs& a, const Geom& g, int j, int c0) {
+  using W = WaveSweep<T, K, MCT>;
+  using V = typename W::V;
+  constexpr int NF = W::RT * W::KS;
+  const Layout& L = a.L;
+  const T* fac = wsp<T>(a.ws, L.fac) + (size_t)j * L.nbmax * L.rec;
+  const T* swx = wsp<T>(a.ws, L.swx) + (size_t)j * L.nbmax * 3 * K * K;
+  const int* flg = wsp<int>(a.ws, L.flag) + (size_t)j * L.nbmax;
+  V x1[W::RT][MCT], x2[W::RT][MCT], zb[W::RT][MCT], zn[W::RT][MCT], xb[W::RT][MCT];
+  zero_strip<T, K, MCT>(x1);
+  zero_strip<T, K, MCT>(x2);
+  T up[NF], upn[NF], ud[NF], udn[NF];
+  int b = g.nb - 1;
+  load_frags<T, K>(up, fac + (size_t)b * L.rec + K * K);
+  load_diag<T, K>(ud, fac + (size_t)b * L.rec + 2 * K * K);
+  int fl = flg[b];
+  load_strip<T, K, MCT>(zb, a.dst, a.ld, g, b, c0, a.m, nullptr, nullptr);
+  for (; b >= 0; --b) {
+    const bool last = (b == g.nb - 1);
+    int fln = 0;
+    if (b > 0) {
+      load_frags<T, K>(upn, fac + (size_t)(b - 1) * L.rec + K * K);
+      load_diag<T, K>(udn, fac + (size_t)(b - 1) * L.rec + 2 * K * K);
+      fln = flg[b - 1];
+      load_strip<T, K, MCT>(zn, a.dst, a.ld, g, b - 1, c0, a.m, nullptr, nullptr);
+    }
+    if (!last) {
+      if (fl & 2) {
+        T u12[NF];
+        load_frags<T, K>(u12, swx + (size_t)b * 3 * K * K + K * K);
+        blk_mul<T, K, MCT, 9>(u12, nullptr, T(-1), x1, zb);
+      } else {
+        blk_mul<T, K, MCT, 3>(up, ud, T(-1), x1, zb);  // z_b -= U12 x_{b+1}
+      }
+      if (fl & 1) {
+        T u13[NF];
+        load_frags<T, K>(u13, swx + (size_t)b * 3 * K * K + 2 * K * K);
+        blk_mul<T, K, MCT, 9>(u13, nullptr, T(-1), x2, zb);
+      }
+    }
+    zero_strip<T, K, MCT>(xb);
+    blk_mul<T, K, MCT, 2>(up, nullptr, T(1), zb, xb);  // x_b = U11^{-1} (...)
+    store_strip<T, K, MCT>(xb, a.dst, a.ld, g, b, c0, a.m);
+#pragma unroll
+    for (int t = 0; t < W::RT; ++t)
+#pragma unroll
+      for (int ct = 0; ct < MCT; ++ct) {
+        x2[t][ct] = x1[t][ct];
+        x1[t][ct] = xb[t][ct];
+        zb[t][ct] = zn[t][ct];
+      }
+    if (b > 0) {
+#pragma unroll
+      for (int f = 0; f < NF; ++f) {
+        up[f] = upn[f];
+        ud[f] = udn[f];
+      }
+      fl = fln;
+    }
+  }
+}
+
+template <typename T, int K, int MCT>
+__global__ __launch_bounds__(64) void dstage_wave_kernel(SolveArgs a) {
+  extern __shared__ __align__(16) unsigned char lds_raw[];
+  T* lds = reinterpret_cast<T*>(lds_raw);
+  const int j = blockIdx.x, c0 = blockIdx.y * 16 * MCT;
+  const Geom g = part_geom(a.L.n, a.L.p, j, K);
+  fwd_wave<T, K, MCT, true>(a, g, j, c0, lds, nullptr, nullptr);
+}
+
+template <typename T, int K, int MCT>
+__global__ __launch_bounds__(64) void retrieve_wave_kernel(SolveArgs a) {
+  using W = WaveSweep<T, K, MCT>;
+  constexpr int NC = W::NC;
+  extern __shared__ __align__(16) unsigned char lds_raw[];
+  T* lds = reinterpret_cast<T*>(lds_raw);
+  const Layout& L = a.L;
+  const int j = blockIdx.x, c0 = blockIdx.y * NC;
+  const int mc = min(NC, a.m - c0);
+  const Geom g = part_geom(L.n, L.p, j, K);
+  const int lane = threadIdx.x & 63, k = L.k;
+  T* Ct = lds + W::oCt;
+  T* Cb = lds + W::oCb;
+  T* Xn = lds + W::oXn;
+  auto sync = [] {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+  };
+  // Xn uses the generic interface-tip routine with its pitch MC + 1; keep a
+  // local copy of the logic at pitch NC instead.
+  auto tip = [&](int i, bool top) {
+    const int r = L.r;
+    const double* yt = wsp<double>(a.ws, L.ytip) + ((size_t)i * 2 + (top ? 0 : 1)) * K * L.mmax;
+    const double* pt = wsp<double>(a.ws, L.ptip) + (size_t)i * 4 * K * r;
+    const double* P = pt + (top ? 0 : 1) * K * r;
+    const double* Q = pt + (top ? 2 : 3) * K * r;
+    const double* zg = wsp<double>(a.ws, L.zg);
+    for (int o = lane; o < K * mc; o += 64) {
+      int row = o / mc, c = o % mc;
+      double v = yt[row * L.mmax + c0 + c];
+      if (r > 0) {
+        if (i <= L.p - 2) {
+          const double* av = zg + (size_t)i * L.R2 * L.mmax;
+          for (int q = 0; q < r; ++q) v -= P[row * r + q] * av[q * L.mmax + c0 + c];
+        }
+        if (i >= 1) {
+          const double* cv = zg + ((size_t)(i - 1) * L.R2 + r) * L.mmax;
+          for (int q = 0; q < r; ++q) v -= Q[row * r + q] * cv[q * L.mmax + c0 + c];
+        }
+      }
+      Xn[row * NC + c] = (T)v;
+    }
+  };
+  if (j > 0) {
+    tip(j - 1, false);  // x_{j-1,b}
+    sync();
+    for (int o = lane; o < K * mc; o += 64) {
+      int i = o / mc, c = o % mc;
+      double s = 0.0;
+      for (int l = 0; l < K; ++l) s += band_at(a.bands, L.n, k, g.s + i, g.s - K + l) * (double)Xn[l * NC + c];
+      Ct[i * NC + c] = (T)s;
+    }
+    sync();
+  }
+  if (j < L.p - 1) {
+    tip(j + 1, true);  // x_{j+1,t}
+    sync();
+    const int64_t s1 = g.s + g.nj;
+    for (int o = lane; o < K * mc; o += 64) {
+      int i = o / mc, c = o % mc;
+      double s = 0.0;
+      for (int l = 0; l < K; ++l) s += band_at(a.bands, L.n, k, s1 - K + i, s1 + l) * (double)Xn[l * NC + c];
+      Cb[i * NC + c] = (T)s;
+    }
+    sync();
+  }
+  fwd_wave<T, K, MCT, false>(a, g, j, c0, lds, j > 0 ? Ct : nullptr, j < L.p - 1 ? Cb : nullptr);
+  bwd_wave<T, K, MCT>(a, g, j, c0);
+}
+
+}  // namespace lrs

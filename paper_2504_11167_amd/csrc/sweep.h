@@ -31,13 +31,14 @@ __device__ inline void load_lfac(const T* rec, const T* sx, int fl, bool last, T
   constexpr int LDK = K + 1;
   for (int o = threadIdx.x; o < K * K; o += blockDim.x) {
     int i = o / K, c = o % K;
-    T lp = rec[o];
+    const int fo = fidx<T, K>(i, c);
+    T lp = rec[fo];
     Li[i * LDK + c] = (i > c) ? lp : (i == c ? T(1) : T(0));
     T l21;
     if (last)
       l21 = T(0);
     else if (sw)
-      l21 = sx[o];
+      l21 = sx[fo];
     else
       l21 = (i <= c) ? lp : T(0);
     L21[i * LDK + c] = l21;
@@ -51,15 +52,16 @@ __device__ inline void load_ufac(const T* rec, const T* sx, int fl, bool last, T
   constexpr int LDK = K + 1;
   for (int o = threadIdx.x; o < K * K; o += blockDim.x) {
     int i = o / K, c = o % K;
-    T up = rec[K * K + o];
+    const int fo = fidx<T, K>(i, c);
+    T up = rec[K * K + fo];
     Ui[i * LDK + c] = (i <= c) ? up : T(0);
     T u12 = T(0), u13 = T(0);
     if (!last) {
       if (fl & 2)
-        u12 = sx[K * K + o];
+        u12 = sx[K * K + fo];
       else
         u12 = (i > c) ? up : (i == c ? rec[2 * K * K + i] : T(0));
-      if (fl & 1) u13 = sx[2 * K * K + o];
+      if (fl & 1) u13 = sx[2 * K * K + fo];
     }
     U12[i * LDK + c] = u12;
     U13[i * LDK + c] = u13;
