@@ -137,9 +137,13 @@ int run_factor(lrspike_plan P) {
   LRS_LAUNCH("factor_pass1", factor_pass1<T, K>, dim3(L.p), dim3(LRS_NT), b1, fa);
   RedArgs ra{P->ws, L, 0, 0, 0};
   if (L.r < L.K) {
-    size_t b2 = lds_p2<T, K>();
-    if (!set_lds((const void*)factor_pass2<T, K>, b2)) return LRSPIKE_ERR_NOT_SUPPORTED;
-    LRS_LAUNCH("factor_pass2", factor_pass2<T, K>, dim3(L.p), dim3(LRS_NT), b2, fa);
+    if constexpr (K >= 16) {
+      LRS_LAUNCH("factor_pass2", pass2_wave_kernel<T, K>, dim3(L.p, 2), dim3(64), 0, fa);
+    } else {
+      size_t b2 = lds_p2<T, K>();
+      if (!set_lds((const void*)factor_pass2<T, K>, b2)) return LRSPIKE_ERR_NOT_SUPPORTED;
+      LRS_LAUNCH("factor_pass2", factor_pass2<T, K>, dim3(L.p), dim3(LRS_NT), b2, fa);
+    }
     if (L.r > 0) {
       LRS_LAUNCH("eigen_kernel", eigen_kernel<K>, dim3(L.p, 2), dim3(LRS_NT), 0, ra);
       }

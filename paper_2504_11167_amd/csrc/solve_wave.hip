@@ -166,17 +166,37 @@ __device__ __forceinline__ void load_frags(T (&dst)[(K / 16) * (K / 4)], const T
   for (int f = 0; f < (K / 16) * (K / 4); ++f) dst[f] = src[(f << 6) + lane];
 }
 
-// Per-fragment diagonal entries of U12 (UD vector of the record): lane value
-// is UD[i] where the fragment element is on the diagonal, else 0.
+// Diagonal of U12 (UD vector of the record) at the strip rows a lane holds.
 template <typename T, int K>
-__device__ __forceinline__ void load_diag(T (&dst)[(K / 16) * (K / 4)], const T* ud) {
+__device__ __forceinline__ void load_udrows(T (&dst)[K / 16][4], const T* ud) {
   const int lane = threadIdx.x & 63;
 #pragma unroll
-  for (int f = 0; f < (K / 16) * (K / 4); ++f) {
-    const int t = f / (K / 4), step = f % (K / 4);
-    const int i = 16 * t + (lane & 15), kk = frag_k<T>(step, lane >> 4);
-    dst[f] = (i == kk) ? ud[i] : T(0);
-  }
+  for (int t = 0; t < K / 16; ++t)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) dst[t][v] = ud[16 * t + acc_row<T>(lane, v)];
+}
+
+// out -= U12 x with U12 = strict lower part of UP + diag(UD) (no side slot)
+template <typename T, int K, int MCT>
+__device__ __forceinline__ void u12_mul(const T (&up)[(K / 16) * (K / 4)], const T (&udr)[K / 16][4],
+                                        const typename WaveSweep<T, K, MCT>::V (&x)[K / 16][MCT],
+                                        typename WaveSweep<T, K, MCT>::V (&out)[K / 16][MCT]) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int t = 0; t < K / 16; ++t)
+#pragma unroll
+    for (int step = 0; step < K / 4; ++step) {
+      const int i = 16 * t + (lane & 15), kk = frag_k<T>(step, lane >> 4);
+      const T av = (i > kk) ? -up[t * (K / 4) + step] : T(0);
+#pragma unroll
+      for (int ct = 0; ct < MCT; ++ct) out[t][ct] = mfma_step(av, x[step >> 2][ct][step & 3], out[t][ct]);
+    }
+#pragma unroll
+  for (int t = 0; t < K / 16; ++t)
+#pragma unroll
+    for (int ct = 0; ct < MCT; ++ct)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) out[t][ct][v] -= udr[t][v] * x[t][ct][v];
 }
 
 template <typename T, int K, int MCT>
@@ -297,10 +317,10 @@ __device__ void bwd_wave(const SolveArgs& a, const Geom& g, int j, int c0) {
   V x1[W::RT][MCT], x2[W::RT][MCT], zb[W::RT][MCT], zn[W::RT][MCT], xb[W::RT][MCT];
   zero_strip<T, K, MCT>(x1);
   zero_strip<T, K, MCT>(x2);
-  T up[NF], upn[NF], ud[NF], udn[NF];
+  T up[NF], upn[NF], ud[W::RT][4], udn[W::RT][4];
   int b = g.nb - 1;
   load_frags<T, K>(up, fac + (size_t)b * L.rec + K * K);
-  load_diag<T, K>(ud, fac + (size_t)b * L.rec + 2 * K * K);
+  load_udrows<T, K>(ud, fac + (size_t)b * L.rec + 2 * K * K);
   int fl = flg[b];
   load_strip<T, K, MCT>(zb, a.dst, a.ld, g, b, c0, a.m, nullptr, nullptr);
   for (; b >= 0; --b) {
@@ -308,7 +328,7 @@ __device__ void bwd_wave(const SolveArgs& a, const Geom& g, int j, int c0) {
     int fln = 0;
     if (b > 0) {
       load_frags<T, K>(upn, fac + (size_t)(b - 1) * L.rec + K * K);
-      load_diag<T, K>(udn, fac + (size_t)(b - 1) * L.rec + 2 * K * K);
+      load_udrows<T, K>(udn, fac + (size_t)(b - 1) * L.rec + 2 * K * K);
       fln = flg[b - 1];
       load_strip<T, K, MCT>(zn, a.dst, a.ld, g, b - 1, c0, a.m, nullptr, nullptr);
     }
@@ -318,7 +338,7 @@ __device__ void bwd_wave(const SolveArgs& a, const Geom& g, int j, int c0) {
         load_frags<T, K>(u12, swx + (size_t)b * 3 * K * K + K * K);
         blk_mul<T, K, MCT, 9>(u12, nullptr, T(-1), x1, zb);
       } else {
-        blk_mul<T, K, MCT, 3>(up, ud, T(-1), x1, zb);  // z_b -= U12 x_{b+1}
+        u12_mul<T, K, MCT>(up, ud, x1, zb);  // z_b -= U12 x_{b+1}
       }
       if (fl & 1) {
         T u13[NF];
@@ -339,10 +359,11 @@ __device__ void bwd_wave(const SolveArgs& a, const Geom& g, int j, int c0) {
       }
     if (b > 0) {
 #pragma unroll
-      for (int f = 0; f < NF; ++f) {
-        up[f] = upn[f];
-        ud[f] = udn[f];
-      }
+      for (int f = 0; f < NF; ++f) up[f] = upn[f];
+#pragma unroll
+      for (int t = 0; t < W::RT; ++t)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) ud[t][v] = udn[t][v];
       fl = fln;
     }
   }
@@ -426,6 +447,112 @@ __global__ __launch_bounds__(64) void retrieve_wave_kernel(SolveArgs a) {
   }
   fwd_wave<T, K, MCT, false>(a, g, j, c0, lds, j > 0 ? Ct : nullptr, j < L.p - 1 ? Cb : nullptr);
   bwd_wave<T, K, MCT>(a, g, j, c0);
+}
+
+
+// Factorization pass 2 for K >= 16 (r < k): back substitution of one spike
+// (blockIdx.y = 0: W, 1: V) over the stored forward intermediate Y,
+//   z_b = U11^{-1} (Y_b - U12 z_{b+1} - U13 z_{b+2}),
+// accumulating the Gram matrix z^T z on the matrix cores: the accumulator
+// tiles of z are at once the B operand and (tile-transposed) the A operand.
+template <typename T, int K>
+__global__ __launch_bounds__(64) void pass2_wave_kernel(FactorArgs a) {
+  constexpr int MCT = K / 16;
+  using W = WaveSweep<T, K, MCT>;
+  using V = typename W::V;
+  constexpr int NF = W::RT * W::KS;
+  const Layout& L = a.L;
+  const int j = blockIdx.x, spike = blockIdx.y, lane = threadIdx.x & 63;
+  const Geom g = part_geom(L.n, L.p, j, K);
+  const T* fac = wsT<T>(a.ws, L.fac) + (size_t)j * L.nbmax * L.rec;
+  const T* swx = wsT<T>(a.ws, L.swx) + (size_t)j * L.nbmax * 3 * K * K;
+  const T* ym = wsT<T>(a.ws, L.ymat) + (size_t)j * L.nbmax * 2 * K * K;
+  const int* flg = wsT<int>(a.ws, L.flag) + (size_t)j * L.nbmax;
+  const int coff = spike == 0 ? 0 : K;  // Y columns [W | V]
+  auto load_y = [&](int b, V (&st)[W::RT][MCT]) {
+#pragma unroll
+    for (int t = 0; t < W::RT; ++t)
+#pragma unroll
+      for (int ct = 0; ct < MCT; ++ct)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int row = 16 * t + acc_row<T>(lane, v), col = 16 * ct + (lane & 15);
+          st[t][ct][v] = ym[(size_t)b * 2 * K * K + row * 2 * K + coff + col];
+        }
+  };
+  V x1[W::RT][MCT], x2[W::RT][MCT], zb[W::RT][MCT], zn[W::RT][MCT], xb[W::RT][MCT], gr[W::RT][W::RT];
+  zero_strip<T, K, MCT>(x1);
+  zero_strip<T, K, MCT>(x2);
+#pragma unroll
+  for (int ti = 0; ti < W::RT; ++ti)
+#pragma unroll
+    for (int tj = 0; tj < W::RT; ++tj) gr[ti][tj] = V{0, 0, 0, 0};
+  T up[NF], upn[NF], ud[W::RT][4], udn[W::RT][4];
+  int b = g.nb - 1;
+  load_frags<T, K>(up, fac + (size_t)b * L.rec + K * K);
+  load_udrows<T, K>(ud, fac + (size_t)b * L.rec + 2 * K * K);
+  int fl = flg[b];
+  load_y(b, zb);
+  for (; b >= 0; --b) {
+    const bool last = (b == g.nb - 1);
+    int fln = 0;
+    if (b > 0) {
+      load_frags<T, K>(upn, fac + (size_t)(b - 1) * L.rec + K * K);
+      load_udrows<T, K>(udn, fac + (size_t)(b - 1) * L.rec + 2 * K * K);
+      fln = flg[b - 1];
+      load_y(b - 1, zn);
+    }
+    if (!last) {
+      if (fl & 2) {
+        T u12[NF];
+        load_frags<T, K>(u12, swx + (size_t)b * 3 * K * K + K * K);
+        blk_mul<T, K, MCT, 9>(u12, nullptr, T(-1), x1, zb);
+      } else {
+        u12_mul<T, K, MCT>(up, ud, x1, zb);
+      }
+      if (fl & 1) {
+        T u13[NF];
+        load_frags<T, K>(u13, swx + (size_t)b * 3 * K * K + 2 * K * K);
+        blk_mul<T, K, MCT, 9>(u13, nullptr, T(-1), x2, zb);
+      }
+    }
+    zero_strip<T, K, MCT>(xb);
+    blk_mul<T, K, MCT, 2>(up, nullptr, T(1), zb, xb);
+    // Gram += z_b^T z_b
+#pragma unroll
+    for (int ti = 0; ti < W::RT; ++ti)
+#pragma unroll
+      for (int tj = 0; tj < W::RT; ++tj)
+#pragma unroll
+        for (int step = 0; step < W::KS; ++step)
+          gr[ti][tj] = mfma_step(xb[step >> 2][ti][step & 3], xb[step >> 2][tj][step & 3], gr[ti][tj]);
+#pragma unroll
+    for (int t = 0; t < W::RT; ++t)
+#pragma unroll
+      for (int ct = 0; ct < MCT; ++ct) {
+        x2[t][ct] = x1[t][ct];
+        x1[t][ct] = xb[t][ct];
+        zb[t][ct] = zn[t][ct];
+      }
+    if (b > 0) {
+#pragma unroll
+      for (int f = 0; f < NF; ++f) up[f] = upn[f];
+#pragma unroll
+      for (int t = 0; t < W::RT; ++t)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) ud[t][v] = udn[t][v];
+      fl = fln;
+    }
+  }
+  // gram layout [GV | GW], K x K row-major each
+  double* gram = wsT<double>(a.ws, L.gram) + ((size_t)j * 2 + (spike == 0 ? 1 : 0)) * K * K;
+#pragma unroll
+  for (int ti = 0; ti < W::RT; ++ti)
+#pragma unroll
+    for (int tj = 0; tj < W::RT; ++tj)
+#pragma unroll
+      for (int v = 0; v < 4; ++v)
+        gram[(16 * ti + acc_row<T>(lane, v)) * K + 16 * tj + (lane & 15)] = (double)gr[ti][tj][v];
 }
 
 }  // namespace lrs
