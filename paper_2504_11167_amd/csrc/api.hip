@@ -145,7 +145,7 @@ int run_factor(lrspike_plan P) {
       LRS_LAUNCH("factor_pass2", factor_pass2<T, K>, dim3(L.p), dim3(LRS_NT), b2, fa);
     }
     if (L.r > 0) {
-      LRS_LAUNCH("eigen_kernel", eigen_kernel<K>, dim3(L.p, 2), dim3(LRS_NT), 0, ra);
+      LRS_LAUNCH("eigen_kernel", eigen_kernel<K>, dim3(L.p, 2), dim3(64), 0, ra);
       }
   } else {
     LRS_LAUNCH("identity_proj_kernel", identity_proj_kernel<K>, dim3(L.p), dim3(256), 0, ra);
@@ -156,7 +156,7 @@ int run_factor(lrspike_plan P) {
   if (L.NI > 0 && L.r > 0) {
     LRS_LAUNCH("zassemble_kernel", zassemble_kernel<K>, dim3(L.NI), dim3(256), 0, ra);
     const int R2 = L.R2;
-    size_t bodd = (size_t)(R2 * (R2 + 1) + R2 * (2 * R2 + 1)) * 8;
+    size_t bodd = (size_t)(R2 * (R2 + 1) + R2 * (3 * R2 + 1)) * 8;
     if (!set_lds((const void*)cr_odd_kernel, bodd)) return LRSPIKE_ERR_NOT_SUPPORTED;
     for (int l = 0; l < L.levels; ++l) {
       int s = 1 << l;
@@ -183,8 +183,7 @@ int run_reduced(lrspike_plan P, int m, int transpose) {
   if (!set_lds((const void*)zrhs_kernel<K>, bz)) return LRSPIKE_ERR_NOT_SUPPORTED;
   LRS_LAUNCH("zrhs_kernel", zrhs_kernel<K>, dim3(L.NI), dim3(256), bz, ra, P->bands);
   const int R2 = L.R2;
-  size_t bf = (size_t)2 * R2 * m * 8, bb = (size_t)R2 * m * 8;
-  if (!set_lds((const void*)crs_forward_kernel, bf)) return LRSPIKE_ERR_NOT_SUPPORTED;
+  size_t bf = 0, bb = (size_t)R2 * m * 8;
   for (int l = 0; l < L.levels; ++l) {
     int s = 1 << l;
     ra.level = l;

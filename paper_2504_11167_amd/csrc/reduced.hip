@@ -39,7 +39,7 @@ __device__ inline T* rws(char* ws, size_t off) {
 }
 
 // ------------------------------------------------------------------ Jacobi
-// One workgroup per (partition, spike): eigen-decomposition of the K x K Gram
+// One wave per (partition, spike): eigen-decomposition of the K x K Gram
 // matrix by cyclic Jacobi with a round-robin (parallel) pair ordering; writes
 // the eigenvectors of the r largest eigenvalues as the columns of Pi (K x r).
 template <int K>
@@ -56,25 +56,30 @@ __global__ __launch_bounds__(LRS_NT) void eigen_kernel(RedArgs a) {
   const int tid = threadIdx.x, r = L.r;
   double* Pi = rws<double>(a.ws, L.proj) + ((size_t)j * 2 + which) * K * r;
   const double* gram = rws<double>(a.ws, L.gram) + ((size_t)j * 2 + which) * K * K;
-  for (int o = tid; o < K * K; o += LRS_NT) {
+  for (int o = tid; o < K * K; o += blockDim.x) {
     int i = o / K, c = o % K;
     G[i * LD + c] = gram[o];
     V[i * LD + c] = (i == c) ? 1.0 : 0.0;
   }
   __syncthreads();
-  for (int sweep = 0; sweep < 30; ++sweep) {
-    // convergence: off-diagonal mass against the diagonal mass
-    if (tid == 0) {
+  for (int sweep = 0; sweep < 20; ++sweep) {
+    // convergence: off-diagonal mass against the diagonal mass (Frobenius,
+    // relative 1e-14: below that the entries are rounding noise of the Gram)
+    {
       double off = 0.0, dia = 0.0;
-      for (int i = 0; i < K; ++i)
-        for (int c = 0; c < K; ++c) {
-          double v = G[i * LD + c] * G[i * LD + c];
-          if (i == c)
-            dia += v;
-          else
-            off += v;
-        }
-      s_done = (off <= 1e-30 * dia) ? 1 : 0;
+      for (int o = tid; o < K * K; o += blockDim.x) {
+        int i = o / K, c = o % K;
+        double v = G[i * LD + c] * G[i * LD + c];
+        if (i == c)
+          dia += v;
+        else
+          off += v;
+      }
+      for (int w = 32; w >= 1; w >>= 1) {
+        off += __shfl_xor(off, w);
+        dia += __shfl_xor(dia, w);
+      }
+      if (tid == 0) s_done = (off <= 1e-28 * dia) ? 1 : 0;
     }
     __syncthreads();
     if (s_done) break;
@@ -103,7 +108,7 @@ __global__ __launch_bounds__(LRS_NT) void eigen_kernel(RedArgs a) {
       }
       __syncthreads();
       // columns: G <- G J, V <- V J
-      for (int o = tid; o < K * (KE / 2); o += LRS_NT) {
+      for (int o = tid; o < K * (KE / 2); o += blockDim.x) {
         int i = o / (KE / 2), q = o % (KE / 2);
         int p1 = pa[q], p2 = pb[q];
         if (p2 >= K) continue;
@@ -117,7 +122,7 @@ __global__ __launch_bounds__(LRS_NT) void eigen_kernel(RedArgs a) {
       }
       __syncthreads();
       // rows: G <- J^T G
-      for (int o = tid; o < K * (KE / 2); o += LRS_NT) {
+      for (int o = tid; o < K * (KE / 2); o += blockDim.x) {
         int i = o / (KE / 2), q = o % (KE / 2);
         int p1 = pa[q], p2 = pb[q];
         if (p2 >= K) continue;
@@ -142,7 +147,7 @@ __global__ __launch_bounds__(LRS_NT) void eigen_kernel(RedArgs a) {
     }
   }
   __syncthreads();
-  for (int o = tid; o < K * r; o += LRS_NT) {
+  for (int o = tid; o < K * r; o += blockDim.x) {
     int i = o / r, q = o % r;
     Pi[i * r + q] = V[i * LD + order[q]];
   }
@@ -306,8 +311,14 @@ __device__ inline void lu_solve_cols(const double* LU, int ld, const int* piv, i
 }
 
 // ------------------------------------------------------------------ CR factorization
-// Odd rows of level l: LU of D_i (kept), X^F_i = D_i^{-1} F_i, X^E_i = D_i^{-1} E_i.
-// Also used for the top level (row 0 alone, no X needed).
+// Level l (stride s = 2^l), active rows i = 0, s, 2s, ... < NI.
+// Odd rows (i/s odd) are eliminated: Dinv_i = D_i^{-1} (partial-pivoting LU,
+// then solves against the identity), X^F_i = Dinv_i F_i, X^E_i = Dinv_i E_i
+// replace (F_i, E_i) in the row's level slot.  Even rows survive:
+//   D_i -= F_i X^E_{i-s} + E_i X^F_{i+s},  F_i' = -F_i X^F_{i-s},  E_i' = -E_i X^E_{i+s},
+// and their level slot is overwritten by M^F_i = F_i Dinv_{i-s}, M^E_i = E_i Dinv_{i+s}.
+// With these the four solves (Z, Z^T, forward and back substitution) are
+// products of small dense blocks only.
 __global__ __launch_bounds__(LRS_NT) void cr_odd_kernel(RedArgs a) {
   extern __shared__ __align__(16) unsigned char lds_raw[];
   double* M = reinterpret_cast<double*>(lds_raw);
@@ -317,38 +328,37 @@ __global__ __launch_bounds__(LRS_NT) void cr_odd_kernel(RedArgs a) {
   const bool top = a.level >= L.levels;
   const int i = top ? 0 : (2 * blockIdx.x + 1) * s;
   if (i >= L.NI) return;
-  const int ld = R2 + 1, ldx = 2 * R2 + 1;
+  const int ld = R2 + 1, ldx = 3 * R2 + 1;
   double* X = M + R2 * ld;
   int* latch = rws<int>(a.ws, L.latch);
   const double* D = rws<double>(a.ws, L.zD) + (size_t)i * R2 * R2;
   for (int o = threadIdx.x; o < R2 * R2; o += blockDim.x) M[o / R2 * ld + o % R2] = D[o];
-  __syncthreads();
-  dense_lu(M, ld, R2, piv, latch, i);
-  double* LU = rws<double>(a.ws, L.zLU) + (size_t)i * R2 * R2;
-  int* gp = rws<int>(a.ws, L.zpiv) + (size_t)i * R2;
-  for (int o = threadIdx.x; o < R2 * R2; o += blockDim.x) LU[o] = M[o / R2 * ld + o % R2];
-  for (int o = threadIdx.x; o < R2; o += blockDim.x) gp[o] = piv[o];
-  if (top) return;
-  const double* FE = rws<double>(a.ws, L.zFE) + (size_t)(L.lvl_off[a.level] + i / s) * 2 * R2 * R2;
-  for (int o = threadIdx.x; o < R2 * 2 * R2; o += blockDim.x) {
-    int row = o / (2 * R2), col = o % (2 * R2);
-    X[row * ldx + col] = (col < R2) ? FE[row * R2 + col] : FE[R2 * R2 + row * R2 + col - R2];
+  double* FE = top ? nullptr : rws<double>(a.ws, L.zFE) + (size_t)(L.lvl_off[a.level] + i / s) * 2 * R2 * R2;
+  // right-hand sides [I | F | E]
+  for (int o = threadIdx.x; o < R2 * 3 * R2; o += blockDim.x) {
+    int row = o / (3 * R2), col = o % (3 * R2);
+    double v;
+    if (col < R2)
+      v = (row == col) ? 1.0 : 0.0;
+    else if (top)
+      v = 0.0;
+    else
+      v = FE[(col < 2 * R2 ? 0 : R2 * R2) + row * R2 + (col < 2 * R2 ? col - R2 : col - 2 * R2)];
+    X[row * ldx + col] = v;
   }
   __syncthreads();
-  lu_solve_cols(M, ld, piv, R2, X, ldx, 2 * R2, false);
+  dense_lu(M, ld, R2, piv, latch, i);
+  lu_solve_cols(M, ld, piv, R2, X, ldx, top ? R2 : 3 * R2, false);
   __syncthreads();
-  double* XG = rws<double>(a.ws, L.zX) + (size_t)i * 2 * R2 * R2;  // [X^F][X^E]
-  for (int o = threadIdx.x; o < R2 * 2 * R2; o += blockDim.x) {
-    int row = o / (2 * R2), col = o % (2 * R2);
-    if (col < R2)
-      XG[row * R2 + col] = X[row * ldx + col];
-    else
-      XG[R2 * R2 + row * R2 + col - R2] = X[row * ldx + col];
+  double* Dinv = rws<double>(a.ws, L.zLU) + (size_t)i * R2 * R2;
+  for (int o = threadIdx.x; o < R2 * R2; o += blockDim.x) Dinv[o] = X[o / R2 * ldx + o % R2];
+  if (top) return;
+  for (int o = threadIdx.x; o < 2 * R2 * R2; o += blockDim.x) {
+    int which = o / (R2 * R2), e = o % (R2 * R2), row = e / R2, col = e % R2;
+    FE[o] = X[row * ldx + R2 + which * R2 + col];  // [X^F | X^E]
   }
 }
 
-// Even rows of level l:  D_i -= F_i X^E_{i-s} + E_i X^F_{i+s};
-// F_i' = -F_i X^F_{i-s};  E_i' = -E_i X^E_{i+s}  (level l+1 slots).
 __global__ __launch_bounds__(LRS_NT) void cr_even_kernel(RedArgs a) {
   const Layout& L = a.L;
   const int R2 = L.R2, s = 1 << a.level;
@@ -356,115 +366,127 @@ __global__ __launch_bounds__(LRS_NT) void cr_even_kernel(RedArgs a) {
   if (i >= L.NI) return;
   const bool hasL = i - s >= 0, hasR = i + s < L.NI;
   double* D = rws<double>(a.ws, L.zD) + (size_t)i * R2 * R2;
-  const double* FE = rws<double>(a.ws, L.zFE) + (size_t)(L.lvl_off[a.level] + i / s) * 2 * R2 * R2;
+  double* FE = rws<double>(a.ws, L.zFE) + (size_t)(L.lvl_off[a.level] + i / s) * 2 * R2 * R2;
   double* FEn = rws<double>(a.ws, L.zFE) + (size_t)(L.lvl_off[a.level + 1] + i / (2 * s)) * 2 * R2 * R2;
   const double* F = FE;
   const double* E = FE + R2 * R2;
-  const double* XL = hasL ? rws<double>(a.ws, L.zX) + (size_t)(i - s) * 2 * R2 * R2 : nullptr;
-  const double* XR = hasR ? rws<double>(a.ws, L.zX) + (size_t)(i + s) * 2 * R2 * R2 : nullptr;
+  auto slot = [&](int row) { return rws<double>(a.ws, L.zFE) + (size_t)(L.lvl_off[a.level] + row / s) * 2 * R2 * R2; };
+  const double* XL = hasL ? slot(i - s) : nullptr;  // [X^F | X^E] of row i - s
+  const double* XR = hasR ? slot(i + s) : nullptr;
+  const double* DL = hasL ? rws<double>(a.ws, L.zLU) + (size_t)(i - s) * R2 * R2 : nullptr;
+  const double* DR = hasR ? rws<double>(a.ws, L.zLU) + (size_t)(i + s) * R2 * R2 : nullptr;
+  // pass 1: next-level blocks and the new D (reads F, E); M^F, M^E staged in
+  // the row's scratch block until every thread is done reading F, E
+  double* MS = rws<double>(a.ws, L.zX) + (size_t)i * 2 * R2 * R2;
   for (int o = threadIdx.x; o < R2 * R2; o += blockDim.x) {
     int row = o / R2, col = o % R2;
-    double dd = 0.0, fn = 0.0, en = 0.0;
+    double dd = 0.0, fn = 0.0, en = 0.0, mf = 0.0, me = 0.0;
     for (int l = 0; l < R2; ++l) {
       if (hasL) {
         double fl = F[row * R2 + l];
         dd += fl * XL[R2 * R2 + l * R2 + col];  // F X^E_{i-s}
         fn += fl * XL[l * R2 + col];            // F X^F_{i-s}
+        mf += fl * DL[l * R2 + col];            // F Dinv_{i-s}
       }
       if (hasR) {
         double el = E[row * R2 + l];
         dd += el * XR[l * R2 + col];            // E X^F_{i+s}
         en += el * XR[R2 * R2 + l * R2 + col];  // E X^E_{i+s}
+        me += el * DR[l * R2 + col];            // E Dinv_{i+s}
       }
     }
     D[o] -= dd;
     FEn[o] = -fn;
     FEn[R2 * R2 + o] = -en;
+    MS[o] = mf;
+    MS[R2 * R2 + o] = me;
   }
+  __syncthreads();
+  for (int o = threadIdx.x; o < 2 * R2 * R2; o += blockDim.x) FE[o] = MS[o];  // [M^F | M^E]
 }
 
 // ------------------------------------------------------------------ CR solves
 // g (compressed vectors, [NI][R2][mmax]) is solved in place.
 // Forward reduction at level l, even rows:
-//   g_i -= F_i D_{i-s}^{-1} g_{i-s} + E_i D_{i+s}^{-1} g_{i+s}              (Z)
-//   g_i -= E_{i-s}^T D_{i-s}^{-T} g_{i-s} + F_{i+s}^T D_{i+s}^{-T} g_{i+s}  (Z^T)
+//   Z:    g_i -= M^F_i g_{i-s} + M^E_i g_{i+s}
+//   Z^T:  g_i -= (X^E_{i-s})^T g_{i-s} + (X^F_{i+s})^T g_{i+s}
 __global__ __launch_bounds__(LRS_NT) void crs_forward_kernel(RedArgs a) {
-  extern __shared__ __align__(16) unsigned char lds_raw[];
-  double* T1 = reinterpret_cast<double*>(lds_raw);  // [R2][m]
-  double* T2 = T1 + a.L.R2 * a.m;
   const Layout& L = a.L;
   const int R2 = L.R2, s = 1 << a.level, m = a.m, mm = L.mmax;
   const int i = 2 * blockIdx.x * s;
   if (i >= L.NI) return;
   const bool hasL = i - s >= 0, hasR = i + s < L.NI;
   double* g = rws<double>(a.ws, L.zg);
-  const double* FEall = rws<double>(a.ws, L.zFE);
-  auto slot = [&](int row) { return FEall + (size_t)(L.lvl_off[a.level] + row / s) * 2 * R2 * R2; };
-  for (int side = 0; side < 2; ++side) {
-    if ((side == 0 && !hasL) || (side == 1 && !hasR)) continue;
-    const int o_i = side == 0 ? i - s : i + s;
-    const double* LU = rws<double>(a.ws, L.zLU) + (size_t)o_i * R2 * R2;
-    const int* pv = rws<int>(a.ws, L.zpiv) + (size_t)o_i * R2;
-    double* T = side == 0 ? T1 : T2;
-    for (int o = threadIdx.x; o < R2 * m; o += blockDim.x) T[o] = g[((size_t)o_i * R2 + o / m) * mm + o % m];
-    __syncthreads();
-    lu_solve_cols(LU, R2, pv, R2, T, m, m, a.transpose != 0);
-    __syncthreads();
-  }
+  auto slot = [&](int row) { return rws<double>(a.ws, L.zFE) + (size_t)(L.lvl_off[a.level] + row / s) * 2 * R2 * R2; };
+  const double* own = slot(i);
   for (int o = threadIdx.x; o < R2 * m; o += blockDim.x) {
     int row = o / m, c = o % m;
     double acc = 0.0;
     if (hasL) {
-      // Z: F_i (own slot) ; Z^T: E_{i-s}^T (odd neighbour's slot)
-      const double* Mx = a.transpose ? slot(i - s) + R2 * R2 : slot(i);
-      for (int l = 0; l < R2; ++l)
-        acc += (a.transpose ? Mx[l * R2 + row] : Mx[row * R2 + l]) * T1[l * m + c];
+      const double* gl = g + (size_t)(i - s) * R2 * mm;
+      if (!a.transpose) {
+        for (int l = 0; l < R2; ++l) acc += own[row * R2 + l] * gl[l * mm + c];
+      } else {
+        const double* XE = slot(i - s) + R2 * R2;
+        for (int l = 0; l < R2; ++l) acc += XE[l * R2 + row] * gl[l * mm + c];
+      }
     }
     if (hasR) {
-      const double* Mx = a.transpose ? slot(i + s) : slot(i) + R2 * R2;
-      for (int l = 0; l < R2; ++l)
-        acc += (a.transpose ? Mx[l * R2 + row] : Mx[row * R2 + l]) * T2[l * m + c];
+      const double* gr = g + (size_t)(i + s) * R2 * mm;
+      if (!a.transpose) {
+        for (int l = 0; l < R2; ++l) acc += own[R2 * R2 + row * R2 + l] * gr[l * mm + c];
+      } else {
+        const double* XF = slot(i + s);
+        for (int l = 0; l < R2; ++l) acc += XF[l * R2 + row] * gr[l * mm + c];
+      }
     }
     g[((size_t)i * R2 + row) * mm + c] -= acc;
   }
 }
 
 // Top (row 0 alone) and back substitution of the odd rows of level l:
-//   g_i = D_i^{-1} (g_i - F_i g_{i-s} - E_i g_{i+s})                 (Z)
-//   g_i = D_i^{-T} (g_i - E_{i-s}^T g_{i-s} - F_{i+s}^T g_{i+s})     (Z^T)
+//   Z:    g_i = Dinv_i g_i - X^F_i g_{i-s} - X^E_i g_{i+s}
+//   Z^T:  g_i = Dinv_i^T g_i - (M^E_{i-s})^T g_{i-s} - (M^F_{i+s})^T g_{i+s}
 __global__ __launch_bounds__(LRS_NT) void crs_backward_kernel(RedArgs a) {
   extern __shared__ __align__(16) unsigned char lds_raw[];
-  double* T = reinterpret_cast<double*>(lds_raw);
+  double* Tg = reinterpret_cast<double*>(lds_raw);
   const Layout& L = a.L;
   const int R2 = L.R2, s = 1 << a.level, m = a.m, mm = L.mmax;
   const bool top = a.level >= L.levels;
   const int i = top ? 0 : (2 * blockIdx.x + 1) * s;
   if (i >= L.NI) return;
   double* g = rws<double>(a.ws, L.zg);
-  const double* FEall = rws<double>(a.ws, L.zFE);
-  auto slot = [&](int row) { return FEall + (size_t)(L.lvl_off[a.level] + row / s) * 2 * R2 * R2; };
+  auto slot = [&](int row) { return rws<double>(a.ws, L.zFE) + (size_t)(L.lvl_off[a.level] + row / s) * 2 * R2 * R2; };
   const bool hasL = !top && i - s >= 0, hasR = !top && i + s < L.NI;
+  const double* Dinv = rws<double>(a.ws, L.zLU) + (size_t)i * R2 * R2;
+  for (int o = threadIdx.x; o < R2 * m; o += blockDim.x) Tg[o] = g[((size_t)i * R2 + o / m) * mm + o % m];
+  __syncthreads();
   for (int o = threadIdx.x; o < R2 * m; o += blockDim.x) {
     int row = o / m, c = o % m;
-    double v = g[((size_t)i * R2 + row) * mm + c];
+    double v = 0.0;
+    for (int l = 0; l < R2; ++l) v += (a.transpose ? Dinv[l * R2 + row] : Dinv[row * R2 + l]) * Tg[l * m + c];
     if (hasL) {
-      const double* Mx = a.transpose ? slot(i - s) + R2 * R2 : slot(i);
-      for (int l = 0; l < R2; ++l)
-        v -= (a.transpose ? Mx[l * R2 + row] : Mx[row * R2 + l]) * g[((size_t)(i - s) * R2 + l) * mm + c];
+      const double* gl = g + (size_t)(i - s) * R2 * mm;
+      if (!a.transpose) {
+        const double* XF = slot(i);
+        for (int l = 0; l < R2; ++l) v -= XF[row * R2 + l] * gl[l * mm + c];
+      } else {
+        const double* ME = slot(i - s) + R2 * R2;
+        for (int l = 0; l < R2; ++l) v -= ME[l * R2 + row] * gl[l * mm + c];
+      }
     }
     if (hasR) {
-      const double* Mx = a.transpose ? slot(i + s) : slot(i) + R2 * R2;
-      for (int l = 0; l < R2; ++l)
-        v -= (a.transpose ? Mx[l * R2 + row] : Mx[row * R2 + l]) * g[((size_t)(i + s) * R2 + l) * mm + c];
+      const double* gr = g + (size_t)(i + s) * R2 * mm;
+      if (!a.transpose) {
+        const double* XE = slot(i) + R2 * R2;
+        for (int l = 0; l < R2; ++l) v -= XE[row * R2 + l] * gr[l * mm + c];
+      } else {
+        const double* MF = slot(i + s);
+        for (int l = 0; l < R2; ++l) v -= MF[l * R2 + row] * gr[l * mm + c];
+      }
     }
-    T[row * m + c] = v;
+    g[((size_t)i * R2 + row) * mm + c] = v;
   }
-  __syncthreads();
-  const double* LU = rws<double>(a.ws, L.zLU) + (size_t)i * R2 * R2;
-  const int* pv = rws<int>(a.ws, L.zpiv) + (size_t)i * R2;
-  lu_solve_cols(LU, R2, pv, R2, T, m, m, a.transpose != 0);
-  __syncthreads();
-  for (int o = threadIdx.x; o < R2 * m; o += blockDim.x) g[((size_t)i * R2 + o / m) * mm + o % m] = T[o];
 }
 
 // ------------------------------------------------------------------ compressed rhs
