@@ -19,7 +19,7 @@ struct RedArgs;
 #include "factor.hip"
 #include "reduced.hip"
 #include "solve.hip"
-#include "solve_wave.hip"
+#include "factor_wave.hip"
 
 using namespace lrs;
 
@@ -134,7 +134,21 @@ int run_factor(lrspike_plan P) {
   hipStream_t st = P->stream;
   size_t b1 = lds_p1<T, K>();
   if (!set_lds((const void*)factor_pass1<T, K>, b1)) return LRSPIKE_ERR_NOT_SUPPORTED;
-  LRS_LAUNCH("factor_pass1", factor_pass1<T, K>, dim3(L.p), dim3(LRS_NT), b1, fa);
+  if constexpr (K >= 16) {
+    // one wave per partition without interchanges; partitions that need them
+    // are flagged and refactored by the general kernel (a no-op elsewhere)
+    LRS_LAUNCH("zero_kernel", zero_kernel, dim3((L.p + 255) / 256), dim3(256), 0,
+               reinterpret_cast<int*>(P->ws + L.npv), L.p);
+    const size_t bw = (size_t)FWave<T, K>::total * sizeof(T);
+    if (!set_lds((const void*)factor_wave_kernel<T, K>, bw)) return LRSPIKE_ERR_NOT_SUPPORTED;
+    LRS_LAUNCH("factor_pass1", factor_wave_kernel<T, K>, dim3(L.p), dim3(64), bw, fa);
+    LRS_LAUNCH("spike_fwd", spike_wave_kernel<T, K>, dim3(L.p), dim3(64), 0, fa);
+    fa.only_flagged = 1;
+    LRS_LAUNCH("factor_pass1_pivoting", factor_pass1<T, K>, dim3(L.p), dim3(LRS_NT), b1, fa);
+    fa.only_flagged = 0;
+  } else {
+    LRS_LAUNCH("factor_pass1", factor_pass1<T, K>, dim3(L.p), dim3(LRS_NT), b1, fa);
+  }
   RedArgs ra{P->ws, L, 0, 0, 0};
   if (L.r < L.K) {
     if constexpr (K >= 16) {

@@ -31,6 +31,7 @@ struct FactorArgs {
   const double* bands;
   char* ws;
   Layout L;
+  int only_flagged;  // factor only the partitions flagged in the npv array
 };
 
 template <typename T>
@@ -76,6 +77,7 @@ __global__ __launch_bounds__(LRS_NT) void factor_pass1(FactorArgs a) {
   const Layout& L = a.L;
   const int j = blockIdx.x;
   const int tid = threadIdx.x;
+  if (a.only_flagged && wsT<int>(a.ws, L.npv)[j] == 0) return;
   const Geom g = part_geom(L.n, L.p, j, K);
   const int k = L.k;
   const int nb = g.nb;

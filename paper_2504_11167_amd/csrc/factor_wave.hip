@@ -1,0 +1,434 @@
+// Factorization pass 1 for K >= 16, one wave per partition (no workgroup
+// barriers; every partition of a 1024-partition problem resident at once).
+//
+// Per K-row block b (see factor.hip for the block formulation):
+//   panel [Dc_b; Lo_{b+1}] eliminated in registers (lane = row, the pivot row
+//   broadcast through LDS) WITHOUT row interchanges, an identity block riding
+//   along so that the first K lanes end with the rows of L11^{-1};  if any
+//   multiplier exceeds 1 in magnitude (or a pivot is zero) partial pivoting
+//   would have interchanged rows: the partition is flagged and refactored by
+//   the interchanging kernel, so the result is always the partial-pivoting
+//   factorization;
+//   U11^{-1} by an upward Gauss-Jordan pass over the same registers;
+//   U12 = L11^{-1} Up_b, Dc_{b+1} = D_{b+1} - L21 U12          (matrix cores)
+//   G step:    g_b = U11^{-T} (e_b + pending), pending' = -U12^T g_b (matrix cores)
+// The spike forward sweeps run afterwards in spike_wave_kernel over the
+// stored factors (same structure as the D-stage of the solve).
+// Block products keep their operands in accumulator tiles (the accumulator
+// layout is the B operand layout, and tile-transposed the A operand of the
+// transposed product); LDS holds only the band slab of the next row block,
+// the packed L11^{-1}\U11 (later U11^{-1}) and L21 (later U12) blocks.
+#include "solve_wave.hip"
+
+namespace lrs {
+
+template <typename T, int K>
+struct FWave {
+  static constexpr int RT = K / 16, KS = K / 4, PT = K + 1;
+  using V = typename AccVec<T>::type;
+  static constexpr int oSlab = 0;                    // (2K+1) x K, diagonal-major
+  static constexpr int oLib = oSlab + (2 * K + 1) * K;  // K x PT
+  static constexpr int oL21 = oLib + K * PT;         // K x PT
+  static constexpr int oRow = oL21 + K * PT;         // broadcast pivot row, 2K
+  static constexpr int total = oRow + 2 * K;
+};
+
+__device__ __forceinline__ void wave_fence() {  // order LDS accesses of one wave
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Forward elimination step C of the 2K x K panel without interchanges, lane =
+// row, row held in pa[] (U part / multipliers) and iv[] (the row of L11^{-1}
+// being formed, implicit 1 at the lane's own column).  The pivot row is
+// published through LDS and read back as a broadcast.
+template <typename T, int K, int C>
+struct FwdElim {
+  static __device__ __forceinline__ void run(T (&pa)[K], T (&iv)[K], T* prow, int lane, int nr, T& mx,
+                                             T& dmin) {
+    if constexpr (C < K) {
+      if (lane == C) {
+#pragma unroll
+        for (int c = C; c < K; ++c) prow[c] = pa[c];
+#pragma unroll
+        for (int c = 0; c < C; ++c) prow[K + c] = iv[c];
+      }
+      wave_fence();
+      const T d = prow[C];
+      dmin = fmin(dmin, fabs(d));
+      const bool act = lane > C && lane < nr;
+      const T l = act ? pa[C] / d : T(0);
+      mx = fmax(mx, fabs(l));
+      if (act) pa[C] = l;
+#pragma unroll
+      for (int c = C + 1; c < K; ++c) pa[c] = fma(-l, prow[c], pa[c]);
+#pragma unroll
+      for (int c = 0; c < C; ++c) iv[c] = fma(-l, prow[K + c], iv[c]);
+      iv[C] -= l;
+      wave_fence();
+      FwdElim<T, K, C + 1>::run(pa, iv, prow, lane, nr, mx, dmin);
+    }
+  }
+};
+
+// Upward Gauss-Jordan step C (counting down): lane i < K holds in uv[] the row
+// i of U11^{-1} being formed; U11 itself is read from pa[] (upper part).
+template <typename T, int K, int C>
+struct BwdElim {
+  static __device__ __forceinline__ void run(const T (&pa)[K], T (&uv)[K], T* prow, int lane) {
+    if constexpr (C >= 0) {
+      if (lane == C) {
+        const T s = T(1) / pa[C];
+#pragma unroll
+        for (int c = C; c < K; ++c) {
+          uv[c] *= s;
+          prow[c] = uv[c];
+        }
+      }
+      wave_fence();
+      const T m = lane < C ? pa[C] : T(0);
+#pragma unroll
+      for (int c = C; c < K; ++c) uv[c] = fma(-m, prow[c], uv[c]);
+      wave_fence();
+      BwdElim<T, K, C - 1>::run(pa, uv, prow, lane);
+    }
+  }
+};
+
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+
+template <typename T, int K>
+__global__ __launch_bounds__(64) void factor_wave_kernel(FactorArgs a) {
+  using F = FWave<T, K>;
+  using V = typename F::V;
+  constexpr int RT = F::RT, KS = F::KS, PT = F::PT;
+  extern __shared__ __align__(16) unsigned char lds_raw[];
+  T* lds = reinterpret_cast<T*>(lds_raw);
+  T* slab = lds + F::oSlab;
+  T* lib = lds + F::oLib;
+  T* l21b = lds + F::oL21;
+  T* prow = lds + F::oRow;
+  const Layout& L = a.L;
+  const int j = blockIdx.x, lane = threadIdx.x & 63, k = L.k;
+  const Geom g = part_geom(L.n, L.p, j, K);
+  const int nb = g.nb;
+  T* fac = wsT<T>(a.ws, L.fac) + (size_t)j * L.nbmax * L.rec;
+  T* gm = wsT<T>(a.ws, L.gmat) + (size_t)j * L.nbmax * K * K;
+  int* ipv = wsT<int>(a.ws, L.ipiv) + (size_t)j * L.nbmax * K;
+  int* flg = wsT<int>(a.ws, L.flag) + (size_t)j * L.nbmax;
+  int* npv = wsT<int>(a.ws, L.npv);
+
+  // band slab of row block R: slab[(d + K) K + i] = A(R K + i, R K + i + d)
+  // (partition-local, identity on the virtual rows, zero outside)
+  auto slab_load = [&](int R) {
+    for (int o = lane; o < (2 * k + 1) * K; o += 64) {
+      const int d = o / K - k, i = o % K;
+      const int lr = R * K + i - g.pad;
+      T v = T(0);
+      if (lr < 0) {
+        v = (d == 0) ? T(1) : T(0);
+      } else if (lr < g.nj) {
+        const int lc = lr + d;
+        if (lc >= 0 && lc < g.nj) v = (T)a.bands[(int64_t)(d + k) * L.n + g.s + lr];
+      }
+      slab[(d + K) * K + i] = v;
+    }
+  };
+  auto sl = [&](int i, int d) -> T { return (d >= -K && d <= K) ? slab[(d + K) * K + i] : T(0); };
+  auto for_elems = [&](auto&& fn) {  // (t, ct, v, row, col) of the lane's accumulator elements
+#pragma unroll
+    for (int t = 0; t < RT; ++t)
+#pragma unroll
+      for (int ct = 0; ct < RT; ++ct)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) fn(t, ct, v, 16 * t + acc_row<T>(lane, v), 16 * ct + (lane & 15));
+  };
+  auto zero = [&](V (&x)[RT][RT]) {
+#pragma unroll
+    for (int t = 0; t < RT; ++t)
+#pragma unroll
+      for (int ct = 0; ct < RT; ++ct) x[t][ct] = V{0, 0, 0, 0};
+  };
+  // out (+)= op(A) * in; A operand element (i, kk) from fa(i, kk); B from accumulator tiles
+  auto mul = [&](auto&& fa, const V (&in)[RT][RT], V (&out)[RT][RT], T sign) {
+#pragma unroll
+    for (int t = 0; t < RT; ++t)
+#pragma unroll
+      for (int step = 0; step < KS; ++step) {
+        const T av = sign * fa(16 * t + (lane & 15), frag_k<T>(step, lane >> 4));
+#pragma unroll
+        for (int ct = 0; ct < RT; ++ct) out[t][ct] = mfma_step(av, in[step >> 2][ct][step & 3], out[t][ct]);
+      }
+  };
+  // out += X^T * in with X in accumulator tiles (tile-transposed A operand)
+  auto mul_tr = [&](const V (&X)[RT][RT], const V (&in)[RT][RT], V (&out)[RT][RT], T sign) {
+#pragma unroll
+    for (int t = 0; t < RT; ++t)
+#pragma unroll
+      for (int step = 0; step < KS; ++step) {
+        const T av = sign * X[step >> 2][t][step & 3];
+#pragma unroll
+        for (int ct = 0; ct < RT; ++ct) out[t][ct] = mfma_step(av, in[step >> 2][ct][step & 3], out[t][ct]);
+      }
+  };
+
+  // ---- initial state: Dc_0 (lib, row-major), Up_0 (uc), W rhs of blocks 0 and 1
+  for (int o = lane; o < (2 * K + 1) * K; o += 64) slab[o] = T(0);
+  wave_sync();
+  slab_load(0);
+  wave_sync();
+  V uc[RT][RT], gc[RT][RT];
+  for (int o = lane; o < K * K; o += 64) lib[(o / K) * PT + o % K] = sl(o / K, o % K - o / K);
+  for_elems([&](int t, int ct, int v, int row, int col) { uc[t][ct][v] = sl(row, K + col - row); });
+  zero(gc);
+  wave_sync();
+  if (nb > 1) slab_load(1);
+  wave_sync();
+
+  for (int b = 0; b < nb; ++b) {
+    const bool last = (b == nb - 1);
+    const int nr = last ? K : 2 * K;
+    // ---- panel [Dc_b; Lo_{b+1}]: lane i < K takes row i of Dc_b (lib), lane K + i
+    // row i of Lo_{b+1} (slab)
+    {
+      T pa[K], iv[K];
+#pragma unroll
+      for (int c = 0; c < K; ++c) {
+        T v = T(0);
+        if (lane < K)
+          v = lib[lane * PT + c];
+        else if (lane < nr)
+          v = sl(lane - K, c - lane);
+        pa[c] = v;
+        iv[c] = T(0);
+      }
+      T mx = T(0), dmin = T(1e30);
+      FwdElim<T, K, 0>::run(pa, iv, prow, lane, nr, mx, dmin);
+      const bool ok = !__any(!(mx <= T(1))) && (dmin > T(0));
+      if (!ok) {
+        if (lane == 0) npv[j] = 1;
+        return;  // refactored with row interchanges by the general kernel
+      }
+      // lib <- L11^{-1} strictly below the diagonal; l21b <- L21
+      if (lane < K) {
+#pragma unroll
+        for (int c = 0; c < K; ++c)
+          if (c < lane) lib[lane * PT + c] = iv[c];
+      } else if (lane < nr) {
+#pragma unroll
+        for (int c = 0; c < K; ++c) l21b[(lane - K) * PT + c] = pa[c];
+      }
+      // U11^{-1} rows, then lib <- U11^{-1} on and above the diagonal
+#pragma unroll
+      for (int c = 0; c < K; ++c) iv[c] = (c == lane) ? T(1) : T(0);
+      BwdElim<T, K, K - 1>::run(pa, iv, prow, lane);
+      if (lane < K)
+#pragma unroll
+        for (int c = 0; c < K; ++c)
+          if (c >= lane) lib[lane * PT + c] = iv[c];
+      wave_sync();
+    }
+    auto Li = [&](int i, int kk) -> T { return i > kk ? lib[i * PT + kk] : (i == kk ? T(1) : T(0)); };
+    auto Ui = [&](int i, int kk) -> T { return i <= kk ? lib[i * PT + kk] : T(0); };
+    auto UiT = [&](int i, int kk) -> T { return kk <= i ? lib[kk * PT + i] : T(0); };
+    auto L21 = [&](int i, int kk) -> T { return i <= kk ? l21b[i * PT + kk] : T(0); };
+    V u12[RT][RT], dn[RT][RT];
+    if (!last) {
+      zero(u12);
+      mul(Li, uc, u12, T(1));  // U12 = L11^{-1} Up_b
+    }
+    // ---- G step (the columns of E_t met in this block enter the pending sum)
+    {
+      V gb[RT][RT];
+      for_elems([&](int t, int ct, int v, int row, int col) {
+        if (col == b * K + row - g.pad) gc[t][ct][v] += T(1);
+      });
+      zero(gb);
+      mul(UiT, gc, gb, T(1));
+      zero(gc);
+      if (!last) mul_tr(u12, gb, gc, T(-1));  // pending(b+1) = -U12^T g_b
+#pragma unroll
+      for (int t = 0; t < RT; ++t)
+#pragma unroll
+        for (int step = 0; step < KS; ++step)
+          gm[(size_t)b * K * K + ((t * KS + step) << 6) + lane] = gb[step >> 2][t][step & 3];
+    }
+    if (!last) {
+      for_elems([&](int t, int ct, int v, int row, int col) { dn[t][ct][v] = sl(row, col - row); });
+      mul(L21, u12, dn, T(-1));  // Dc_{b+1} = D_{b+1} - L21 U12
+    }
+    // ---- stores: LP, pivots, flags
+    T* rec = fac + (size_t)b * L.rec;
+    for (int o = lane; o < K * K; o += 64) {
+      int i, c;
+      fidx_inv<T, K>(o, i, c);
+      rec[o] = (i > c) ? lib[i * PT + c] : (last ? T(0) : l21b[i * PT + c]);
+    }
+    if (lane < K) ipv[(size_t)b * K + lane] = lane;
+    if (lane == 0) flg[b] = 0;
+    wave_sync();
+    if (!last) {
+      // U12 staged row-major in l21b (L21 no longer needed), then UP = U11^{-1} | U12
+      for_elems([&](int t, int ct, int v, int row, int col) { l21b[row * PT + col] = u12[t][ct][v]; });
+      wave_sync();
+      for (int o = lane; o < K * K; o += 64) {
+        int i, c;
+        fidx_inv<T, K>(o, i, c);
+        rec[K * K + o] = (i <= c) ? lib[i * PT + c] : l21b[i * PT + c];
+      }
+      if (lane < K) rec[2 * K * K + lane] = l21b[lane * PT + lane];
+      wave_sync();
+      // next state: Dc_{b+1} -> lib, Up_{b+1} -> uc, W window shifts, next slab
+      for_elems([&](int t, int ct, int v, int row, int col) {
+        lib[row * PT + col] = dn[t][ct][v];
+        uc[t][ct][v] = sl(row, K + col - row);
+      });
+      wave_sync();
+      if (b + 2 < nb) slab_load(b + 2);
+      wave_sync();
+    } else {
+      for (int o = lane; o < K * K; o += 64) {
+        int i, c;
+        fidx_inv<T, K>(o, i, c);
+        rec[K * K + o] = (i <= c) ? lib[i * PT + c] : T(0);
+      }
+      if (lane < K) rec[2 * K * K + lane] = T(0);
+    }
+  }
+}
+
+
+// Spike forward sweeps over the stored factors (partitions factored without
+// interchanges; the others were fully handled by the interchanging kernel).
+//   W: rhs [C_j; 0] (first K real rows):  z_b = L11^{-1} r_b, r_{b+1} -= L21 z_b,
+//      W_t = sum_b G_b^T z_b, W_b = U11^{-1} z_last; z_b kept for the Gram pass (r < k)
+//   V: rhs [0; B_j] lives in the last block only: z = L11^{-1} B_j there,
+//      V_b = U11^{-1} z, V_t = G_last^T z.
+template <typename T, int K>
+__global__ __launch_bounds__(64) void spike_wave_kernel(FactorArgs a) {
+  constexpr int MCT = K / 16;
+  using W = WaveSweep<T, K, MCT>;
+  using V = typename W::V;
+  constexpr int NF = W::RT * W::KS;
+  const Layout& L = a.L;
+  const int j = blockIdx.x, lane = threadIdx.x & 63, k = L.k;
+  if (wsT<int>(a.ws, L.npv)[j]) return;
+  const Geom g = part_geom(L.n, L.p, j, K);
+  const T* fac = wsT<T>(a.ws, L.fac) + (size_t)j * L.nbmax * L.rec;
+  const T* gm = wsT<T>(a.ws, L.gmat) + (size_t)j * L.nbmax * K * K;
+  T* ym = (L.r < K) ? wsT<T>(a.ws, L.ymat) + (size_t)j * L.nbmax * 2 * K * K : nullptr;
+  double* tips = wsT<double>(a.ws, L.tips) + (size_t)j * 4 * K * K;  // Vt, Vb, Wt, Wb
+  auto rhs_w = [&](int R, V (&st)[W::RT][MCT]) {
+#pragma unroll
+    for (int t = 0; t < W::RT; ++t)
+#pragma unroll
+      for (int ct = 0; ct < MCT; ++ct)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int row = 16 * t + acc_row<T>(lane, v), col = 16 * ct + (lane & 15);
+          const int lr = R * K + row - g.pad;
+          st[t][ct][v] = (j > 0 && lr >= 0 && lr < K && lr < g.nj) ? (T)band_at(a.bands, L.n, k, g.s + lr, g.s - K + col) : T(0);
+        }
+  };
+  auto put = [&](int which, const V (&st)[W::RT][MCT]) {
+#pragma unroll
+    for (int t = 0; t < W::RT; ++t)
+#pragma unroll
+      for (int ct = 0; ct < MCT; ++ct)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int row = 16 * t + acc_row<T>(lane, v), col = 16 * ct + (lane & 15);
+          tips[(size_t)which * K * K + row * K + col] = (double)st[t][ct][v];
+        }
+  };
+  auto put_y = [&](int b, int coff, const V (&st)[W::RT][MCT]) {
+#pragma unroll
+    for (int t = 0; t < W::RT; ++t)
+#pragma unroll
+      for (int ct = 0; ct < MCT; ++ct)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int row = 16 * t + acc_row<T>(lane, v), col = 16 * ct + (lane & 15);
+          ym[(size_t)b * 2 * K * K + row * 2 * K + coff + col] = st[t][ct][v];
+        }
+  };
+  V w0[W::RT][MCT], w1[W::RT][MCT], z[W::RT][MCT], acc[W::RT][MCT];
+  zero_strip<T, K, MCT>(acc);
+  rhs_w(0, w0);
+  if (g.nb > 1)
+    rhs_w(1, w1);
+  else
+    zero_strip<T, K, MCT>(w1);
+  T lp[NF], gt[NF], lpn[NF], gtn[NF];
+  load_frags<T, K>(lp, fac);
+  load_frags<T, K>(gt, gm);
+  for (int b = 0; b < g.nb; ++b) {
+    const bool last = (b == g.nb - 1);
+    if (!last) {
+      load_frags<T, K>(lpn, fac + (size_t)(b + 1) * L.rec);
+      load_frags<T, K>(gtn, gm + (size_t)(b + 1) * K * K);
+    }
+    zero_strip<T, K, MCT>(z);
+    blk_mul<T, K, MCT, 0>(lp, nullptr, T(1), w0, z);
+    if (!last) blk_mul<T, K, MCT, 1>(lp, nullptr, T(-1), z, w1);
+    blk_mul<T, K, MCT, 9>(gt, nullptr, T(1), z, acc);
+    if (ym) {
+      put_y(b, 0, z);
+      if (!last) {
+        V zz[W::RT][MCT];
+        zero_strip<T, K, MCT>(zz);
+        put_y(b, K, zz);
+      }
+    }
+    if (last) {
+      T up[NF];
+      load_frags<T, K>(up, fac + (size_t)b * L.rec + K * K);
+      V wb[W::RT][MCT], bv[W::RT][MCT], zv[W::RT][MCT], vb[W::RT][MCT], vt[W::RT][MCT];
+      zero_strip<T, K, MCT>(wb);
+      blk_mul<T, K, MCT, 2>(up, nullptr, T(1), z, wb);
+      // V spike in the last block
+#pragma unroll
+      for (int t = 0; t < W::RT; ++t)
+#pragma unroll
+        for (int ct = 0; ct < MCT; ++ct)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int row = 16 * t + acc_row<T>(lane, v), col = 16 * ct + (lane & 15);
+            const int lr = b * K + row - g.pad;
+            bv[t][ct][v] = (j < L.p - 1 && lr >= 0) ? (T)band_at(a.bands, L.n, k, g.s + lr, g.s + g.nj + col) : T(0);
+          }
+      zero_strip<T, K, MCT>(zv);
+      blk_mul<T, K, MCT, 0>(lp, nullptr, T(1), bv, zv);
+      zero_strip<T, K, MCT>(vb);
+      blk_mul<T, K, MCT, 2>(up, nullptr, T(1), zv, vb);
+      zero_strip<T, K, MCT>(vt);
+      blk_mul<T, K, MCT, 9>(gt, nullptr, T(1), zv, vt);
+      if (ym) put_y(b, K, zv);
+      put(0, vt);
+      put(1, vb);
+      put(2, acc);
+      put(3, wb);
+    }
+#pragma unroll
+    for (int t = 0; t < W::RT; ++t)
+#pragma unroll
+      for (int ct = 0; ct < MCT; ++ct) w0[t][ct] = w1[t][ct];
+    if (b + 2 < g.nb)
+      rhs_w(b + 2, w1);  // only the first two blocks carry [C_j; 0]
+    else
+      zero_strip<T, K, MCT>(w1);
+    if (!last)
+#pragma unroll
+      for (int f = 0; f < NF; ++f) {
+        lp[f] = lpn[f];
+        gt[f] = gtn[f];
+      }
+  }
+}
+
+}  // namespace lrs

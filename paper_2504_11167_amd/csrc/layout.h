@@ -27,6 +27,7 @@ struct Layout {
   // solve vectors (double): y tips [p][2][K][mmax], compressed rhs [NI][R2][mmax],
   // scratch n x mmax (adjoint D-stage), refinement copy of f and residual n x mmax, norms
   size_t ytip, zg, scr, fcopy, res, norms;
+  size_t npv;    // int32[p]: partition needs the interchanging factorization
   size_t latch;  // int32[16]
   size_t total;
 };
@@ -94,6 +95,7 @@ inline void make_layout(Layout& L, int64_t n, int k, int p, int r, int tsize, in
   L.fcopy = take(tsize == 4 ? (size_t)n * mmax * 8 : 0);
   L.res = take(tsize == 4 ? (size_t)n * mmax * 8 : 0);  // residual / correction (refinement)
   L.norms = take((size_t)4 * mmax * 8 + 64);
+  L.npv = take((size_t)p * 4);
   L.latch = take(16 * 4);
   L.total = o;
 }
