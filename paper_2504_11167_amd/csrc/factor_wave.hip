@@ -114,7 +114,8 @@ __global__ __launch_bounds__(64) void factor_wave_kernel(FactorArgs a) {
   T* l21b = lds + F::oL21;
   T* prow = lds + F::oRow;
   const Layout& L = a.L;
-  const int j = blockIdx.x, lane = threadIdx.x & 63, k = L.k;
+  const int j = blockIdx.x, k = L.k;
+  int lane = threadIdx.x & 63;
   const Geom g = part_geom(L.n, L.p, j, K);
   const int nb = g.nb;
   T* fac = wsT<T>(a.ws, L.fac) + (size_t)j * L.nbmax * L.rec;
@@ -125,18 +126,37 @@ __global__ __launch_bounds__(64) void factor_wave_kernel(FactorArgs a) {
 
   // band slab of row block R: slab[(d + K) K + i] = A(R K + i, R K + i + d)
   // (partition-local, identity on the virtual rows, zero outside)
+  // (loads issued in groups of SG before their LDS stores, so that the
+  // latency is paid once per group rather than once per element)
   auto slab_load = [&](int R) {
-    for (int o = lane; o < (2 * k + 1) * K; o += 64) {
-      const int d = o / K - k, i = o % K;
-      const int lr = R * K + i - g.pad;
-      T v = T(0);
-      if (lr < 0) {
-        v = (d == 0) ? T(1) : T(0);
-      } else if (lr < g.nj) {
-        const int lc = lr + d;
-        if (lc >= 0 && lc < g.nj) v = (T)a.bands[(int64_t)(d + k) * L.n + g.s + lr];
+    constexpr int NS = ((2 * K + 1) * K + 63) / 64, SG = NS < 17 ? NS : 17;
+    // the lane index made opaque: the per-element offsets are cheap to
+    // recompute, and hoisting them out of the block loop only spills them
+    int ln = lane;
+    asm volatile("" : "+v"(ln));
+    for (int it0 = 0; it0 < NS; it0 += SG) {
+      T v[SG];
+#pragma unroll
+      for (int u = 0; u < SG; ++u) {
+        const int o = ln + 64 * (it0 + u);
+        const int d = o / K - k, i = o % K;
+        const int lr = R * K + i - g.pad;
+        T x = T(0);
+        if (o < (2 * k + 1) * K) {
+          if (lr < 0) {
+            x = (d == 0) ? T(1) : T(0);
+          } else if (lr < g.nj) {
+            const int lc = lr + d;
+            if (lc >= 0 && lc < g.nj) x = (T)a.bands[(int64_t)(d + k) * L.n + g.s + lr];
+          }
+        }
+        v[u] = x;
       }
-      slab[(d + K) * K + i] = v;
+#pragma unroll
+      for (int u = 0; u < SG; ++u) {
+        const int o = ln + 64 * (it0 + u);
+        if (o < (2 * k + 1) * K) slab[o + (K - k) * K] = v[u];
+      }
     }
   };
   auto sl = [&](int i, int d) -> T { return (d >= -K && d <= K) ? slab[(d + K) * K + i] : T(0); };
@@ -193,6 +213,7 @@ __global__ __launch_bounds__(64) void factor_wave_kernel(FactorArgs a) {
   for (int b = 0; b < nb; ++b) {
     const bool last = (b == nb - 1);
     const int nr = last ? K : 2 * K;
+    asm volatile("" : "+v"(lane));  // (same: no lane-derived values kept across blocks)
     // ---- panel [Dc_b; Lo_{b+1}]: lane i < K takes row i of Dc_b (lib), lane K + i
     // row i of Lo_{b+1} (slab)
     {
@@ -316,7 +337,8 @@ __global__ __launch_bounds__(64) void spike_wave_kernel(FactorArgs a) {
   using V = typename W::V;
   constexpr int NF = W::RT * W::KS;
   const Layout& L = a.L;
-  const int j = blockIdx.x, lane = threadIdx.x & 63, k = L.k;
+  const int j = blockIdx.x, k = L.k;
+  int lane = threadIdx.x & 63;
   if (wsT<int>(a.ws, L.npv)[j]) return;
   const Geom g = part_geom(L.n, L.p, j, K);
   const T* fac = wsT<T>(a.ws, L.fac) + (size_t)j * L.nbmax * L.rec;
@@ -369,6 +391,7 @@ __global__ __launch_bounds__(64) void spike_wave_kernel(FactorArgs a) {
   load_frags<T, K>(gt, gm);
   for (int b = 0; b < g.nb; ++b) {
     const bool last = (b == g.nb - 1);
+    asm volatile("" : "+v"(lane));  // no lane-derived values kept across blocks
     if (!last) {
       load_frags<T, K>(lpn, fac + (size_t)(b + 1) * L.rec);
       load_frags<T, K>(gtn, gm + (size_t)(b + 1) * K * K);
