@@ -9,10 +9,15 @@ recovery).  Workload: n = 2^22, half-bandwidth k = 32, p = 1024 partitions
 
 Prints ONE JSON line.  `value` is rows x RHS per second of the whole step;
 `roofline` reports the dominant kernel's algorithmic bytes per launch over
-its average HIP-event duration in the timed region, against 8 TB/s;
-`cpu_baseline` times the CPU oracle on a bounded sample of the same workload.
+its average HIP-event duration in the timed region, against 8 TB/s, and the
+HBM bytes that kernel moved according to the PMC counters recorded under
+profiles/ (null when the kernel sources changed since they were taken);
+`refined_vs_fp64` times FP32 factors with FP64 refinement against plain FP64
+at r = k on the same matrix; `cpu_baseline` times the CPU oracle on a bounded
+sample of the same workload.
 """
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -28,13 +33,15 @@ HBM_PEAK_GBS = 8000.0
 def algorithmic_bytes(kernel, n, k, m, r, wf):
     """Bytes per launch the method itself must move (spikes streamed, never stored whole).
 
-    Per row: factor = read band 8(2k+1) + write LU wf(2k+1) + [r < k] W forward
-    intermediate written wf k (pass 1) and read back with U re-read wf(k+1) + wf k
-    (pass 2); solve = one sweep pair per stage over the factors wf(2k+1), plus
-    f read (D-stage) and f read + x written (recovery).
+    Per row: LU = read band 8(2k+1) + write LU wf(2k+1) + write the top-tip
+    operator G wf k; spike forward = read L wf k and G wf k, write the W forward
+    intermediate wf k when r < k; back-sweeps = read U wf(k+1) and the
+    intermediate wf k; solve = one sweep pair per stage over the factors
+    wf(2k+1), plus f read (D-stage) and f read + x written (recovery).
     """
     per_row = {
-        "factor_pass1": 8 * (2 * k + 1) + wf * (2 * k + 1) + (wf * k if r < k else 0),
+        "factor_pass1": 8 * (2 * k + 1) + wf * (2 * k + 1) + wf * k,
+        "spike_fwd": 2 * wf * k + (wf * k if r < k else 0),
         "factor_pass2": wf * (k + 1) + wf * k,
         "dstage_kernel": wf * (2 * k + 1) + 8 * m,
         "retrieve_kernel": wf * (2 * k + 1) + 16 * m,
@@ -42,11 +49,92 @@ def algorithmic_bytes(kernel, n, k, m, r, wf):
     return None if per_row is None else per_row * n
 
 
+def source_digest():
+    """SHA-256 over the HIP sources and the header (identifies the kernels the counters were taken on)."""
+    import paper_2504_11167_amd.build as b
+    h = hashlib.sha256()
+    for d in sorted(b.DEPS):
+        with open(os.path.join(b.CSRC, d), "rb") as fh:
+            h.update(d.encode() + fh.read())
+    return h.hexdigest()[:16]
+
+
+def counter_traffic(kernel, workload):
+    """HBM bytes per launch of `kernel` from profiles/traffic_*.json, if taken on the current sources."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{kernel}_{workload}.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        rec = json.load(fh)
+    if rec.get("sources") != source_digest():
+        return None
+    return rec.get("traffic_bytes")
+
+
+def rel_err(a, b):
+    import torch
+    num = torch.linalg.vector_norm(a - b, dim=0)
+    den = torch.linalg.vector_norm(b, dim=0).clamp_min(1e-300)
+    return float((num / den).max())
+
+
+def rel_residual(bands, x, f):
+    """max_c ||f_c - A x_c|| / ||f_c|| with torch ops (a diagnostic outside the timed region)."""
+    import torch
+    k = (bands.shape[0] - 1) // 2
+    n = bands.shape[1]
+    ax = torch.zeros_like(x)
+    for d in range(-k, k + 1):
+        lo, hi = max(0, -d), min(n, n - d)
+        ax[lo:hi] += bands[d + k, lo:hi, None] * x[lo + d:hi + d]
+    num = torch.linalg.vector_norm(f - ax, dim=0)
+    return float((num / torch.linalg.vector_norm(f, dim=0)).max())
+
+
+def refined_vs_fp64(lr, bands, f, x, ws_bytes_fn, p, steps, log):
+    """Plain FP64 and FP32-factor + FP64-refinement LR-SPIKE at r = k on the same
+    matrix and right-hand sides: whole factor + solve time each, and the accuracy
+    both reach (difference between the two results and relative residuals)."""
+    import torch
+    k = (bands.shape[0] - 1) // 2
+    m = f.shape[1]
+    out = {"r": k}
+    xs = {}
+    for prec in ("fp64", "fp32_refined"):
+        ws = torch.empty(ws_bytes_fn(prec), dtype=torch.uint8, device=bands.device)
+        y = torch.empty_like(f)
+
+        def once():
+            y.copy_(f)
+            plan = lr.Plan(bands, p, k, precision=prec, max_nrhs=m, workspace=ws)
+            plan.solve(y, inplace=True)
+            return plan
+
+        once().status()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(steps):
+            plan = once()
+        e1.record()
+        torch.cuda.synchronize()
+        info = plan.status()
+        ms = e0.elapsed_time(e1) / steps
+        xs[prec] = y.clone()
+        out[prec] = {"ms_per_step": round(ms, 4), "rows_rhs_per_s": f.shape[0] * m / (ms * 1e-3),
+                     "refine_iters": info["refine_iters"], "rel_residual": rel_residual(bands, y, f)}
+        log(f"[bench] r=k {prec}: {ms:.3f} ms/step, iters {info['refine_iters']}")
+        del ws, plan
+    out["rel_diff_refined_vs_fp64"] = rel_err(xs["fp32_refined"], xs["fp64"])
+    out["time_ratio_fp64_over_refined"] = out["fp64"]["ms_per_step"] / out["fp32_refined"]["ms_per_step"]
+    return out
+
+
 def cpu_baseline(k, r, m, seconds_hint=True):
     import numpy as np
     import oracle
     import synth
-    n_s, p_s = 1 << 20, 256  # a quarter of the rows: 256 partitions of 4096 rows
+    n_s, p_s = 1 << 22, 1024  # the whole workload (about 10 s on 16 host threads)
     bands, f = synth.make_problem(n_s, k, m, seed=1, rule="weak")
     threads = min(16, os.cpu_count() or 1)
     t = time.perf_counter()
@@ -54,7 +142,7 @@ def cpu_baseline(k, r, m, seconds_hint=True):
     dt = time.perf_counter() - t
     del bands, f
     return {"value": n_s * m / dt, "unit": "rows*rhs/s", "cores": threads, "kind": "oracle",
-            "sample": f"n={n_s} (256 partitions of 4096 rows), k={k}, r={r}, {m} RHS, weak dominance, "
+            "sample": f"n={n_s} ({p_s} partitions of {n_s // p_s} rows), k={k}, r={r}, {m} RHS, weak dominance, "
                       f"factor+solve in one oracle call, {dt:.1f} s wall"}
 
 
@@ -66,6 +154,7 @@ def main():
     ap.add_argument("--r", type=int, default=8)
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32_refined"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-refined", action="store_true", help="skip the refined-FP32 vs FP64 comparison")
     ap.add_argument("--quiet", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -142,9 +231,16 @@ def main():
     avg_ms = tot_ms / cnt
     abytes = algorithmic_bytes(name, n, k, m, r, wf)
     achieved = abytes / (avg_ms * 1e-3) / 1e9
+    wl = f"n{n}_k{k}_p{p}_r{r}_m{m}_{args.precision}"
     roof = {"bound": "hbm", "kernel": name, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": counter_traffic(name, wl),
             "algorithmic_bytes_per_launch": abytes, "avg_launch_ms": round(avg_ms, 4)}
+
+    comp = None
+    if not args.no_refined and args.precision == "fp64":
+        del plan, ws
+        comp = refined_vs_fp64(lr, bands, f, x, lambda prec: lr.workspace_bytes(n, k, p, k, prec, m), p,
+                               max(2, args.steps // 2), log)
 
     cpu = None if args.no_cpu_baseline else cpu_baseline(k, r, m)
     out = {
@@ -165,6 +261,7 @@ def main():
         "roofline": roof,
         "cpu_baseline": cpu,
         "solve_only": {"ms": round(ms_solve, 4), "rows_rhs_per_s": n * m / (ms_solve * 1e-3)},
+        "refined_vs_fp64": comp,
         "kernels_ms_per_step": {kk: round(v[0] / args.steps, 4) for kk, v in sorted(kern.items(), key=lambda kv: -kv[1][0])},
         "swapped_blocks": info["swapped_blocks"],
     }
