@@ -63,7 +63,10 @@ enum {
 typedef struct {
   int32_t precision;     /* LRSPIKE_FP64 (default) or LRSPIKE_FP32_REFINED */
   int32_t max_refine;    /* FP32_REFINED: max corrections (default 30) */
-  double refine_tol;     /* FP32_REFINED: stop when ||d_c||_2 <= tol ||x_c||_2 for all columns (default 1e-13) */
+  double refine_tol;     /* FP32_REFINED: stop when ||d_c||_2 <= tol ||x_c||_2 for all columns (default 1e-13).
+                            A correction that shrinks by less than half ends the iteration: converged if
+                            it is already <= 100 tol (the rounding level of an ill-conditioned system),
+                            else NOT_CONVERGED is latched */
   void *stream;          /* hipStream_t to enqueue on; NULL = null stream */
   void *workspace;       /* device memory of >= lrspike_workspace_size bytes, caller-owned,
                             must outlive the plan */

@@ -47,36 +47,38 @@ __global__ void zero_kernel(int* p, int n) {
   if (i < n) p[i] = 0;
 }
 
-__global__ void axpy_kernel(double* x, const double* d, int64_t n) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) x[i] += d[i];
-}
-
-// per-column squared norms of x and d (rows strided by ld), accumulated by atomics
-__global__ void colnorm_kernel(const double* x, const double* d, int64_t n, int m, int ld,
-                               double* out) {
-  extern __shared__ double red[];
-  int c = blockIdx.y;
-  double sx = 0.0, sd = 0.0;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-    double xv = x[i * ld + c], dv = d[i * ld + c];
-    sx += xv * xv;
-    sd += dv * dv;
-  }
-  red[threadIdx.x] = sx;
-  red[blockDim.x + threadIdx.x] = sd;
+// x += d over `total` elements of an n x m row-major block, and the per-column
+// squared norms of the new x and of d added into out[2c], out[2c+1].  When
+// the grid stride is a multiple of m every thread stays in one column and
+// accumulates in registers; otherwise each element goes to an LDS atomic.
+__global__ void axpy_norms_kernel(double* x, const double* d, int64_t total, int m, double* out) {
+  extern __shared__ double red[];  // 2m
+  for (int c = threadIdx.x; c < 2 * m; c += blockDim.x) red[c] = 0.0;
   __syncthreads();
-  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
-    if ((int)threadIdx.x < s) {
-      red[threadIdx.x] += red[threadIdx.x + s];
-      red[blockDim.x + threadIdx.x] += red[blockDim.x + threadIdx.x + s];
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  const bool fixed = (stride % m) == 0;
+  double sx = 0.0, sd = 0.0;
+  int cfix = -1;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += stride) {
+    const double dv = d[e], xv = x[e] + dv;
+    x[e] = xv;
+    if (fixed) {
+      sx = fma(xv, xv, sx);
+      sd = fma(dv, dv, sd);
+      cfix = (int)(e % m);
+    } else {
+      const int c = (int)(e % m);
+      atomicAdd(&red[2 * c], xv * xv);
+      atomicAdd(&red[2 * c + 1], dv * dv);
     }
-    __syncthreads();
   }
-  if (threadIdx.x == 0) {
-    atomicAdd(out + 2 * c, red[0]);
-    atomicAdd(out + 2 * c + 1, red[blockDim.x]);
+  if (cfix >= 0) {
+    atomicAdd(&red[2 * cfix], sx);
+    atomicAdd(&red[2 * cfix + 1], sd);
   }
+  __syncthreads();
+  for (int c = threadIdx.x; c < 2 * m; c += blockDim.x)
+    if (red[c] != 0.0) atomicAdd(out + c, red[c]);
 }
 
 __global__ void zero_d_kernel(double* p, int n) {
@@ -170,15 +172,16 @@ int run_factor(lrspike_plan P) {
   if (L.NI > 0 && L.r > 0) {
     LRS_LAUNCH("zassemble_kernel", zassemble_kernel<K>, dim3(L.NI), dim3(256), 0, ra);
     const int R2 = L.R2;
-    size_t bodd = (size_t)(R2 * (R2 + 1) + R2 * (3 * R2 + 1)) * 8;
-    if (!set_lds((const void*)cr_odd_kernel, bodd)) return LRSPIKE_ERR_NOT_SUPPORTED;
+    const size_t bodd = (size_t)(R2 * (2 * R2 + 1) + 3 * R2) * 8, beven = (size_t)2 * R2 * (R2 + 1) * 8;
+    if (!set_lds((const void*)cr_odd_kernel, bodd) || !set_lds((const void*)cr_even_kernel, beven))
+      return LRSPIKE_ERR_NOT_SUPPORTED;
     for (int l = 0; l < L.levels; ++l) {
       int s = 1 << l;
       int nodd = (L.NI + s - 1) / (2 * s);  // rows (2q+1)s < NI
       ra.level = l;
       if (nodd > 0) LRS_LAUNCH("cr_odd_kernel", cr_odd_kernel, dim3(nodd), dim3(LRS_NT), bodd, ra);
       int neven = (L.NI + 2 * s - 1) / (2 * s);
-      LRS_LAUNCH("cr_even_kernel", cr_even_kernel, dim3(neven), dim3(LRS_NT), 0, ra);
+      LRS_LAUNCH("cr_even_kernel", cr_even_kernel, dim3(neven), dim3(LRS_NT), beven, ra);
       }
     ra.level = L.levels;
     LRS_LAUNCH("cr_odd_kernel", cr_odd_kernel, dim3(1), dim3(LRS_NT), bodd, ra);
@@ -196,21 +199,23 @@ int run_reduced(lrspike_plan P, int m, int transpose) {
   size_t bz = (size_t)4 * K * m * 8;
   if (!set_lds((const void*)zrhs_kernel<K>, bz)) return LRSPIKE_ERR_NOT_SUPPORTED;
   LRS_LAUNCH("zrhs_kernel", zrhs_kernel<K>, dim3(L.NI), dim3(256), bz, ra, P->bands);
-  const int R2 = L.R2;
-  size_t bf = 0, bb = (size_t)R2 * m * 8;
+  const int R2 = L.R2, mc = m < CRS_MC ? m : CRS_MC, nch = (m + CRS_MC - 1) / CRS_MC;
+  const size_t bs = (size_t)(R2 * (R2 + 1) + R2 * (mc + 1) + R2 * mc) * 8;
+  if (!set_lds((const void*)crs_forward_kernel, bs) || !set_lds((const void*)crs_backward_kernel, bs))
+    return LRSPIKE_ERR_NOT_SUPPORTED;
   for (int l = 0; l < L.levels; ++l) {
     int s = 1 << l;
     ra.level = l;
     int neven = (L.NI + 2 * s - 1) / (2 * s);
-    LRS_LAUNCH("crs_forward_kernel", crs_forward_kernel, dim3(neven), dim3(LRS_NT), bf, ra);
+    LRS_LAUNCH("crs_forward_kernel", crs_forward_kernel, dim3(neven, nch), dim3(LRS_NT), bs, ra);
   }
   ra.level = L.levels;
-  LRS_LAUNCH("crs_backward_kernel", crs_backward_kernel, dim3(1), dim3(LRS_NT), bb, ra);
+  LRS_LAUNCH("crs_backward_kernel", crs_backward_kernel, dim3(1, nch), dim3(LRS_NT), bs, ra);
   for (int l = L.levels - 1; l >= 0; --l) {
     int s = 1 << l;
     ra.level = l;
     int nodd = (L.NI + s - 1) / (2 * s);
-    if (nodd > 0) LRS_LAUNCH("crs_backward_kernel", crs_backward_kernel, dim3(nodd), dim3(LRS_NT), bb, ra);
+    if (nodd > 0) LRS_LAUNCH("crs_backward_kernel", crs_backward_kernel, dim3(nodd, nch), dim3(LRS_NT), bs, ra);
   }
   return 0;
 }
@@ -281,13 +286,15 @@ int run_refined(lrspike_plan P, double* rhs, int m, int transpose) {
   P->refine_iters = 0;
   P->last_corr = INFINITY;
   double prev = INFINITY;
+  const size_t bres = (size_t)(RES_ROWS + 2 * L.k) * (RES_MC + 2) * 8;
+  if (!set_lds((const void*)residual_kernel, bres)) return LRSPIKE_ERR_NOT_SUPPORTED;
   for (int it = 0; it < P->max_refine; ++it) {
-    int blocks = (int)((nm + 255) / 256);
-    LRS_LAUNCH("residual_kernel", residual_kernel, dim3(blocks), dim3(256), 0, P->bands, L.n, L.k, fcopy, rhs, scr, m, m, transpose);
+    LRS_LAUNCH("residual_kernel", residual_kernel, dim3((unsigned)((L.n + RES_ROWS - 1) / RES_ROWS)), dim3(RES_ROWS),
+               bres, P->bands, L.n, L.k, fcopy, rhs, scr, m, m, transpose);
     if ((rc = run_apply<T, K>(P, scr, m, transpose))) return rc;
-    LRS_LAUNCH("axpy_kernel", axpy_kernel, dim3(blocks), dim3(256), 0, rhs, scr, nm);
     LRS_LAUNCH("zero_d_kernel", zero_d_kernel, dim3(1), dim3(256), 0, norms, 2 * m);
-    LRS_LAUNCH("colnorm_kernel", colnorm_kernel, dim3(256, m), dim3(256), 2 * 256 * 8, rhs, scr, L.n, m, m, norms);
+    LRS_LAUNCH("axpy_norms_kernel", axpy_norms_kernel, dim3(1024), dim3(256), (size_t)2 * m * 8, rhs, scr, nm, m,
+               norms);
     if (hipMemcpyAsync(hn.data(), norms, 2 * m * 8, hipMemcpyDeviceToHost, st) != hipSuccess) return LRSPIKE_ERR_HIP;
     if (hipStreamSynchronize(st) != hipSuccess) return LRSPIKE_ERR_HIP;
     double worst = 0.0;
@@ -299,7 +306,13 @@ int run_refined(lrspike_plan P, double* rhs, int m, int transpose) {
     P->refine_iters = it + 1;
     P->last_corr = worst;
     if (worst <= P->refine_tol) return 0;
-    if (!(worst < INFINITY) || (it > 0 && worst > 0.5 * prev)) break;
+    if (!(worst < INFINITY)) break;
+    if (it > 0 && worst > 0.5 * prev) {
+      // the corrections stopped shrinking: the rounding level of an
+      // ill-conditioned system when they are already small, else failure
+      if (worst <= 100.0 * P->refine_tol) return 0;
+      break;
+    }
     prev = worst;
   }
   int* latch = reinterpret_cast<int*>(P->ws + L.latch);
@@ -396,6 +409,8 @@ int lrspike_factor(int64_t n, int32_t k, const double* bands, int32_t p, int32_t
   if (opts->precision != LRSPIKE_FP64 && opts->precision != LRSPIKE_FP32_REFINED) return -6;
   if (opts->max_nrhs < 1) return -6;
   if (K > 32) return LRSPIKE_ERR_NOT_SUPPORTED;
+  // reduced-system blocks of order 2r are inverted in one workgroup's LDS
+  if (p > 1 && 2 * ((r == k) ? K : r) > 64) return LRSPIKE_ERR_NOT_SUPPORTED;
   lrspike_plan P = new lrspike_plan_s();
   make_layout(P->L, n, k, p, r, opts->precision == LRSPIKE_FP64 ? 8 : 4, opts->max_nrhs);
   if (!opts->workspace || opts->workspace_bytes < P->L.total || !is_device_ptr(opts->workspace)) {

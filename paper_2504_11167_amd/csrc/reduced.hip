@@ -225,222 +225,269 @@ __global__ void zassemble_kernel(RedArgs a) {
   }
 }
 
-// ------------------------------------------------------------------ small dense LU
-// Partial-pivoting LU of the R2 x R2 matrix M (LDS, pitch ld) by one workgroup.
-__device__ inline void dense_lu(double* M, int ld, int R2, int* piv, int* latch, int part) {
-  const int tid = threadIdx.x;
-  for (int c = 0; c < R2; ++c) {
-    if (tid == 0) {
-      int best = c;
-      double bv = fabs(M[c * ld + c]);
-      for (int i = c + 1; i < R2; ++i)
-        if (fabs(M[i * ld + c]) > bv) {
-          bv = fabs(M[i * ld + c]);
-          best = i;
-        }
-      piv[c] = best;
-      if (bv == 0.0) latch_error(latch, 2, part, c);
+// ------------------------------------------------------------------ block products
+// C (R x N) from sum_l a(i, l) b(l, j) over l < Kd, by one 256-thread
+// workgroup: every thread owns TS x TS register tiles of C; a and b read LDS.
+// `out(i, j, v)` receives each finished element.
+template <int TS, typename FA, typename FB, typename FO>
+__device__ inline void block_mm_ts(int R, int N, int Kd, FA a, FB b, FO out) {
+  const int ntj = (N + TS - 1) / TS, nt = ((R + TS - 1) / TS) * ntj;
+  for (int t = threadIdx.x; t < nt; t += blockDim.x) {
+    const int i0 = (t / ntj) * TS, j0 = (t % ntj) * TS;
+    double acc[TS][TS];
+#pragma unroll
+    for (int u = 0; u < TS; ++u)
+#pragma unroll
+      for (int v = 0; v < TS; ++v) acc[u][v] = 0.0;
+    for (int l = 0; l < Kd; ++l) {
+      double av[TS], bv[TS];
+#pragma unroll
+      for (int u = 0; u < TS; ++u) av[u] = (i0 + u < R) ? a(i0 + u, l) : 0.0;
+#pragma unroll
+      for (int v = 0; v < TS; ++v) bv[v] = (j0 + v < N) ? b(l, j0 + v) : 0.0;
+#pragma unroll
+      for (int u = 0; u < TS; ++u)
+#pragma unroll
+        for (int v = 0; v < TS; ++v) acc[u][v] = fma(av[u], bv[v], acc[u][v]);
     }
-    __syncthreads();
-    int pv = piv[c];
-    if (pv != c)
-      for (int col = tid; col < R2; col += blockDim.x) {
-        double t = M[c * ld + col];
-        M[c * ld + col] = M[pv * ld + col];
-        M[pv * ld + col] = t;
-      }
-    __syncthreads();
-    double d = M[c * ld + c];
-    for (int i = c + 1 + tid; i < R2; i += blockDim.x) M[i * ld + c] /= d;
-    __syncthreads();
-    int w = R2 - c - 1;
-    for (int o = tid; o < w * w; o += blockDim.x) {
-      int i = c + 1 + o / w, col = c + 1 + o % w;
-      M[i * ld + col] -= M[i * ld + c] * M[c * ld + col];
-    }
-    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < TS; ++u)
+#pragma unroll
+      for (int v = 0; v < TS; ++v)
+        if (i0 + u < R && j0 + v < N) out(i0 + u, j0 + v, acc[u][v]);
+  }
+}
+// register tile chosen so that the tiles cover about one workgroup
+template <typename FA, typename FB, typename FO>
+__device__ inline void block_mm(int R, int N, int Kd, FA a, FB b, FO out) {
+  const int rn = R * N;
+  if (rn <= 256)
+    block_mm_ts<1>(R, N, Kd, a, b, out);
+  else if (rn <= 1024)
+    block_mm_ts<2>(R, N, Kd, a, b, out);
+  else
+    block_mm_ts<4>(R, N, Kd, a, b, out);
+}
+
+// rows x cols block from global (row-major, pitch gl) into LDS (pitch pl); zero if src is null
+__device__ inline void stage(double* dst, int pl, const double* src, int gl, int rows, int cols) {
+  for (int o = threadIdx.x; o < rows * cols; o += blockDim.x) {
+    const int i = o / cols, j = o % cols;
+    dst[i * pl + j] = src ? src[(size_t)i * gl + j] : 0.0;
   }
 }
 
-// Solve (LU) X = B in place for B (R2 x nc, pitch ldb), LU in global or LDS.
-// transpose: solve (LU)^T-form, i.e. D^T X = B for D = P L U.
-// Columns are independent: one thread per column.
-__device__ inline void lu_solve_cols(const double* LU, int ld, const int* piv, int R2, double* B,
-                                     int ldb, int nc, bool transpose) {
-  for (int c = threadIdx.x; c < nc; c += blockDim.x) {
-    if (!transpose) {
-      for (int i = 0; i < R2; ++i) {
-        int pv = piv[i];
-        if (pv != i) {
-          double t = B[i * ldb + c];
-          B[i * ldb + c] = B[pv * ldb + c];
-          B[pv * ldb + c] = t;
+// In-place Gauss-Jordan inversion with partial pivoting (first maximum wins)
+// of the R x R left half of W = [D | I] (LDS, pitch pw = 2R + 1): on return
+// the right half holds D^{-1}.  colc (R) and rowc (2R) are LDS scratch.
+// Latches REDUCED_SINGULAR on an exactly zero pivot.  Needs R <= 64 and 256 threads.
+__device__ inline void gauss_jordan(double* W, int pw, int R, double* colc, double* rowc, int* s_piv,
+                                    int* latch, int part) {
+  const int tid = threadIdx.x, lane = tid & 63;
+  for (int c = 0; c < R; ++c) {
+    if (tid < 64) {  // one wave finds the pivot row
+      double bv = -1.0;
+      int bi = R;
+      for (int i = c + lane; i < R; i += 64) {
+        const double v = fabs(W[i * pw + c]);
+        if (v > bv) {
+          bv = v;
+          bi = i;
         }
       }
-      for (int i = 0; i < R2; ++i) {
-        double s = B[i * ldb + c];
-        for (int l = 0; l < i; ++l) s -= LU[i * ld + l] * B[l * ldb + c];
-        B[i * ldb + c] = s;
-      }
-      for (int i = R2 - 1; i >= 0; --i) {
-        double s = B[i * ldb + c];
-        for (int l = i + 1; l < R2; ++l) s -= LU[i * ld + l] * B[l * ldb + c];
-        B[i * ldb + c] = s / LU[i * ld + i];
-      }
-    } else {
-      for (int i = 0; i < R2; ++i) {  // U^T y = b
-        double s = B[i * ldb + c];
-        for (int l = 0; l < i; ++l) s -= LU[l * ld + i] * B[l * ldb + c];
-        B[i * ldb + c] = s / LU[i * ld + i];
-      }
-      for (int i = R2 - 1; i >= 0; --i) {  // L^T w = y
-        double s = B[i * ldb + c];
-        for (int l = i + 1; l < R2; ++l) s -= LU[l * ld + i] * B[l * ldb + c];
-        B[i * ldb + c] = s;
-      }
-      for (int i = R2 - 1; i >= 0; --i) {
-        int pv = piv[i];
-        if (pv != i) {
-          double t = B[i * ldb + c];
-          B[i * ldb + c] = B[pv * ldb + c];
-          B[pv * ldb + c] = t;
+      for (int off = 32; off > 0; off >>= 1) {
+        const double ov = __shfl_xor(bv, off, 64);
+        const int oi = __shfl_xor(bi, off, 64);
+        if (ov > bv || (ov == bv && oi < bi)) {
+          bv = ov;
+          bi = oi;
         }
+      }
+      if (lane == 0) {
+        *s_piv = bi;
+        if (!(bv > 0.0)) latch_error(latch, 2, part, c);
       }
     }
+    __syncthreads();
+    const int pv = *s_piv;
+    if (pv != c && pv < R)
+      for (int j = tid; j < 2 * R; j += blockDim.x) {
+        const double t = W[c * pw + j];
+        W[c * pw + j] = W[pv * pw + j];
+        W[pv * pw + j] = t;
+      }
+    __syncthreads();
+    const double inv = 1.0 / W[c * pw + c];
+    for (int i = tid; i < R; i += blockDim.x) colc[i] = W[i * pw + c];
+    for (int j = tid; j < 2 * R; j += blockDim.x) rowc[j] = W[c * pw + j] * inv;
+    __syncthreads();
+    // columns that still matter: c+1 .. R-1 of the left half, all of the right
+    // half; a thread keeps its columns (tid mod 64) and rows tid/64 + 4q, whose
+    // entries are all loaded before any is stored (R <= 64, 256 threads)
+    const int wl = R - c - 1, w = wl + R, i0 = tid >> 6;
+    double cc[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) cc[q] = (i0 + 4 * q < R) ? colc[i0 + 4 * q] : 0.0;
+    for (int jj = lane; jj < w; jj += 64) {
+      const int j = jj < wl ? c + 1 + jj : R + (jj - wl);
+      const double rj = rowc[j];
+      double wv[16];
+#pragma unroll
+      for (int q = 0; q < 16; ++q) wv[q] = (i0 + 4 * q < R) ? W[(i0 + 4 * q) * pw + j] : 0.0;
+#pragma unroll
+      for (int q = 0; q < 16; ++q) {
+        const int i = i0 + 4 * q;
+        if (i < R) W[i * pw + j] = (i == c) ? rj : fma(-cc[q], rj, wv[q]);
+      }
+    }
+    __syncthreads();
   }
 }
 
 // ------------------------------------------------------------------ CR factorization
 // Level l (stride s = 2^l), active rows i = 0, s, 2s, ... < NI.
-// Odd rows (i/s odd) are eliminated: Dinv_i = D_i^{-1} (partial-pivoting LU,
-// then solves against the identity), X^F_i = Dinv_i F_i, X^E_i = Dinv_i E_i
-// replace (F_i, E_i) in the row's level slot.  Even rows survive:
+// Odd rows (i/s odd) are eliminated: Dinv_i = D_i^{-1} (Gauss-Jordan with
+// partial pivoting), X^F_i = Dinv_i F_i, X^E_i = Dinv_i E_i replace (F_i, E_i)
+// in the row's level slot.  Even rows survive:
 //   D_i -= F_i X^E_{i-s} + E_i X^F_{i+s},  F_i' = -F_i X^F_{i-s},  E_i' = -E_i X^E_{i+s},
 // and their level slot is overwritten by M^F_i = F_i Dinv_{i-s}, M^E_i = E_i Dinv_{i+s}.
 // With these the four solves (Z, Z^T, forward and back substitution) are
 // products of small dense blocks only.
+// LDS: W = R2 x (2 R2 + 1), then column and row scratch (3 R2).
 __global__ __launch_bounds__(LRS_NT) void cr_odd_kernel(RedArgs a) {
   extern __shared__ __align__(16) unsigned char lds_raw[];
-  double* M = reinterpret_cast<double*>(lds_raw);
-  __shared__ int piv[128];
+  double* W = reinterpret_cast<double*>(lds_raw);
+  __shared__ int s_piv;
   const Layout& L = a.L;
-  const int R2 = L.R2, s = 1 << a.level;
+  const int R = L.R2, s = 1 << a.level, pw = 2 * R + 1;
   const bool top = a.level >= L.levels;
   const int i = top ? 0 : (2 * blockIdx.x + 1) * s;
   if (i >= L.NI) return;
-  const int ld = R2 + 1, ldx = 3 * R2 + 1;
-  double* X = M + R2 * ld;
-  int* latch = rws<int>(a.ws, L.latch);
-  const double* D = rws<double>(a.ws, L.zD) + (size_t)i * R2 * R2;
-  for (int o = threadIdx.x; o < R2 * R2; o += blockDim.x) M[o / R2 * ld + o % R2] = D[o];
-  double* FE = top ? nullptr : rws<double>(a.ws, L.zFE) + (size_t)(L.lvl_off[a.level] + i / s) * 2 * R2 * R2;
-  // right-hand sides [I | F | E]
-  for (int o = threadIdx.x; o < R2 * 3 * R2; o += blockDim.x) {
-    int row = o / (3 * R2), col = o % (3 * R2);
-    double v;
-    if (col < R2)
-      v = (row == col) ? 1.0 : 0.0;
-    else if (top)
-      v = 0.0;
-    else
-      v = FE[(col < 2 * R2 ? 0 : R2 * R2) + row * R2 + (col < 2 * R2 ? col - R2 : col - 2 * R2)];
-    X[row * ldx + col] = v;
+  double* colc = W + R * pw;
+  double* rowc = colc + R;
+  const double* D = rws<double>(a.ws, L.zD) + (size_t)i * R * R;
+  for (int o = threadIdx.x; o < R * 2 * R; o += blockDim.x) {
+    const int row = o / (2 * R), col = o % (2 * R);
+    W[row * pw + col] = col < R ? D[row * R + col] : (col - R == row ? 1.0 : 0.0);
   }
   __syncthreads();
-  dense_lu(M, ld, R2, piv, latch, i);
-  lu_solve_cols(M, ld, piv, R2, X, ldx, top ? R2 : 3 * R2, false);
-  __syncthreads();
-  double* Dinv = rws<double>(a.ws, L.zLU) + (size_t)i * R2 * R2;
-  for (int o = threadIdx.x; o < R2 * R2; o += blockDim.x) Dinv[o] = X[o / R2 * ldx + o % R2];
+  gauss_jordan(W, pw, R, colc, rowc, &s_piv, rws<int>(a.ws, L.latch), i);
+  double* Dinv = rws<double>(a.ws, L.zLU) + (size_t)i * R * R;
+  for (int o = threadIdx.x; o < R * R; o += blockDim.x) Dinv[o] = W[(o / R) * pw + R + o % R];
   if (top) return;
-  for (int o = threadIdx.x; o < 2 * R2 * R2; o += blockDim.x) {
-    int which = o / (R2 * R2), e = o % (R2 * R2), row = e / R2, col = e % R2;
-    FE[o] = X[row * ldx + R2 + which * R2 + col];  // [X^F | X^E]
+  double* FE = rws<double>(a.ws, L.zFE) + (size_t)(L.lvl_off[a.level] + i / s) * 2 * R * R;
+  for (int which = 0; which < 2; ++which) {  // X^F = Dinv F, then X^E = Dinv E
+    double* slot = FE + which * R * R;
+    stage(W, pw, slot, R, R, R);  // into the (now free) left half
+    __syncthreads();
+    block_mm(R, R, R, [&](int r, int l) { return W[r * pw + R + l]; }, [&](int l, int c) { return W[l * pw + c]; },
+             [&](int r, int c, double v) { slot[r * R + c] = v; });
+    __syncthreads();
   }
 }
 
+// LDS: A and B blocks, R2 x (R2 + 1) each.
 __global__ __launch_bounds__(LRS_NT) void cr_even_kernel(RedArgs a) {
+  extern __shared__ __align__(16) unsigned char lds_raw[];
   const Layout& L = a.L;
-  const int R2 = L.R2, s = 1 << a.level;
+  const int R = L.R2, s = 1 << a.level, pl = R + 1;
   const int i = 2 * blockIdx.x * s;
   if (i >= L.NI) return;
+  double* A = reinterpret_cast<double*>(lds_raw);
+  double* B = A + R * pl;
   const bool hasL = i - s >= 0, hasR = i + s < L.NI;
-  double* D = rws<double>(a.ws, L.zD) + (size_t)i * R2 * R2;
-  double* FE = rws<double>(a.ws, L.zFE) + (size_t)(L.lvl_off[a.level] + i / s) * 2 * R2 * R2;
-  double* FEn = rws<double>(a.ws, L.zFE) + (size_t)(L.lvl_off[a.level + 1] + i / (2 * s)) * 2 * R2 * R2;
-  const double* F = FE;
-  const double* E = FE + R2 * R2;
-  auto slot = [&](int row) { return rws<double>(a.ws, L.zFE) + (size_t)(L.lvl_off[a.level] + row / s) * 2 * R2 * R2; };
-  const double* XL = hasL ? slot(i - s) : nullptr;  // [X^F | X^E] of row i - s
-  const double* XR = hasR ? slot(i + s) : nullptr;
-  const double* DL = hasL ? rws<double>(a.ws, L.zLU) + (size_t)(i - s) * R2 * R2 : nullptr;
-  const double* DR = hasR ? rws<double>(a.ws, L.zLU) + (size_t)(i + s) * R2 * R2 : nullptr;
-  // pass 1: next-level blocks and the new D (reads F, E); M^F, M^E staged in
-  // the row's scratch block until every thread is done reading F, E
-  double* MS = rws<double>(a.ws, L.zX) + (size_t)i * 2 * R2 * R2;
-  for (int o = threadIdx.x; o < R2 * R2; o += blockDim.x) {
-    int row = o / R2, col = o % R2;
-    double dd = 0.0, fn = 0.0, en = 0.0, mf = 0.0, me = 0.0;
-    for (int l = 0; l < R2; ++l) {
-      if (hasL) {
-        double fl = F[row * R2 + l];
-        dd += fl * XL[R2 * R2 + l * R2 + col];  // F X^E_{i-s}
-        fn += fl * XL[l * R2 + col];            // F X^F_{i-s}
-        mf += fl * DL[l * R2 + col];            // F Dinv_{i-s}
+  double* D = rws<double>(a.ws, L.zD) + (size_t)i * R * R;
+  double* FE = rws<double>(a.ws, L.zFE) + (size_t)(L.lvl_off[a.level] + i / s) * 2 * R * R;
+  double* FEn = rws<double>(a.ws, L.zFE) + (size_t)(L.lvl_off[a.level + 1] + i / (2 * s)) * 2 * R * R;
+  auto slot = [&](int row) { return rws<double>(a.ws, L.zFE) + (size_t)(L.lvl_off[a.level] + row / s) * 2 * R * R; };
+  auto dinv = [&](int row) { return rws<double>(a.ws, L.zLU) + (size_t)row * R * R; };
+  auto fa = [&](int r, int l) { return A[r * pl + l]; };
+  auto fb = [&](int l, int c) { return B[l * pl + c]; };
+  // side 0: A = F with the row i - s;  side 1: A = E with the row i + s
+  for (int side = 0; side < 2; ++side) {
+    const bool has = side == 0 ? hasL : hasR;
+    double* own = FE + side * R * R;  // F_i or E_i, replaced by M^F_i or M^E_i
+    double* nxt = FEn + side * R * R;
+    if (!has) {
+      for (int o = threadIdx.x; o < R * R; o += blockDim.x) {
+        own[o] = 0.0;
+        nxt[o] = 0.0;
       }
-      if (hasR) {
-        double el = E[row * R2 + l];
-        dd += el * XR[l * R2 + col];            // E X^F_{i+s}
-        en += el * XR[R2 * R2 + l * R2 + col];  // E X^E_{i+s}
-        me += el * DR[l * R2 + col];            // E Dinv_{i+s}
-      }
+      continue;
     }
-    D[o] -= dd;
-    FEn[o] = -fn;
-    FEn[R2 * R2 + o] = -en;
-    MS[o] = mf;
-    MS[R2 * R2 + o] = me;
+    const double* X = slot(side == 0 ? i - s : i + s);  // [X^F | X^E] of the neighbour
+    __syncthreads();
+    stage(A, pl, own, R, R, R);
+    stage(B, pl, X + (side == 0 ? R * R : 0), R, R, R);  // X^E_{i-s} or X^F_{i+s}
+    __syncthreads();
+    block_mm(R, R, R, fa, fb, [&](int r, int c, double v) { D[r * R + c] -= v; });
+    __syncthreads();
+    stage(B, pl, X + (side == 0 ? 0 : R * R), R, R, R);  // X^F_{i-s} or X^E_{i+s}
+    __syncthreads();
+    block_mm(R, R, R, fa, fb, [&](int r, int c, double v) { nxt[r * R + c] = -v; });
+    __syncthreads();
+    stage(B, pl, dinv(side == 0 ? i - s : i + s), R, R, R);
+    __syncthreads();
+    block_mm(R, R, R, fa, fb, [&](int r, int c, double v) { own[r * R + c] = v; });
   }
-  __syncthreads();
-  for (int o = threadIdx.x; o < 2 * R2 * R2; o += blockDim.x) FE[o] = MS[o];  // [M^F | M^E]
 }
 
 // ------------------------------------------------------------------ CR solves
-// g (compressed vectors, [NI][R2][mmax]) is solved in place.
+// g (compressed vectors, [NI][R2][mmax]) is solved in place, in chunks of up
+// to CRS_MC columns (grid y).  Every product stages its R2 x R2 block and the
+// R2 x mc vector block in LDS.
+// LDS: R2 x (R2 + 1) block, R2 x (mc + 1) vectors, R2 x mc own vector copy.
+#define CRS_MC 32
+struct CrsLds {
+  double *A, *G, *O;
+  int pa, pg;
+};
+__device__ inline CrsLds crs_lds(int R, int m) {
+  extern __shared__ __align__(16) unsigned char lds_raw[];
+  CrsLds c;
+  c.A = reinterpret_cast<double*>(lds_raw);
+  c.pa = R + 1;
+  c.G = c.A + R * c.pa;
+  c.pg = m + 1;
+  c.O = c.G + R * c.pg;
+  return c;
+}
+// out(i, c) op= op(Mblk) x gblk with op = transpose or not
+template <typename FO>
+__device__ inline void crs_product(const CrsLds& w, int R, int m, int mm, const double* Mblk, bool tr,
+                                   const double* gblk, FO out) {
+  __syncthreads();
+  stage(w.A, w.pa, Mblk, R, R, R);
+  stage(w.G, w.pg, gblk, mm, R, m);
+  __syncthreads();
+  if (tr)
+    block_mm(R, m, R, [&](int r, int l) { return w.A[l * w.pa + r]; }, [&](int l, int c) { return w.G[l * w.pg + c]; },
+             out);
+  else
+    block_mm(R, m, R, [&](int r, int l) { return w.A[r * w.pa + l]; }, [&](int l, int c) { return w.G[l * w.pg + c]; },
+             out);
+}
+
 // Forward reduction at level l, even rows:
 //   Z:    g_i -= M^F_i g_{i-s} + M^E_i g_{i+s}
 //   Z^T:  g_i -= (X^E_{i-s})^T g_{i-s} + (X^F_{i+s})^T g_{i+s}
 __global__ __launch_bounds__(LRS_NT) void crs_forward_kernel(RedArgs a) {
   const Layout& L = a.L;
-  const int R2 = L.R2, s = 1 << a.level, m = a.m, mm = L.mmax;
+  const int R = L.R2, s = 1 << a.level, c0 = blockIdx.y * CRS_MC, m = min(CRS_MC, a.m - c0), mm = L.mmax;
   const int i = 2 * blockIdx.x * s;
   if (i >= L.NI) return;
-  const bool hasL = i - s >= 0, hasR = i + s < L.NI;
-  double* g = rws<double>(a.ws, L.zg);
-  auto slot = [&](int row) { return rws<double>(a.ws, L.zFE) + (size_t)(L.lvl_off[a.level] + row / s) * 2 * R2 * R2; };
-  const double* own = slot(i);
-  for (int o = threadIdx.x; o < R2 * m; o += blockDim.x) {
-    int row = o / m, c = o % m;
-    double acc = 0.0;
-    if (hasL) {
-      const double* gl = g + (size_t)(i - s) * R2 * mm;
-      if (!a.transpose) {
-        for (int l = 0; l < R2; ++l) acc += own[row * R2 + l] * gl[l * mm + c];
-      } else {
-        const double* XE = slot(i - s) + R2 * R2;
-        for (int l = 0; l < R2; ++l) acc += XE[l * R2 + row] * gl[l * mm + c];
-      }
-    }
-    if (hasR) {
-      const double* gr = g + (size_t)(i + s) * R2 * mm;
-      if (!a.transpose) {
-        for (int l = 0; l < R2; ++l) acc += own[R2 * R2 + row * R2 + l] * gr[l * mm + c];
-      } else {
-        const double* XF = slot(i + s);
-        for (int l = 0; l < R2; ++l) acc += XF[l * R2 + row] * gr[l * mm + c];
-      }
-    }
-    g[((size_t)i * R2 + row) * mm + c] -= acc;
+  const CrsLds w = crs_lds(R, m);
+  double* g = rws<double>(a.ws, L.zg) + c0;
+  double* gi = g + (size_t)i * R * mm;
+  auto slot = [&](int row) { return rws<double>(a.ws, L.zFE) + (size_t)(L.lvl_off[a.level] + row / s) * 2 * R * R; };
+  auto sub = [&](int r, int c, double v) { gi[r * mm + c] -= v; };
+  if (i - s >= 0) {
+    const double* Mb = a.transpose ? slot(i - s) + R * R : slot(i);
+    crs_product(w, R, m, mm, Mb, a.transpose, g + (size_t)(i - s) * R * mm, sub);
+  }
+  if (i + s < L.NI) {
+    const double* Mb = a.transpose ? slot(i + s) : slot(i) + R * R;
+    crs_product(w, R, m, mm, Mb, a.transpose, g + (size_t)(i + s) * R * mm, sub);
   }
 }
 
@@ -448,45 +495,30 @@ __global__ __launch_bounds__(LRS_NT) void crs_forward_kernel(RedArgs a) {
 //   Z:    g_i = Dinv_i g_i - X^F_i g_{i-s} - X^E_i g_{i+s}
 //   Z^T:  g_i = Dinv_i^T g_i - (M^E_{i-s})^T g_{i-s} - (M^F_{i+s})^T g_{i+s}
 __global__ __launch_bounds__(LRS_NT) void crs_backward_kernel(RedArgs a) {
-  extern __shared__ __align__(16) unsigned char lds_raw[];
-  double* Tg = reinterpret_cast<double*>(lds_raw);
   const Layout& L = a.L;
-  const int R2 = L.R2, s = 1 << a.level, m = a.m, mm = L.mmax;
+  const int R = L.R2, s = 1 << a.level, c0 = blockIdx.y * CRS_MC, m = min(CRS_MC, a.m - c0), mm = L.mmax;
   const bool top = a.level >= L.levels;
   const int i = top ? 0 : (2 * blockIdx.x + 1) * s;
   if (i >= L.NI) return;
-  double* g = rws<double>(a.ws, L.zg);
-  auto slot = [&](int row) { return rws<double>(a.ws, L.zFE) + (size_t)(L.lvl_off[a.level] + row / s) * 2 * R2 * R2; };
+  const CrsLds w = crs_lds(R, m);
+  double* g = rws<double>(a.ws, L.zg) + c0;
+  double* gi = g + (size_t)i * R * mm;
+  auto slot = [&](int row) { return rws<double>(a.ws, L.zFE) + (size_t)(L.lvl_off[a.level] + row / s) * 2 * R * R; };
   const bool hasL = !top && i - s >= 0, hasR = !top && i + s < L.NI;
-  const double* Dinv = rws<double>(a.ws, L.zLU) + (size_t)i * R2 * R2;
-  for (int o = threadIdx.x; o < R2 * m; o += blockDim.x) Tg[o] = g[((size_t)i * R2 + o / m) * mm + o % m];
-  __syncthreads();
-  for (int o = threadIdx.x; o < R2 * m; o += blockDim.x) {
-    int row = o / m, c = o % m;
-    double v = 0.0;
-    for (int l = 0; l < R2; ++l) v += (a.transpose ? Dinv[l * R2 + row] : Dinv[row * R2 + l]) * Tg[l * m + c];
-    if (hasL) {
-      const double* gl = g + (size_t)(i - s) * R2 * mm;
-      if (!a.transpose) {
-        const double* XF = slot(i);
-        for (int l = 0; l < R2; ++l) v -= XF[row * R2 + l] * gl[l * mm + c];
-      } else {
-        const double* ME = slot(i - s) + R2 * R2;
-        for (int l = 0; l < R2; ++l) v -= ME[l * R2 + row] * gl[l * mm + c];
-      }
-    }
-    if (hasR) {
-      const double* gr = g + (size_t)(i + s) * R2 * mm;
-      if (!a.transpose) {
-        const double* XE = slot(i) + R2 * R2;
-        for (int l = 0; l < R2; ++l) v -= XE[row * R2 + l] * gr[l * mm + c];
-      } else {
-        const double* MF = slot(i + s);
-        for (int l = 0; l < R2; ++l) v -= MF[l * R2 + row] * gr[l * mm + c];
-      }
-    }
-    g[((size_t)i * R2 + row) * mm + c] = v;
+  // own vector first (it is overwritten by the first product)
+  crs_product(w, R, m, mm, rws<double>(a.ws, L.zLU) + (size_t)i * R * R, a.transpose, gi,
+              [&](int r, int c, double v) { w.O[r * m + c] = v; });
+  auto sub = [&](int r, int c, double v) { w.O[r * m + c] -= v; };
+  if (hasL) {
+    const double* Mb = a.transpose ? slot(i - s) + R * R : slot(i);
+    crs_product(w, R, m, mm, Mb, a.transpose, g + (size_t)(i - s) * R * mm, sub);
   }
+  if (hasR) {
+    const double* Mb = a.transpose ? slot(i + s) : slot(i) + R * R;
+    crs_product(w, R, m, mm, Mb, a.transpose, g + (size_t)(i + s) * R * mm, sub);
+  }
+  __syncthreads();
+  for (int o = threadIdx.x; o < R * m; o += blockDim.x) gi[(o / m) * mm + o % m] = w.O[o];
 }
 
 // ------------------------------------------------------------------ compressed rhs

@@ -491,22 +491,55 @@ __global__ __launch_bounds__(LRS_NT) void adj_retrieve_kernel(SolveArgs a) {
 
 // ---------------------------------------------------------------- FP64 band kernels
 
-// out = f - A x (FP64), or f - A^T x when transpose; rows distributed over the grid.
-__global__ void residual_kernel(const double* __restrict__ bands, int64_t n, int k,
-                                const double* __restrict__ f, const double* __restrict__ x,
-                                double* __restrict__ out, int ld, int m, int transpose) {
-  int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (gid >= n * (int64_t)m) return;
-  int64_t i = gid / m;
-  int c = (int)(gid % m);
-  double s = f[i * ld + c];
-  for (int d = -k; d <= k; ++d) {
-    int64_t jj = i + d;
-    if (jj < 0 || jj >= n) continue;
-    double aij = transpose ? bands[(int64_t)(-d + k) * n + jj] : bands[(int64_t)(d + k) * n + i];
-    s -= aij * x[jj * ld + c];
+// r = f - op(A) x (op(A) = A or A^T), FP64, for RES_ROWS rows per workgroup in
+// chunks of RES_MC columns: the x rows a block needs (RES_ROWS + 2k) are staged
+// in LDS once per chunk, each thread owns one row and the chunk's columns (every
+// band entry is read once, coalesced along the diagonal), and f and r pass
+// through LDS so that their global accesses are coalesced too.
+#define RES_ROWS 256
+#define RES_MC 16
+__global__ __launch_bounds__(RES_ROWS) void residual_kernel(const double* __restrict__ bands, int64_t n, int k,
+                                                            const double* __restrict__ f,
+                                                            const double* __restrict__ x,
+                                                            double* __restrict__ out, int ld, int m,
+                                                            int transpose) {
+  extern __shared__ double xs[];  // (RES_ROWS + 2k) x PX
+  constexpr int PX = RES_MC + 2;
+  const int t = threadIdx.x;
+  const int64_t i0 = (int64_t)blockIdx.x * RES_ROWS, i = i0 + t;
+  const int rows = RES_ROWS + 2 * k;
+  for (int c0 = 0; c0 < m; c0 += RES_MC) {
+    const int mc = min(RES_MC, m - c0);
+    __syncthreads();
+    for (int o = t; o < rows * mc; o += RES_ROWS) {
+      const int rr = o / mc, cc = o % mc;
+      const int64_t gi = i0 - k + rr;
+      xs[rr * PX + cc] = (gi >= 0 && gi < n) ? x[gi * ld + c0 + cc] : 0.0;
+    }
+    __syncthreads();
+    double acc[RES_MC];
+#pragma unroll
+    for (int cc = 0; cc < RES_MC; ++cc) acc[cc] = 0.0;
+    if (i < n) {
+      for (int d = -k; d <= k; ++d) {
+        const int64_t jj = i + d;
+        double a = 0.0;
+        if (jj >= 0 && jj < n) a = transpose ? bands[(int64_t)(-d + k) * n + jj] : bands[(int64_t)(d + k) * n + i];
+        const double* xr = xs + (t + d + k) * PX;
+#pragma unroll
+        for (int cc = 0; cc < RES_MC; ++cc) acc[cc] = fma(-a, xr[cc], acc[cc]);
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int cc = 0; cc < RES_MC; ++cc) xs[t * PX + cc] = acc[cc];
+    __syncthreads();
+    for (int o = t; o < RES_ROWS * mc; o += RES_ROWS) {
+      const int rr = o / mc, cc = o % mc;
+      const int64_t gi = i0 + rr;
+      if (gi < n) out[gi * ld + c0 + cc] = f[gi * ld + c0 + cc] + xs[rr * PX + cc];
+    }
   }
-  out[i * ld + c] = s;
 }
 
 // grad[(d+k) n + i] = - sum_c lam[i, c] x[i+d, c]

@@ -73,10 +73,11 @@ def test_adjoint_matches_oracle(gpu, n, k, p, r, m, rule):
     assert rel(x, ref) <= 1e-12
 
 
-@pytest.mark.parametrize("theta", [0.3, 0.15])
-def test_pivoting_nondominant(gpu, theta):
-    """Non-dominant matrices make the partition LUs interchange rows."""
-    n, k, p, m = 1200, 4, 3, 2
+@pytest.mark.parametrize("k,theta", [(4, 0.3), (4, 0.15), (16, 0.3), (32, 0.15), (32, 0.1)])
+def test_pivoting_nondominant(gpu, k, theta):
+    """Non-dominant matrices make the partition LUs interchange rows (for
+    k >= 16 every partition leaves the no-interchange kernel for the general one)."""
+    n, p, m = 1200 if k <= 16 else 2400, 3, 2
     bands, f = synth.make_problem(n, k, m, seed=3, rule="theta", theta=theta)
     x, info = run(gpu, bands, f, p, k)
     assert info["swapped_blocks"] > 0
@@ -187,3 +188,63 @@ def test_repeat_solves_reuse_factorization(gpu):
     x2 = plan.solve(to_dev(f)).cpu().numpy()
     assert rel(x1, ref) <= 1e-12
     assert np.array_equal(x1, x2)  # deterministic
+
+
+def test_mixed_interchange_partitions(gpu):
+    """Only partition 2 is non-dominant: it alone is refactored with
+    interchanges while the others keep the no-interchange factorization."""
+    n, k, p, m = 4096, 32, 4, 3
+    bands, f = synth.make_problem(n, k, m, seed=8, rule="weak")
+    lo, hi = 2 * n // p, 3 * n // p
+    off = np.abs(bands[:, lo:hi]).sum(axis=0) - np.abs(bands[k, lo:hi])
+    bands[k, lo:hi] = 0.1 * off
+    for r in (k, 8):
+        x, info = run(gpu, bands, f, p, r)
+        assert info["swapped_blocks"] > 0
+        ref = oracle.lrspike(bands, f, p, r)
+        assert rel(x, ref) <= 1e-11
+
+
+def _c2_problem(m):
+    import json
+    import os
+    with open(os.path.join(os.path.dirname(__file__), "golden", "c2_nondominant.json")) as fh:
+        c2 = json.load(fh)
+    bands, f = synth.make_problem(c2["n"], c2["k"], m, seed=c2["seed"], rule="theta", theta=c2["theta"])
+    return bands, f
+
+
+@pytest.mark.parametrize("r", [32, 28])
+def test_refined_nondominant_cond_1e6(gpu, r):
+    """FP32 factors + FP64 refinement on the non-dominant workload (condition
+    number ~3e5..3e6, theta from tests/golden/c2_nondominant.json) reach the
+    extended-precision reference within 1e-11."""
+    bands, f = _c2_problem(4)
+    x, info = run(gpu, bands, f, 16, r, precision="fp32_refined")
+    assert info["refine_iters"] >= 1
+    assert info["swapped_blocks"] > 0
+    assert rel(x, oracle.band_solve_refined(bands, f, steps=2)) <= 1e-11
+
+
+def test_refined_nondominant_low_rank_reports_failure(gpu):
+    """At r = 8 the truncated spikes of the non-dominant workload do not make a
+    contractive preconditioner: the refinement must stop and latch
+    NOT_CONVERGED rather than return a wrong answer silently."""
+    bands, f = _c2_problem(2)
+    plan = gpu.factor(to_dev(bands), 16, 8, precision="fp32_refined", max_nrhs=2)
+    plan.solve(to_dev(f))
+    with pytest.raises(gpu.LRSpikeError) as e:
+        plan.status()
+    assert e.value.code == 3
+    assert e.value.info["last_correction"] > 1e-6
+
+
+@pytest.mark.slow
+def test_full_size_large_workload(gpu):
+    """The benchmark configuration itself (n = 2^22, k = 32, p = 1024, r = 8,
+    16 right-hand sides, FP64), element by element against the oracle."""
+    n, k, p, r, m = 1 << 22, 32, 1024, 8, 16
+    bands, f = synth.make_problem(n, k, m, seed=0, rule="weak")
+    x, info = run(gpu, bands, f, p, r)
+    ref = oracle.lrspike(bands, f, p, r)
+    assert rel(x, ref) <= 1e-12
