@@ -160,8 +160,65 @@ int lrspike_profile(lrspike_plan plan, int32_t enable);
 int lrspike_profile_read(lrspike_plan plan, int32_t max, char *names, double *total_ms,
                          int32_t *launches, int32_t *count);
 
-/* Frees the host object (the workspace belongs to the caller). */
+/* Frees the host object (the workspace belongs to the caller; a batched
+ * plan also frees the device memory it allocated). */
 int lrspike_destroy(lrspike_plan plan);
+
+/*
+ * Batched independent systems: many banded systems of different orders,
+ * bandwidths and right-hand-side counts factored and solved together (the
+ * partitioned solve of section "SPIKE partitioning" applied to every system).
+ * Systems with equal (k, r) are solved as one LR-SPIKE problem over their
+ * concatenated band with a partition boundary at every system boundary: the
+ * coupling blocks across a system boundary are zero, so the reduced system
+ * splits into independent per-system blocks and every result equals that of
+ * the system's own plan with the same p.
+ */
+typedef struct {
+  int64_t n;            /* order, >= 1 */
+  int32_t k;            /* half-bandwidth, 1 <= k <= 32 */
+  int32_t p;            /* partitions (n / p >= max(2k, K), K = next power of two >= k);
+                           0 = chosen by the autotuner */
+  int32_t r;            /* retained rank, 0 <= r <= k (2r <= 64) */
+  int32_t nrhs;         /* right-hand-side columns, >= 1 */
+  int64_t band_offset;  /* element offset of the system's (2k+1) x n band-major band in bands_base */
+  int64_t rhs_offset;   /* element offset of its n x nrhs row-major right-hand sides in rhs_base */
+} lrspike_batch_desc;
+
+/*
+ * Factor every system.  descs: HOST array of count descriptors.  bands_base:
+ * device pointer, borrowed for the plan's lifetime (lrspike_run_batched
+ * re-reads it).  opts: precision and stream are used; the plan allocates its
+ * own device memory (the concatenated bands, right-hand sides and
+ * workspaces), so opts.workspace is ignored.  Systems with p = 0 get their
+ * partition count from the autotuner, which times candidate partition sizes
+ * (and, for K >= 16, matrix-core against workgroup sweeps) on the systems
+ * themselves and keeps the fastest; this synchronizes the stream.
+ * Returns -2 for an invalid descriptor, NOT_SUPPORTED for k > 32 or 2r > 64.
+ */
+int lrspike_factor_batched(int32_t count, const lrspike_batch_desc *descs, const double *bands_base,
+                           const lrspike_opts *opts, lrspike_plan *plan_out);
+
+/* In place: every system's right-hand sides at rhs_base + rhs_offset are
+ * overwritten by its solution.  rhs_base: device pointer. */
+int lrspike_solve_batched(lrspike_plan plan, double *rhs_base);
+
+/*
+ * Factor (from the current contents of bands_base) and solve every system, as
+ * one HIP graph: the first call with a given rhs_base runs eagerly and
+ * captures the sequence; later calls with the same rhs_base replay the graph
+ * (a new rhs_base captures again).  FP64 plans only (the refinement loop
+ * reads norms on the host): NOT_SUPPORTED otherwise.
+ */
+int lrspike_run_batched(lrspike_plan plan, double *rhs_base);
+
+/* p_out[s] = the partition count used for system s (count = the descriptor count). */
+int lrspike_batch_partitions(lrspike_plan plan, int32_t count, int32_t *p_out);
+
+/* For a batched plan, lrspike_status reports the first latched error of any
+ * system (info.partition = that system's index) and sums swapped_blocks;
+ * lrspike_solve, lrspike_solve_adjoint, lrspike_band_grad and the profiling
+ * calls return -1 for it. */
 
 const char *lrspike_strerror(int code);
 

@@ -10,6 +10,9 @@ library or a GPU every call raises.
     x = plan.solve(b)                                  # b: (n,) or (n, m) float64 CUDA tensor
     lam = plan.solve_adjoint(g)
     x = solve(bands, b, p, r)                          # differentiable in bands and b
+
+    bp = factor_batched(systems, bands_base)           # many independent systems
+    bp.solve(rhs_base); bp.run(rhs_base)               # eager / one graph replay of factor + solve
 """
 import ctypes
 import os
@@ -18,7 +21,8 @@ import torch
 
 from . import build as _build
 
-__all__ = ["factor", "solve", "Plan", "LRSpikeError", "library_path", "load_library"]
+__all__ = ["factor", "solve", "Plan", "BatchedPlan", "factor_batched", "pack_systems", "LRSpikeError",
+           "library_path", "load_library"]
 
 FP64, FP32_REFINED = 0, 1
 _PRECISIONS = {"fp64": FP64, "fp32_refined": FP32_REFINED}
@@ -59,11 +63,24 @@ class _Info(ctypes.Structure):
     ]
 
 
+class _BatchDesc(ctypes.Structure):
+    _fields_ = [
+        ("n", ctypes.c_int64),
+        ("k", ctypes.c_int32),
+        ("p", ctypes.c_int32),
+        ("r", ctypes.c_int32),
+        ("nrhs", ctypes.c_int32),
+        ("band_offset", ctypes.c_int64),
+        ("rhs_offset", ctypes.c_int64),
+    ]
+
+
 _lib = None
 SYMBOLS = (
     "lrspike_default_opts", "lrspike_workspace_size", "lrspike_factor", "lrspike_solve",
     "lrspike_solve_adjoint", "lrspike_band_grad", "lrspike_status", "lrspike_destroy",
-    "lrspike_strerror", "lrspike_profile", "lrspike_profile_read",
+    "lrspike_strerror", "lrspike_profile", "lrspike_profile_read", "lrspike_factor_batched",
+    "lrspike_solve_batched", "lrspike_run_batched", "lrspike_batch_partitions",
 )
 
 
@@ -94,6 +111,10 @@ def load_library():
     lib.lrspike_profile.argtypes = [P, i32]
     lib.lrspike_profile_read.argtypes = [P, i32, ctypes.c_char_p, ctypes.POINTER(ctypes.c_double),
                                          ctypes.POINTER(i32), ctypes.POINTER(i32)]
+    lib.lrspike_factor_batched.argtypes = [i32, ctypes.POINTER(_BatchDesc), P, ctypes.POINTER(_Opts), ctypes.POINTER(P)]
+    lib.lrspike_solve_batched.argtypes = [P, P]
+    lib.lrspike_run_batched.argtypes = [P, P]
+    lib.lrspike_batch_partitions.argtypes = [P, i32, ctypes.POINTER(i32)]
     lib.lrspike_strerror.argtypes = [i32]
     lib.lrspike_strerror.restype = ctypes.c_char_p
     _lib = lib
@@ -265,3 +286,105 @@ def solve(bands, b, p, r=None, precision="fp64"):
     if r is None:
         r = (bands.shape[0] - 1) // 2
     return LRSpikeSolve.apply(bands, b, p, r, precision)
+
+
+def pack_systems(bands_list, rhs_list, p=None, r=None):
+    """Host-side marshalling for the batched calls: concatenates per-system
+    band-major bands ((2k_s+1, n_s) arrays) and row-major right-hand sides
+    ((n_s, m_s) arrays) into two flat float64 arrays and returns them with the
+    descriptor tuples (n, k, p, r, nrhs, band_offset, rhs_offset).  p defaults
+    to 0 (autotuned), r to k // 2."""
+    import numpy as np
+    descs, bo, ro = [], 0, 0
+    for s, (b, f) in enumerate(zip(bands_list, rhs_list)):
+        k = (b.shape[0] - 1) // 2
+        n = b.shape[1]
+        f2 = f.reshape(n, -1)
+        ps = 0 if p is None else (p[s] if hasattr(p, "__len__") else p)
+        rs = k // 2 if r is None else (r[s] if hasattr(r, "__len__") else r)
+        descs.append((n, k, int(ps), int(rs), f2.shape[1], bo, ro))
+        bo += b.size
+        ro += f2.size
+    bands = np.concatenate([np.ascontiguousarray(b).ravel() for b in bands_list])
+    rhs = np.concatenate([np.ascontiguousarray(f).ravel() for f in rhs_list])
+    return bands, rhs, descs
+
+
+class BatchedPlan:
+    """Factored batch of independent banded systems (``lrspike_factor_batched``).
+
+    ``systems``: descriptor tuples (n, k, p, r, nrhs, band_offset, rhs_offset),
+    offsets in elements of ``bands_base`` / ``rhs_base`` (flat float64 CUDA
+    tensors).  The plan borrows ``bands_base`` and owns its device memory."""
+
+    def __init__(self, systems, bands_base, precision="fp64"):
+        lib = load_library()
+        if not isinstance(bands_base, torch.Tensor) or bands_base.device.type != "cuda" or \
+                bands_base.dtype != torch.float64 or not bands_base.is_contiguous():
+            raise TypeError("bands_base must be a contiguous float64 CUDA tensor")
+        self.count = len(systems)
+        arr = (_BatchDesc * self.count)()
+        for i, d in enumerate(systems):
+            arr[i] = _BatchDesc(*[int(v) for v in d])
+        self.systems = [tuple(int(v) for v in d) for d in systems]
+        self.bands_base = bands_base
+        self.precision = precision
+        opts = _Opts()
+        lib.lrspike_default_opts(ctypes.byref(opts))
+        opts.precision = _PRECISIONS[precision]
+        opts.stream = torch.cuda.current_stream(bands_base.device).cuda_stream
+        handle = ctypes.c_void_p()
+        rc = lib.lrspike_factor_batched(self.count, arr, bands_base.data_ptr(), ctypes.byref(opts),
+                                        ctypes.byref(handle))
+        if rc:
+            raise LRSpikeError(rc, "lrspike_factor_batched")
+        self._h = handle
+        self._lib = lib
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            self._lib.lrspike_destroy(h)
+            self._h = None
+
+    def _check_rhs(self, rhs_base):
+        if not isinstance(rhs_base, torch.Tensor) or rhs_base.device.type != "cuda" or \
+                rhs_base.dtype != torch.float64 or not rhs_base.is_contiguous():
+            raise TypeError("rhs_base must be a contiguous float64 CUDA tensor")
+
+    def solve(self, rhs_base):
+        """In place: every system's right-hand sides are replaced by its solution."""
+        self._check_rhs(rhs_base)
+        rc = self._lib.lrspike_solve_batched(self._h, rhs_base.data_ptr())
+        if rc:
+            raise LRSpikeError(rc, "lrspike_solve_batched")
+        return rhs_base
+
+    def run(self, rhs_base):
+        """Refactor from bands_base and solve in place, as one HIP graph replay."""
+        self._check_rhs(rhs_base)
+        rc = self._lib.lrspike_run_batched(self._h, rhs_base.data_ptr())
+        if rc:
+            raise LRSpikeError(rc, "lrspike_run_batched")
+        return rhs_base
+
+    def partitions(self):
+        out = (ctypes.c_int32 * self.count)()
+        rc = self._lib.lrspike_batch_partitions(self._h, self.count, out)
+        if rc:
+            raise LRSpikeError(rc, "lrspike_batch_partitions")
+        return list(out)
+
+    def status(self):
+        info = _Info()
+        rc = self._lib.lrspike_status(self._h, ctypes.byref(info))
+        d = {f: getattr(info, f) for f, _ in _Info._fields_}
+        if rc:
+            err = LRSpikeError(rc, "lrspike_status")
+            err.info = d
+            raise err
+        return d
+
+
+def factor_batched(systems, bands_base, precision="fp64"):
+    return BatchedPlan(systems, bands_base, precision=precision)

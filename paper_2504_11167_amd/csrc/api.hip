@@ -5,6 +5,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <algorithm>
 #include <vector>
 
 #include "../../include/lrspike.h"
@@ -23,6 +24,10 @@ struct RedArgs;
 
 using namespace lrs;
 
+namespace {
+struct BatchState;
+}
+
 struct lrspike_plan_s {
   Layout L;
   int precision;
@@ -37,6 +42,8 @@ struct lrspike_plan_s {
   // opt-in per-launch timing: an event pair around every kernel on the plan's stream
   int profiling;
   std::vector<std::pair<const char*, std::pair<hipEvent_t, hipEvent_t>>> prof;
+  int wave = 1;                 // matrix-core wave sweeps for K >= 16 (else workgroup sweeps)
+  BatchState* batch = nullptr;  // set for plans made by lrspike_factor_batched
 };
 
 // ------------------------------------------------------------------ dispatch tables
@@ -93,10 +100,16 @@ size_t lds_p2() { return (size_t)P2Lds<K>::total * sizeof(T); }
 template <typename T, int K>
 size_t lds_sw() { return (size_t)SwLds<K>::total * sizeof(T); }
 
+// Dynamic LDS above 64 KB needs the kernel attribute; each (kernel, size) is
+// set once per process (so that no attribute call happens during a capture).
 bool set_lds(const void* fn, size_t bytes) {
   if (bytes > 160 * 1024) return false;
-  if (bytes > 64 * 1024)
-    return hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) == hipSuccess;
+  if (bytes <= 64 * 1024) return true;
+  static std::vector<std::pair<const void*, size_t>> done;
+  for (auto& e : done)
+    if (e.first == fn && e.second >= bytes) return true;
+  if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) != hipSuccess) return false;
+  done.push_back({fn, bytes});
   return true;
 }
 
@@ -229,7 +242,7 @@ int run_apply(lrspike_plan P, double* rhs, int m, int transpose) {
   dim3 grid(L.p, (m + MC - 1) / MC);
   size_t bs = lds_sw<T, K>();
   int rc;
-  if (!transpose && K >= 16) {
+  if (!transpose && K >= 16 && P->wave) {
     // matrix-core sweeps: one wave per partition and column chunk
     if constexpr (K >= 16) {
       const bool one = m <= 16;
@@ -355,6 +368,16 @@ apply_fn pick_apply(int K) {
   return nullptr;
 }
 
+void prof_clear(lrspike_plan P) {
+  for (auto& e : P->prof) {
+    (void)hipEventDestroy(e.second.first);
+    (void)hipEventDestroy(e.second.second);
+  }
+  P->prof.clear();
+}
+
+#include "batched.hip"
+
 bool is_device_ptr(const void* p) {
   if (!p) return false;
   hipPointerAttribute_t at;
@@ -438,7 +461,7 @@ int lrspike_factor(int64_t n, int32_t k, const double* bands, int32_t p, int32_t
 }
 
 static int solve_common(lrspike_plan P, double* rhs, int32_t nrhs, int transpose) {
-  if (!P) return -1;
+  if (!P || P->batch) return -1;
   if (!is_device_ptr(rhs)) return -2;
   if (nrhs < 1 || nrhs > P->L.mmax) return -3;
   apply_fn f;
@@ -458,7 +481,7 @@ int lrspike_solve_adjoint(lrspike_plan plan, double* rhs, int32_t nrhs) {
 
 int lrspike_band_grad(lrspike_plan P, const double* lam, const double* x, int32_t nrhs,
                       double* grad_bands) {
-  if (!P) return -1;
+  if (!P || P->batch) return -1;
   if (!is_device_ptr(lam)) return -2;
   if (!is_device_ptr(x)) return -3;
   if (nrhs < 1) return -4;
@@ -471,6 +494,29 @@ int lrspike_band_grad(lrspike_plan P, const double* lam, const double* x, int32_
 
 int lrspike_status(lrspike_plan P, lrspike_info* info) {
   if (!P) return -1;
+  if (P->batch) {
+    // first latched error over the groups; partition reports the system index
+    lrspike_info gi, out;
+    memset(&out, 0, sizeof(out));
+    out.partition = -1;
+    out.row = -1;
+    int first = 0;
+    for (BatchGroup& G : P->batch->groups) {
+      int rc = lrspike_status(G.plan, &gi);
+      if (rc < 0 || rc == LRSPIKE_ERR_HIP) return rc;
+      out.swapped_blocks += gi.swapped_blocks;
+      out.refine_iters = std::max(out.refine_iters, gi.refine_iters);
+      out.last_correction = std::max(out.last_correction, gi.last_correction);
+      if (rc && !first) {
+        first = rc;
+        out.error = rc;
+        out.partition = gi.partition >= 0 && gi.partition < (int)G.part_sys.size() ? G.part_sys[gi.partition] : -1;
+        out.row = gi.row;
+      }
+    }
+    if (info) *info = out;
+    return first;
+  }
   if (hipStreamSynchronize(P->stream) != hipSuccess) return LRSPIKE_ERR_HIP;
   int latch[16];
   if (hipMemcpy(latch, P->ws + P->L.latch, sizeof(latch), hipMemcpyDeviceToHost) != hipSuccess)
@@ -488,23 +534,15 @@ int lrspike_status(lrspike_plan P, lrspike_info* info) {
   return latch[0];
 }
 
-static void prof_clear(lrspike_plan P) {
-  for (auto& e : P->prof) {
-    (void)hipEventDestroy(e.second.first);
-    (void)hipEventDestroy(e.second.second);
-  }
-  P->prof.clear();
-}
-
 int lrspike_profile(lrspike_plan P, int32_t enable) {
-  if (!P) return -1;
+  if (!P || P->batch) return -1;
   P->profiling = enable ? 1 : 0;
   return 0;
 }
 
 int lrspike_profile_read(lrspike_plan P, int32_t max, char* names, double* total_ms, int32_t* launches,
                          int32_t* count) {
-  if (!P) return -1;
+  if (!P || P->batch) return -1;
   if (max < 0) return -2;
   if (!count) return -6;
   if (hipStreamSynchronize(P->stream) != hipSuccess) return LRSPIKE_ERR_HIP;
@@ -538,8 +576,122 @@ int lrspike_profile_read(lrspike_plan P, int32_t max, char* names, double* total
 }
 
 int lrspike_destroy(lrspike_plan P) {
-  if (P) prof_clear(P);
+  if (P) {
+    prof_clear(P);
+    if (P->batch) {
+      for (BatchGroup& G : P->batch->groups) free_group(G);
+      if (P->batch->graph) (void)hipGraphExecDestroy(P->batch->graph);
+      if (P->batch->capture) (void)hipStreamDestroy(P->batch->capture);
+      delete P->batch;
+    }
+  }
   delete P;
+  return 0;
+}
+
+int lrspike_factor_batched(int32_t count, const lrspike_batch_desc* descs, const double* bands_base,
+                           const lrspike_opts* opts, lrspike_plan* plan_out) {
+  if (count < 1) return -1;
+  if (!descs) return -2;
+  if (!is_device_ptr(bands_base)) return -3;
+  if (!opts) return -4;
+  if (!plan_out) return -5;
+  if (opts->precision != LRSPIKE_FP64 && opts->precision != LRSPIKE_FP32_REFINED) return -4;
+  for (int s = 0; s < count; ++s) {
+    const lrspike_batch_desc& d = descs[s];
+    if (d.n < 1 || d.k < 1 || d.r < 0 || d.r > d.k || d.nrhs < 1 || d.p < 0 || d.p > d.n || d.band_offset < 0 ||
+        d.rhs_offset < 0)
+      return -2;
+    const int K = kernel_K(d.k);
+    const int64_t minrows = std::max<int64_t>(2 * (int64_t)d.k, K);
+    if ((d.p > 0 ? d.n / d.p : d.n) < minrows) return -2;
+    if (K > 32 || 2 * ((d.r == d.k) ? K : d.r) > 64) return LRSPIKE_ERR_NOT_SUPPORTED;
+  }
+  lrspike_plan P = new lrspike_plan_s();
+  P->batch = new BatchState();
+  BatchState& B = *P->batch;
+  B.descs.assign(descs, descs + count);
+  B.bands_base = bands_base;
+  B.precision = opts->precision;
+  P->stream = reinterpret_cast<hipStream_t>(opts->stream);
+  P->precision = opts->precision;
+  // groups: equal (k, r) and padded right-hand-side count
+  auto padded = [](int m) { return m <= 2 ? m : (m <= 4 ? 4 : (m + 7) / 8 * 8); };
+  for (int s = 0; s < count; ++s) {
+    const lrspike_batch_desc& d = descs[s];
+    const int mb = padded(d.nrhs);
+    size_t g = 0;
+    while (g < B.groups.size() && !(B.groups[g].k == d.k && B.groups[g].r == d.r && B.groups[g].mb == mb)) ++g;
+    if (g == B.groups.size()) {
+      B.groups.emplace_back();
+      B.groups.back().k = d.k;
+      B.groups.back().r = d.r;
+      B.groups.back().mb = mb;
+    }
+    B.groups[g].sys.push_back(s);
+  }
+  int rc = autotune(B, opts);
+  if (!rc) rc = run_batched_eager(P, nullptr, true, false);
+  if (rc) {
+    lrspike_destroy(P);
+    return rc;
+  }
+  *plan_out = P;
+  return 0;
+}
+
+int lrspike_solve_batched(lrspike_plan P, double* rhs_base) {
+  if (!P || !P->batch) return -1;
+  if (!is_device_ptr(rhs_base)) return -2;
+  return run_batched_eager(P, rhs_base, false, true);
+}
+
+int lrspike_run_batched(lrspike_plan P, double* rhs_base) {
+  if (!P || !P->batch) return -1;
+  if (!is_device_ptr(rhs_base)) return -2;
+  BatchState& B = *P->batch;
+  if (B.precision != LRSPIKE_FP64) return LRSPIKE_ERR_NOT_SUPPORTED;
+  hipStream_t st = P->stream;
+  if (B.graph && B.graph_rhs == rhs_base) return hipGraphLaunch(B.graph, st) == hipSuccess ? 0 : LRSPIKE_ERR_HIP;
+  if (B.graph) {
+    (void)hipGraphExecDestroy(B.graph);
+    B.graph = nullptr;
+  }
+  // this call runs eagerly; the same sequence is then captured for the next calls
+  int rc = run_batched_eager(P, rhs_base, true, true);
+  if (rc) return rc;
+  if (!B.capture && hipStreamCreateWithFlags(&B.capture, hipStreamNonBlocking) != hipSuccess) {
+    B.capture = nullptr;
+    return LRSPIKE_ERR_HIP;
+  }
+  if (hipStreamSynchronize(st) != hipSuccess) return LRSPIKE_ERR_HIP;
+  hipGraph_t g = nullptr;
+  if (hipStreamBeginCapture(B.capture, hipStreamCaptureModeThreadLocal) != hipSuccess) return LRSPIKE_ERR_HIP;
+  set_group_streams(B, B.capture);
+  rc = run_batched_eager(P, rhs_base, true, true);
+  set_group_streams(B, st);
+  const hipError_t ce = hipStreamEndCapture(B.capture, &g);
+  if (rc || ce != hipSuccess) {
+    if (g) (void)hipGraphDestroy(g);
+    return rc ? rc : LRSPIKE_ERR_HIP;
+  }
+  const hipError_t ie = hipGraphInstantiate(&B.graph, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (ie != hipSuccess) {
+    B.graph = nullptr;
+    return LRSPIKE_ERR_HIP;
+  }
+  B.graph_rhs = rhs_base;
+  return 0;
+}
+
+int lrspike_batch_partitions(lrspike_plan P, int32_t count, int32_t* p_out) {
+  if (!P || !P->batch) return -1;
+  BatchState& B = *P->batch;
+  if (count != (int32_t)B.descs.size()) return -2;
+  if (!p_out) return -3;
+  for (BatchGroup& G : B.groups)
+    for (int s : G.sys) p_out[s] = sys_partitions(B.descs[s], G.target);
   return 0;
 }
 

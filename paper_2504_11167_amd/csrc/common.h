@@ -12,6 +12,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "layout.h"
+
 #define LRS_NT 256  // threads per workgroup (4 wave64)
 
 namespace lrs {
@@ -28,6 +30,17 @@ __device__ __host__ inline Geom part_geom(int64_t n, int p, int j, int K) {
   Geom g;
   g.nj = (int)(base + (j < extra ? 1 : 0));
   g.s = (int64_t)j * base + (j < extra ? j : extra);
+  g.nb = (g.nj + K - 1) / K;
+  g.pad = g.nb * K - g.nj;
+  return g;
+}
+
+// geometry of partition j of a plan (explicit offsets or the uniform rule)
+__device__ inline Geom part_geom(const Layout& L, int j, int K) {
+  if (!L.offs) return part_geom(L.n, L.p, j, K);
+  Geom g;
+  g.s = L.offs[j];
+  g.nj = (int)(L.offs[j + 1] - L.offs[j]);
   g.nb = (g.nj + K - 1) / K;
   g.pad = g.nb * K - g.nj;
   return g;

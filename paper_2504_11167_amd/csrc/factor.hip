@@ -78,7 +78,7 @@ __global__ __launch_bounds__(LRS_NT) void factor_pass1(FactorArgs a) {
   const int j = blockIdx.x;
   const int tid = threadIdx.x;
   if (a.only_flagged && wsT<int>(a.ws, L.npv)[j] == 0) return;
-  const Geom g = part_geom(L.n, L.p, j, K);
+  const Geom g = part_geom(L, j, K);
   const int k = L.k;
   const int nb = g.nb;
   int* latch = wsT<int>(a.ws, L.latch);
@@ -408,7 +408,7 @@ __global__ __launch_bounds__(LRS_NT) void factor_pass2(FactorArgs a) {
   T* Y = lds + LD::oY;
   const Layout& L = a.L;
   const int j = blockIdx.x, tid = threadIdx.x;
-  const Geom g = part_geom(L.n, L.p, j, K);
+  const Geom g = part_geom(L, j, K);
   const T* fac = wsT<T>(a.ws, L.fac) + (size_t)j * L.nbmax * L.rec;
   const T* swx = wsT<T>(a.ws, L.swx) + (size_t)j * L.nbmax * 3 * K * K;
   const T* ym = wsT<T>(a.ws, L.ymat) + (size_t)j * L.nbmax * 2 * K * K;

@@ -116,7 +116,7 @@ __global__ __launch_bounds__(64) void factor_wave_kernel(FactorArgs a) {
   const Layout& L = a.L;
   const int j = blockIdx.x, k = L.k;
   int lane = threadIdx.x & 63;
-  const Geom g = part_geom(L.n, L.p, j, K);
+  const Geom g = part_geom(L, j, K);
   const int nb = g.nb;
   T* fac = wsT<T>(a.ws, L.fac) + (size_t)j * L.nbmax * L.rec;
   T* gm = wsT<T>(a.ws, L.gmat) + (size_t)j * L.nbmax * K * K;
@@ -340,7 +340,7 @@ __global__ __launch_bounds__(64) void spike_wave_kernel(FactorArgs a) {
   const int j = blockIdx.x, k = L.k;
   int lane = threadIdx.x & 63;
   if (wsT<int>(a.ws, L.npv)[j]) return;
-  const Geom g = part_geom(L.n, L.p, j, K);
+  const Geom g = part_geom(L, j, K);
   const T* fac = wsT<T>(a.ws, L.fac) + (size_t)j * L.nbmax * L.rec;
   const T* gm = wsT<T>(a.ws, L.gmat) + (size_t)j * L.nbmax * K * K;
   T* ym = (L.r < K) ? wsT<T>(a.ws, L.ymat) + (size_t)j * L.nbmax * 2 * K * K : nullptr;

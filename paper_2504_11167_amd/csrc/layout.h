@@ -10,6 +10,9 @@ namespace lrs {
 
 struct Layout {
   int64_t n;
+  // partition j covers rows [offs[j], offs[j+1]) when offs (device, p + 1
+  // entries) is set; otherwise the uniform rule floor(n/p) + [j < n mod p]
+  const int64_t* offs;
   int k, K, p, r, R2, nbmax, mmax, tsize;  // r: compressed rank (K when the user's r = k)
   int NI;       // interfaces p - 1
   int levels;   // cyclic-reduction levels (ceil(log2(NI)))
@@ -40,8 +43,12 @@ inline int kernel_K(int k) {
   return K;
 }
 
-inline void make_layout(Layout& L, int64_t n, int k, int p, int r, int tsize, int mmax) {
+// offs_host / offs_dev: explicit partition offsets (p + 1 entries, host and
+// device copies) or null for the uniform partition rule
+inline void make_layout(Layout& L, int64_t n, int k, int p, int r, int tsize, int mmax,
+                        const int64_t* offs_host = nullptr, const int64_t* offs_dev = nullptr) {
   L.n = n;
+  L.offs = offs_dev;
   L.k = k;
   L.K = kernel_K(k);
   L.p = p;
@@ -54,6 +61,11 @@ inline void make_layout(Layout& L, int64_t n, int k, int p, int r, int tsize, in
   L.mmax = mmax;
   const int K = L.K;
   int64_t njmax = (n + p - 1) / p;
+  if (offs_host) {
+    njmax = 0;
+    for (int j = 0; j < p; ++j)
+      if (offs_host[j + 1] - offs_host[j] > njmax) njmax = offs_host[j + 1] - offs_host[j];
+  }
   L.nbmax = (int)((njmax + K - 1) / K);
   L.NI = p - 1;
   L.levels = 0;

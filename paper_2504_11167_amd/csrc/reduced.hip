@@ -557,7 +557,7 @@ __global__ void zrhs_kernel(RedArgs a, const double* bands) {
   // h vectors: H0 = h_{(i,t)}, H1 = h_{(i,b)}, H2 = h_{(i+1,t)}, H3 = h_{(i+1,b)}
   auto hvec = [&](int jj, bool top, double* out) {
     // h_{(jj,t)} = B_{jj-1}^T nu_{jj-1,b} (jj >= 1);  h_{(jj,b)} = C_{jj+1}^T nu_{jj+1,t} (jj <= p-2)
-    Geom gj = part_geom(L.n, p, jj, K);
+    Geom gj = part_geom(L, jj, K);
     for (int o = threadIdx.x; o < K * m; o += blockDim.x) {
       int row = o / m, c = o % m;
       double s = 0.0;

@@ -249,7 +249,7 @@ __global__ __launch_bounds__(LRS_NT) void dstage_kernel(SolveArgs a) {
   T* lds = reinterpret_cast<T*>(lds_raw);
   const int j = blockIdx.x, c0 = blockIdx.y * MC;
   const int mc = min(MC, a.m - c0);
-  const Geom g = part_geom(a.L.n, a.L.p, j, K);
+  const Geom g = part_geom(a.L, j, K);
   forward_pass<T, K, true>(a, g, j, c0, mc, lds, nullptr, nullptr, s_perm);
 }
 
@@ -264,7 +264,7 @@ __global__ __launch_bounds__(LRS_NT) void retrieve_kernel(SolveArgs a) {
   const Layout& L = a.L;
   const int j = blockIdx.x, c0 = blockIdx.y * MC;
   const int mc = min(MC, a.m - c0);
-  const Geom g = part_geom(L.n, L.p, j, K);
+  const Geom g = part_geom(L, j, K);
   T* Ct = lds + LD::oCt;
   T* Cb = lds + LD::oCb;
   T* Xn = lds + LD::oTmp;  // neighbour tip staging
@@ -422,7 +422,7 @@ __global__ __launch_bounds__(LRS_NT) void adj_dstage_kernel(SolveArgs a) {
   const Layout& L = a.L;
   const int j = blockIdx.x, c0 = blockIdx.y * MC;
   const int mc = min(MC, a.m - c0);
-  const Geom g = part_geom(L.n, L.p, j, K);
+  const Geom g = part_geom(L, j, K);
   tforward_pass<T, K>(a, g, j, c0, mc, lds, nullptr, nullptr);
   __syncthreads();
   tbackward_pass<T, K>(a, g, j, c0, mc, lds, s_perm);
@@ -449,7 +449,7 @@ __global__ __launch_bounds__(LRS_NT) void adj_retrieve_kernel(SolveArgs a) {
   const Layout& L = a.L;
   const int j = blockIdx.x, c0 = blockIdx.y * MC;
   const int mc = min(MC, a.m - c0);
-  const Geom g = part_geom(L.n, L.p, j, K);
+  const Geom g = part_geom(L, j, K);
   T* Ct = lds + LD::oCt;
   T* Cb = lds + LD::oCb;
   const int tid = threadIdx.x, k = L.k, r = L.r;

@@ -374,7 +374,7 @@ __global__ __launch_bounds__(64) void dstage_wave_kernel(SolveArgs a) {
   extern __shared__ __align__(16) unsigned char lds_raw[];
   T* lds = reinterpret_cast<T*>(lds_raw);
   const int j = blockIdx.x, c0 = blockIdx.y * 16 * MCT;
-  const Geom g = part_geom(a.L.n, a.L.p, j, K);
+  const Geom g = part_geom(a.L, j, K);
   fwd_wave<T, K, MCT, true>(a, g, j, c0, lds, nullptr, nullptr);
 }
 
@@ -387,7 +387,7 @@ __global__ __launch_bounds__(64) void retrieve_wave_kernel(SolveArgs a) {
   const Layout& L = a.L;
   const int j = blockIdx.x, c0 = blockIdx.y * NC;
   const int mc = min(NC, a.m - c0);
-  const Geom g = part_geom(L.n, L.p, j, K);
+  const Geom g = part_geom(L, j, K);
   const int lane = threadIdx.x & 63, k = L.k;
   T* Ct = lds + W::oCt;
   T* Cb = lds + W::oCb;
@@ -463,7 +463,7 @@ __global__ __launch_bounds__(64) void pass2_wave_kernel(FactorArgs a) {
   constexpr int NF = W::RT * W::KS;
   const Layout& L = a.L;
   const int j = blockIdx.x, spike = blockIdx.y, lane = threadIdx.x & 63;
-  const Geom g = part_geom(L.n, L.p, j, K);
+  const Geom g = part_geom(L, j, K);
   const T* fac = wsT<T>(a.ws, L.fac) + (size_t)j * L.nbmax * L.rec;
   const T* swx = wsT<T>(a.ws, L.swx) + (size_t)j * L.nbmax * 3 * K * K;
   const T* ym = wsT<T>(a.ws, L.ymat) + (size_t)j * L.nbmax * 2 * K * K;

@@ -248,3 +248,78 @@ def test_full_size_large_workload(gpu):
     x, info = run(gpu, bands, f, p, r)
     ref = oracle.lrspike(bands, f, p, r)
     assert rel(x, ref) <= 1e-12
+
+
+def _batch(count, seed, ks=(4, 16, 32), nmax=3000):
+    """count systems of the batched workload's kind: k drawn from ks, n up to nmax, 1..6 right-hand sides."""
+    rng = np.random.default_rng(seed)
+    bl, fl = [], []
+    for s in range(count):
+        k = int(rng.choice(ks))
+        n = int(rng.integers(max(8 * k, 100), nmax))
+        m = int(rng.integers(1, 7))
+        b, f = synth.make_problem(n, k, m, seed=1000 * seed + s, rule="strict")
+        bl.append(b)
+        fl.append(f)
+    return bl, fl
+
+
+def _unpack(x, descs):
+    return [x[d[6]:d[6] + d[0] * d[4]].reshape(d[0], d[4]) for d in descs]
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32_refined"])
+def test_batched_matches_per_system_oracle(gpu, precision):
+    """Every system of a batch (mixed k, n, nrhs; p autotuned for most, given
+    for some) equals the oracle's LR-SPIKE of that system alone."""
+    bl, fl = _batch(18, 1)
+    bands, rhs, descs = gpu.pack_systems(bl, fl)
+    descs = [(d[0], d[1], (3 if s % 4 == 0 else 0), d[3], d[4], d[5], d[6]) for s, d in enumerate(descs)]
+    plan = gpu.factor_batched(descs, to_dev(bands), precision=precision)
+    tr = to_dev(rhs)
+    plan.solve(tr)
+    plan.status()
+    ps = plan.partitions()
+    assert all(ps[s] == 3 for s in range(0, len(descs), 4))
+    for s, xs in enumerate(_unpack(tr.cpu().numpy(), descs)):
+        n, k, _, r, m = descs[s][:5]
+        if precision == "fp64":
+            assert rel(xs, oracle.lrspike(bl[s], fl[s], ps[s], r)) <= 1e-12, s
+        else:
+            assert rel(xs, oracle.band_solve_refined(bl[s], fl[s])) <= 1e-11, s
+
+
+def test_batched_graph_replays_match_eager(gpu):
+    """One HIP graph (factor + solve of every system) replayed several times,
+    with eager solves and synchronizations in between, reproduces the eager
+    result bit for bit each time."""
+    bl, fl = _batch(10, 2)
+    bands, rhs, descs = gpu.pack_systems(bl, fl)
+    plan = gpu.factor_batched(descs, to_dev(bands))
+    eager = to_dev(rhs)
+    plan.solve(eager)
+    plan.status()
+    ref = eager.cpu().numpy()
+    tr = to_dev(rhs)
+    for rep in range(4):
+        tr.copy_(to_dev(rhs))
+        plan.run(tr)
+        other = to_dev(rhs)
+        plan.solve(other)
+        torch.cuda.synchronize()
+        plan.status()
+        assert np.array_equal(tr.cpu().numpy(), ref), rep
+        assert np.array_equal(other.cpu().numpy(), ref), rep
+    for s, xs in enumerate(_unpack(ref, descs)):
+        assert rel(xs, oracle.lrspike(bl[s], fl[s], plan.partitions()[s], descs[s][3])) <= 1e-12
+
+
+def test_batched_rejects_bad_descriptors(gpu):
+    b, f = synth.make_problem(500, 4, 1, seed=0)
+    tb = to_dev(b.ravel())
+    with pytest.raises(gpu.LRSpikeError) as e:
+        gpu.factor_batched([(500, 4, 0, 5, 1, 0, 0)], tb)  # r > k
+    assert e.value.code == -2
+    with pytest.raises(gpu.LRSpikeError) as e:
+        gpu.factor_batched([(500, 4, 100, 2, 1, 0, 0)], tb)  # n / p < 2k
+    assert e.value.code == -2
