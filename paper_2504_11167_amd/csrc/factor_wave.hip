@@ -402,7 +402,7 @@ __global__ __launch_bounds__(64) void spike_wave_kernel(FactorArgs a) {
     blk_mul<T, K, MCT, 9>(gt, nullptr, T(1), z, acc);
     if (ym) {
       put_y(b, 0, z);
-      if (!last) {
+      if (b == g.nb - 2) {  // V's forward result above the last block (zero here; read by the back-sweep)
         V zz[W::RT][MCT];
         zero_strip<T, K, MCT>(zz);
         put_y(b, K, zz);

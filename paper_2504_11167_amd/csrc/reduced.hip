@@ -42,6 +42,7 @@ __device__ inline T* rws(char* ws, size_t off) {
 // One wave per (partition, spike): eigen-decomposition of the K x K Gram
 // matrix by cyclic Jacobi with a round-robin (parallel) pair ordering; writes
 // the eigenvectors of the r largest eigenvalues as the columns of Pi (K x r).
+// Launched with LRS_NT threads.
 template <int K>
 __global__ __launch_bounds__(LRS_NT) void eigen_kernel(RedArgs a) {
   constexpr int LD = K + 1;
@@ -51,6 +52,7 @@ __global__ __launch_bounds__(LRS_NT) void eigen_kernel(RedArgs a) {
   __shared__ int pa[KE / 2], pb[KE / 2];
   __shared__ int order[K];
   __shared__ int s_done;
+  __shared__ double s_red[2 * (LRS_NT / 64)];
   const Layout& L = a.L;
   const int j = blockIdx.x, which = blockIdx.y;  // which: 0 = V (Pi), 1 = W (Psi)
   const int tid = threadIdx.x, r = L.r;
@@ -79,7 +81,19 @@ __global__ __launch_bounds__(LRS_NT) void eigen_kernel(RedArgs a) {
         off += __shfl_xor(off, w);
         dia += __shfl_xor(dia, w);
       }
-      if (tid == 0) s_done = (off <= 1e-28 * dia) ? 1 : 0;
+      if ((tid & 63) == 0) {
+        s_red[2 * (tid >> 6)] = off;
+        s_red[2 * (tid >> 6) + 1] = dia;
+      }
+      __syncthreads();
+      if (tid == 0) {
+        double so = 0.0, sd = 0.0;
+        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) {
+          so += s_red[2 * w];
+          sd += s_red[2 * w + 1];
+        }
+        s_done = (so <= 1e-28 * sd) ? 1 : 0;
+      }
     }
     __syncthreads();
     if (s_done) break;
@@ -134,17 +148,16 @@ __global__ __launch_bounds__(LRS_NT) void eigen_kernel(RedArgs a) {
       __syncthreads();
     }
   }
-  // order eigenvalues descending (stable: ties keep the lower index first)
-  if (tid == 0) {
-    for (int i = 0; i < K; ++i) order[i] = i;
-    for (int i = 0; i < K; ++i) {
-      int best = i;
-      for (int c = i + 1; c < K; ++c)
-        if (G[order[c] * LD + order[c]] > G[order[best] * LD + order[best]]) best = c;
-      int t = order[i];
-      order[i] = order[best];
-      order[best] = t;
+  // order eigenvalues descending (stable: ties keep the lower index first):
+  // lane i places itself at its rank
+  if (tid < K) {
+    const double di = G[tid * LD + tid];
+    int rank = 0;
+    for (int c = 0; c < K; ++c) {
+      const double dc = G[c * LD + c];
+      rank += (dc > di || (dc == di && c < tid)) ? 1 : 0;
     }
+    order[rank] = tid;
   }
   __syncthreads();
   for (int o = tid; o < K * r; o += blockDim.x) {

@@ -469,7 +469,14 @@ __global__ __launch_bounds__(64) void pass2_wave_kernel(FactorArgs a) {
   const T* ym = wsT<T>(a.ws, L.ymat) + (size_t)j * L.nbmax * 2 * K * K;
   const int* flg = wsT<int>(a.ws, L.flag) + (size_t)j * L.nbmax;
   const int coff = spike == 0 ? 0 : K;  // Y columns [W | V]
+  // V's right-hand side lives in the last k rows: its forward result is zero
+  // above the last two blocks (interchanges act within a block pair) and is
+  // neither stored nor read there
   auto load_y = [&](int b, V (&st)[W::RT][MCT]) {
+    if (spike == 1 && b < g.nb - 2) {
+      zero_strip<T, K, MCT>(st);
+      return;
+    }
 #pragma unroll
     for (int t = 0; t < W::RT; ++t)
 #pragma unroll
