@@ -41,57 +41,49 @@ __device__ __forceinline__ void wave_fence() {  // order LDS accesses of one wav
 
 // Forward elimination step C of the 2K x K panel without interchanges, lane =
 // row, row held in pa[] (U part / multipliers) and iv[] (the row of L11^{-1}
-// being formed, implicit 1 at the lane's own column).  The pivot row is
-// published through LDS and read back as a broadcast.
+// being formed, implicit 1 at the lane's own column).  The pivot row (lane C)
+// reaches the other lanes by lane reads into scalar registers (no LDS traffic,
+// so the waves sharing a CU do not contend); a scheduling barrier per step
+// keeps those reads next to their use.
 template <typename T, int K, int C>
 struct FwdElim {
-  static __device__ __forceinline__ void run(T (&pa)[K], T (&iv)[K], T* prow, int lane, int nr, T& mx,
-                                             T& dmin) {
+  static __device__ __forceinline__ void run(T (&pa)[K], T (&iv)[K], int lane, int nr, T& mx, T& dmin, T& dinv) {
     if constexpr (C < K) {
-      if (lane == C) {
-#pragma unroll
-        for (int c = C; c < K; ++c) prow[c] = pa[c];
-#pragma unroll
-        for (int c = 0; c < C; ++c) prow[K + c] = iv[c];
-      }
-      wave_fence();
-      const T d = prow[C];
+      __builtin_amdgcn_sched_barrier(0);
+      const T d = bcast(pa[C], C);
+      const T inv = T(1) / d;  // uniform: one reciprocal per step
+      if (lane == C) dinv = inv;
       dmin = fmin(dmin, fabs(d));
       const bool act = lane > C && lane < nr;
-      const T l = act ? pa[C] / d : T(0);
+      const T l = act ? pa[C] * inv : T(0);
       mx = fmax(mx, fabs(l));
       if (act) pa[C] = l;
 #pragma unroll
-      for (int c = C + 1; c < K; ++c) pa[c] = fma(-l, prow[c], pa[c]);
+      for (int c = C + 1; c < K; ++c) pa[c] = fma(-l, bcast(pa[c], C), pa[c]);
 #pragma unroll
-      for (int c = 0; c < C; ++c) iv[c] = fma(-l, prow[K + c], iv[c]);
+      for (int c = 0; c < C; ++c) iv[c] = fma(-l, bcast(iv[c], C), iv[c]);
       iv[C] -= l;
-      wave_fence();
-      FwdElim<T, K, C + 1>::run(pa, iv, prow, lane, nr, mx, dmin);
+      FwdElim<T, K, C + 1>::run(pa, iv, lane, nr, mx, dmin, dinv);
     }
   }
 };
 
 // Upward Gauss-Jordan step C (counting down): lane i < K holds in uv[] the row
-// i of U11^{-1} being formed; U11 itself is read from pa[] (upper part).
+// i of U11^{-1} being formed; U11 itself is read from pa[] (upper part) and
+// lane C scales its finished row by 1/U_CC (its dinv from the forward pass).
 template <typename T, int K, int C>
 struct BwdElim {
-  static __device__ __forceinline__ void run(const T (&pa)[K], T (&uv)[K], T* prow, int lane) {
+  static __device__ __forceinline__ void run(const T (&pa)[K], T (&uv)[K], int lane, T dinv) {
     if constexpr (C >= 0) {
+      __builtin_amdgcn_sched_barrier(0);
       if (lane == C) {
-        const T s = T(1) / pa[C];
 #pragma unroll
-        for (int c = C; c < K; ++c) {
-          uv[c] *= s;
-          prow[c] = uv[c];
-        }
+        for (int c = C; c < K; ++c) uv[c] *= dinv;
       }
-      wave_fence();
       const T m = lane < C ? pa[C] : T(0);
 #pragma unroll
-      for (int c = C; c < K; ++c) uv[c] = fma(-m, prow[c], uv[c]);
-      wave_fence();
-      BwdElim<T, K, C - 1>::run(pa, uv, prow, lane);
+      for (int c = C; c < K; ++c) uv[c] = fma(-m, bcast(uv[c], C), uv[c]);
+      BwdElim<T, K, C - 1>::run(pa, uv, lane, dinv);
     }
   }
 };
@@ -159,6 +151,37 @@ __global__ __launch_bounds__(64) void factor_wave_kernel(FactorArgs a) {
       }
     }
   };
+  // the same slab through registers: fetched early, stored late
+  constexpr int NS = ((2 * K + 1) * K + 63) / 64;
+  auto slab_fetch = [&](int R, T (&nx)[NS]) {
+    int ln = lane;
+    asm volatile("" : "+v"(ln));
+#pragma unroll
+    for (int it = 0; it < NS; ++it) {
+      const int o = ln + 64 * it;
+      const int d = o / K - k, i = o % K;
+      const int lr = R * K + i - g.pad;
+      T v = T(0);
+      if (o < (2 * k + 1) * K) {
+        if (lr < 0) {
+          v = (d == 0) ? T(1) : T(0);
+        } else if (lr < g.nj) {
+          const int lc = lr + d;
+          if (lc >= 0 && lc < g.nj) v = (T)a.bands[(int64_t)(d + k) * L.n + g.s + lr];
+        }
+      }
+      nx[it] = v;
+    }
+  };
+  auto slab_put = [&](const T (&nx)[NS]) {
+    int ln = lane;
+    asm volatile("" : "+v"(ln));
+#pragma unroll
+    for (int it = 0; it < NS; ++it) {
+      const int o = ln + 64 * it;
+      if (o < (2 * k + 1) * K) slab[o + (K - k) * K] = nx[it];
+    }
+  };
   auto sl = [&](int i, int d) -> T { return (d >= -K && d <= K) ? slab[(d + K) * K + i] : T(0); };
   auto for_elems = [&](auto&& fn) {  // (t, ct, v, row, col) of the lane's accumulator elements
 #pragma unroll
@@ -214,6 +237,9 @@ __global__ __launch_bounds__(64) void factor_wave_kernel(FactorArgs a) {
     const bool last = (b == nb - 1);
     const int nr = last ? K : 2 * K;
     asm volatile("" : "+v"(lane));  // (same: no lane-derived values kept across blocks)
+    // band slab of block b + 2 fetched now, written to LDS once this block is done with the slab
+    T nx[NS];
+    if (b + 2 < nb) slab_fetch(b + 2, nx);
     // ---- panel [Dc_b; Lo_{b+1}]: lane i < K takes row i of Dc_b (lib), lane K + i
     // row i of Lo_{b+1} (slab)
     {
@@ -228,8 +254,8 @@ __global__ __launch_bounds__(64) void factor_wave_kernel(FactorArgs a) {
         pa[c] = v;
         iv[c] = T(0);
       }
-      T mx = T(0), dmin = T(1e30);
-      FwdElim<T, K, 0>::run(pa, iv, prow, lane, nr, mx, dmin);
+      T mx = T(0), dmin = T(1e30), dinv = T(0);
+      FwdElim<T, K, 0>::run(pa, iv, lane, nr, mx, dmin, dinv);
       const bool ok = !__any(!(mx <= T(1))) && (dmin > T(0));
       if (!ok) {
         if (lane == 0) npv[j] = 1;
@@ -247,7 +273,7 @@ __global__ __launch_bounds__(64) void factor_wave_kernel(FactorArgs a) {
       // U11^{-1} rows, then lib <- U11^{-1} on and above the diagonal
 #pragma unroll
       for (int c = 0; c < K; ++c) iv[c] = (c == lane) ? T(1) : T(0);
-      BwdElim<T, K, K - 1>::run(pa, iv, prow, lane);
+      BwdElim<T, K, K - 1>::run(pa, iv, lane, dinv);
       if (lane < K)
 #pragma unroll
         for (int c = 0; c < K; ++c)
@@ -310,7 +336,7 @@ __global__ __launch_bounds__(64) void factor_wave_kernel(FactorArgs a) {
         uc[t][ct][v] = sl(row, K + col - row);
       });
       wave_sync();
-      if (b + 2 < nb) slab_load(b + 2);
+      if (b + 2 < nb) slab_put(nx);
       wave_sync();
     } else {
       for (int o = lane; o < K * K; o += 64) {
