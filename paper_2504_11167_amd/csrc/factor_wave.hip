@@ -151,35 +151,32 @@ __global__ __launch_bounds__(64) void factor_wave_kernel(FactorArgs a) {
       }
     }
   };
-  // the same slab through registers: fetched early, stored late
-  constexpr int NS = ((2 * K + 1) * K + 63) / 64;
+  // The same slab through registers: fetched early, stored late.  With
+  // K >= 16 one pass of 64 lanes covers DPI = 64 / K whole diagonals, so a
+  // lane keeps one row i = lane mod K and walks the diagonals lane / K + DPI it.
+  // The loads are unconditional from clamped (always valid) addresses, so
+  // that they issue back to back; the identity rows, the entries outside the
+  // partition and the padding diagonals are applied when the slab is stored.
+  constexpr int NS = ((2 * K + 1) * K + 63) / 64, DPI = 64 / K;
   auto slab_fetch = [&](int R, T (&nx)[NS]) {
     int ln = lane;
     asm volatile("" : "+v"(ln));
+    const int i = ln % K, dd0 = ln / K;
+    const int lr = min(max(R * K + i - g.pad, 0), g.nj - 1);
+    const double* src = a.bands + g.s + lr;
 #pragma unroll
-    for (int it = 0; it < NS; ++it) {
-      const int o = ln + 64 * it;
-      const int d = o / K - k, i = o % K;
-      const int lr = R * K + i - g.pad;
-      T v = T(0);
-      if (o < (2 * k + 1) * K) {
-        if (lr < 0) {
-          v = (d == 0) ? T(1) : T(0);
-        } else if (lr < g.nj) {
-          const int lc = lr + d;
-          if (lc >= 0 && lc < g.nj) v = (T)a.bands[(int64_t)(d + k) * L.n + g.s + lr];
-        }
-      }
-      nx[it] = v;
-    }
+    for (int it = 0; it < NS; ++it) nx[it] = (T)src[(int64_t)min(dd0 + DPI * it, 2 * k) * L.n];
   };
-  auto slab_put = [&](const T (&nx)[NS]) {
+  auto slab_put = [&](int R, const T (&nx)[NS]) {
     int ln = lane;
     asm volatile("" : "+v"(ln));
+    const int i = ln % K, dd0 = ln / K, lr = R * K + i - g.pad;
+    T* dst = slab + (K - k) * K + ln;
 #pragma unroll
     for (int it = 0; it < NS; ++it) {
-      const int o = ln + 64 * it;
-      if (o < (2 * k + 1) * K) slab[o + (K - k) * K] = nx[it];
+      const int dd = dd0 + DPI * it, d = dd - k, lc = lr + d;
+      const T v = lr < 0 ? ((d == 0) ? T(1) : T(0)) : ((lr < g.nj && lc >= 0 && lc < g.nj) ? nx[it] : T(0));
+      if (dd < 2 * k + 1) dst[64 * it] = v;
     }
   };
   auto sl = [&](int i, int d) -> T { return (d >= -K && d <= K) ? slab[(d + K) * K + i] : T(0); };
@@ -237,9 +234,7 @@ __global__ __launch_bounds__(64) void factor_wave_kernel(FactorArgs a) {
     const bool last = (b == nb - 1);
     const int nr = last ? K : 2 * K;
     asm volatile("" : "+v"(lane));  // (same: no lane-derived values kept across blocks)
-    // band slab of block b + 2 fetched now, written to LDS once this block is done with the slab
-    T nx[NS];
-    if (b + 2 < nb) slab_fetch(b + 2, nx);
+    T nx[NS];  // band slab of block b + 2, fetched below and stored once this block is done with the slab
     // ---- panel [Dc_b; Lo_{b+1}]: lane i < K takes row i of Dc_b (lib), lane K + i
     // row i of Lo_{b+1} (slab)
     {
@@ -254,6 +249,7 @@ __global__ __launch_bounds__(64) void factor_wave_kernel(FactorArgs a) {
         pa[c] = v;
         iv[c] = T(0);
       }
+      if (b + 2 < nb) slab_fetch(b + 2, nx);
       T mx = T(0), dmin = T(1e30), dinv = T(0);
       FwdElim<T, K, 0>::run(pa, iv, lane, nr, mx, dmin, dinv);
       const bool ok = !__any(!(mx <= T(1))) && (dmin > T(0));
@@ -311,11 +307,16 @@ __global__ __launch_bounds__(64) void factor_wave_kernel(FactorArgs a) {
     }
     // ---- stores: LP, pivots, flags
     T* rec = fac + (size_t)b * L.rec;
-    for (int o = lane; o < K * K; o += 64) {
-      int i, c;
-      fidx_inv<T, K>(o, i, c);
-      rec[o] = (i > c) ? lib[i * PT + c] : (last ? T(0) : l21b[i * PT + c]);
-    }
+    // fragment order: position 64 f + lane holds element (16 t + lane mod 16,
+    // frag_k(step, lane / 16)) with f = t KS + step
+    auto frag_store = [&](T* dst, auto&& val) {
+#pragma unroll
+      for (int f = 0; f < K * K / 64; ++f) {
+        const int i = 16 * (f / KS) + (lane & 15), c = frag_k<T>(f % KS, lane >> 4);
+        dst[64 * f + lane] = val(i, c);
+      }
+    };
+    frag_store(rec, [&](int i, int c) { return (i > c) ? lib[i * PT + c] : (last ? T(0) : l21b[i * PT + c]); });
     if (lane < K) ipv[(size_t)b * K + lane] = lane;
     if (lane == 0) flg[b] = 0;
     wave_sync();
@@ -323,11 +324,7 @@ __global__ __launch_bounds__(64) void factor_wave_kernel(FactorArgs a) {
       // U12 staged row-major in l21b (L21 no longer needed), then UP = U11^{-1} | U12
       for_elems([&](int t, int ct, int v, int row, int col) { l21b[row * PT + col] = u12[t][ct][v]; });
       wave_sync();
-      for (int o = lane; o < K * K; o += 64) {
-        int i, c;
-        fidx_inv<T, K>(o, i, c);
-        rec[K * K + o] = (i <= c) ? lib[i * PT + c] : l21b[i * PT + c];
-      }
+      frag_store(rec + K * K, [&](int i, int c) { return (i <= c) ? lib[i * PT + c] : l21b[i * PT + c]; });
       if (lane < K) rec[2 * K * K + lane] = l21b[lane * PT + lane];
       wave_sync();
       // next state: Dc_{b+1} -> lib, Up_{b+1} -> uc, W window shifts, next slab
@@ -336,14 +333,10 @@ __global__ __launch_bounds__(64) void factor_wave_kernel(FactorArgs a) {
         uc[t][ct][v] = sl(row, K + col - row);
       });
       wave_sync();
-      if (b + 2 < nb) slab_put(nx);
+      if (b + 2 < nb) slab_put(b + 2, nx);
       wave_sync();
     } else {
-      for (int o = lane; o < K * K; o += 64) {
-        int i, c;
-        fidx_inv<T, K>(o, i, c);
-        rec[K * K + o] = (i <= c) ? lib[i * PT + c] : T(0);
-      }
+      frag_store(rec + K * K, [&](int i, int c) { return (i <= c) ? lib[i * PT + c] : T(0); });
       if (lane < K) rec[2 * K * K + lane] = T(0);
     }
   }
