@@ -251,7 +251,9 @@ __global__ __launch_bounds__(64) void factor_wave_kernel(FactorArgs a) {
       }
       if (b + 2 < nb) slab_fetch(b + 2, nx);
       T mx = T(0), dmin = T(1e30), dinv = T(0);
-      FwdElim<T, K, 0>::run(pa, iv, lane, nr, mx, dmin, dinv);
+      int ln1 = lane;  // own opaque lane index (its masks are not kept for later use)
+      asm volatile("" : "+v"(ln1));
+      FwdElim<T, K, 0>::run(pa, iv, ln1, nr, mx, dmin, dinv);
       const bool ok = !__any(!(mx <= T(1))) && (dmin > T(0));
       if (!ok) {
         if (lane == 0) npv[j] = 1;
@@ -266,10 +268,13 @@ __global__ __launch_bounds__(64) void factor_wave_kernel(FactorArgs a) {
 #pragma unroll
         for (int c = 0; c < K; ++c) l21b[(lane - K) * PT + c] = pa[c];
       }
-      // U11^{-1} rows, then lib <- U11^{-1} on and above the diagonal
+      // U11^{-1} rows, then lib <- U11^{-1} on and above the diagonal (a fresh
+      // opaque lane index: lane masks are not shared with the forward pass)
+      int ln2 = lane;
+      asm volatile("" : "+v"(ln2));
 #pragma unroll
-      for (int c = 0; c < K; ++c) iv[c] = (c == lane) ? T(1) : T(0);
-      BwdElim<T, K, K - 1>::run(pa, iv, lane, dinv);
+      for (int c = 0; c < K; ++c) iv[c] = (c == ln2) ? T(1) : T(0);
+      BwdElim<T, K, K - 1>::run(pa, iv, ln2, dinv);
       if (lane < K)
 #pragma unroll
         for (int c = 0; c < K; ++c)
