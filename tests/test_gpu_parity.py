@@ -323,3 +323,29 @@ def test_batched_rejects_bad_descriptors(gpu):
     with pytest.raises(gpu.LRSpikeError) as e:
         gpu.factor_batched([(500, 4, 100, 2, 1, 0, 0)], tb)  # n / p < 2k
     assert e.value.code == -2
+
+
+def test_gradient_workload_full_size(gpu):
+    """The gradient workload's shape (n = 2^20, k = 16, p = 256, r = 8, one
+    right-hand side): forward and adjoint solves against the oracle, and the
+    dot-product identity <M^{-1} f, g> = <f, M^{-T} g> at scale."""
+    n, k, p, r = 1 << 20, 16, 256, 8
+    bands, f = synth.make_problem(n, k, 1, seed=0, rule="strict")
+    g = np.random.default_rng(1).standard_normal((n, 1))
+    tb = to_dev(bands)
+    plan = gpu.factor(tb, p, r, max_nrhs=1)
+    x = plan.solve(to_dev(f)).cpu().numpy()
+    lam = plan.solve_adjoint(to_dev(g)).cpu().numpy()
+    plan.status()
+    assert rel(x, oracle.lrspike(bands, f, p, r)) <= 1e-12
+    assert rel(lam, oracle.lrspike(bands, g, p, r, transpose=True)) <= 1e-12
+    lhs, rhs_ = float(x[:, 0] @ g[:, 0]), float(f[:, 0] @ lam[:, 0])
+    assert abs(lhs - rhs_) <= 1e-13 * (np.linalg.norm(x) * np.linalg.norm(g))
+
+
+@pytest.mark.parametrize("n,k,p,r", [(1, 1, 1, 1), (2, 1, 1, 0), (16, 8, 1, 8), (8, 4, 1, 2)])
+def test_tiny_systems(gpu, n, k, p, r):
+    """Degenerate sizes: a 1 x 1 system, n = K with a single partition."""
+    bands, f = synth.make_problem(n, k, 2, seed=n + k, rule="strict")
+    x, _ = run(gpu, bands, f, p, r)
+    assert rel(x, oracle.band_solve(bands, f)) <= 1e-12
