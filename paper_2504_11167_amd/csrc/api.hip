@@ -21,6 +21,7 @@ struct RedArgs;
 #include "reduced.hip"
 #include "solve.hip"
 #include "factor_wave.hip"
+#include "factor_lds.hip"
 
 using namespace lrs;
 
@@ -147,9 +148,19 @@ int run_factor(lrspike_plan P) {
   const Layout& L = P->L;
   FactorArgs fa{P->bands, P->ws, L};
   hipStream_t st = P->stream;
-  size_t b1 = lds_p1<T, K>();
-  if (!set_lds((const void*)factor_pass1<T, K>, b1)) return LRSPIKE_ERR_NOT_SUPPORTED;
-  if constexpr (K >= 16) {
+  size_t b1 = 0;
+  if constexpr (K <= 32) {
+    b1 = lds_p1<T, K>();
+    if (!set_lds((const void*)factor_pass1<T, K>, b1)) return LRSPIKE_ERR_NOT_SUPPORTED;
+  }
+  if constexpr (K == 64) {
+    // workgroup kernels with every block in LDS (no interchanges at this width)
+    const size_t bf = (size_t)FLds<T, K>::total * sizeof(T), bs = (size_t)SLds<T, K>::total * sizeof(T);
+    if (!set_lds((const void*)factor_lds_kernel<T, K>, bf) || !set_lds((const void*)spike_lds_kernel<T, K>, bs))
+      return LRSPIKE_ERR_NOT_SUPPORTED;
+    LRS_LAUNCH("factor_pass1", factor_lds_kernel<T, K>, dim3(L.p), dim3(LRS_NT), bf, fa);
+    LRS_LAUNCH("spike_fwd", spike_lds_kernel<T, K>, dim3(L.p, 2, K / SLds<T, K>::MS), dim3(LRS_NT), bs, fa);
+  } else if constexpr (K >= 16) {
     // one wave per partition without interchanges; partitions that need them
     // are flagged and refactored by the general kernel (a no-op elsewhere)
     LRS_LAUNCH("zero_kernel", zero_kernel, dim3((L.p + 255) / 256), dim3(256), 0,
@@ -164,9 +175,14 @@ int run_factor(lrspike_plan P) {
   } else {
     LRS_LAUNCH("factor_pass1", factor_pass1<T, K>, dim3(L.p), dim3(LRS_NT), b1, fa);
   }
+  (void)b1;
   RedArgs ra{P->ws, L, 0, 0, 0};
   if (L.r < L.K) {
-    if constexpr (K >= 16) {
+    if constexpr (K == 64) {
+      const size_t b2 = (size_t)4 * K * (K + 1) * sizeof(T);
+      if (!set_lds((const void*)pass2_lds_kernel<T, K>, b2)) return LRSPIKE_ERR_NOT_SUPPORTED;
+      LRS_LAUNCH("factor_pass2", pass2_lds_kernel<T, K>, dim3(L.p, 2), dim3(LRS_NT), b2, fa);
+    } else if constexpr (K >= 16) {
       LRS_LAUNCH("factor_pass2", pass2_wave_kernel<T, K>, dim3(L.p, 2), dim3(64), 0, fa);
     } else {
       size_t b2 = lds_p2<T, K>();
@@ -174,7 +190,9 @@ int run_factor(lrspike_plan P) {
       LRS_LAUNCH("factor_pass2", factor_pass2<T, K>, dim3(L.p), dim3(LRS_NT), b2, fa);
     }
     if (L.r > 0) {
-      LRS_LAUNCH("eigen_kernel", eigen_kernel<K>, dim3(L.p, 2), dim3(LRS_NT), 0, ra);
+      const size_t be = (size_t)2 * K * (K + 1) * 8;
+      if (!set_lds((const void*)eigen_kernel<K>, be)) return LRSPIKE_ERR_NOT_SUPPORTED;
+      LRS_LAUNCH("eigen_kernel", eigen_kernel<K>, dim3(L.p, 2), dim3(LRS_NT), be, ra);
       }
   } else {
     LRS_LAUNCH("identity_proj_kernel", identity_proj_kernel<K>, dim3(L.p), dim3(256), 0, ra);
@@ -239,12 +257,12 @@ int run_apply(lrspike_plan P, double* rhs, int m, int transpose) {
   const Layout& L = P->L;
   hipStream_t st = P->stream;
   SolveArgs sa{P->bands, P->ws, L, rhs, rhs, m, m};
-  dim3 grid(L.p, (m + MC - 1) / MC);
+  dim3 grid(L.p, (m + mc_of<K>() - 1) / mc_of<K>());
   size_t bs = lds_sw<T, K>();
   int rc;
-  if (!transpose && K >= 16 && P->wave) {
+  if (!transpose && K >= 16 && K <= 32 && P->wave) {
     // matrix-core sweeps: one wave per partition and column chunk
-    if constexpr (K >= 16) {
+    if constexpr (K >= 16 && K <= 32) {
       const bool one = m <= 16;
       dim3 gw(L.p, one ? 1 : (m + 31) / 32);
       const size_t bw = one ? (size_t)WaveSweep<T, K, 1>::total * sizeof(T) + 2 * K * sizeof(int)
@@ -351,6 +369,7 @@ factor_fn pick_factor(int K) {
     case 8: return run_factor<T, 8>;
     case 16: return run_factor<T, 16>;
     case 32: return run_factor<T, 32>;
+    case 64: return run_factor<T, 64>;
   }
   return nullptr;
 }
@@ -364,6 +383,7 @@ apply_fn pick_apply(int K) {
     case 8: return REF ? run_refined<T, 8> : run_apply<T, 8>;
     case 16: return REF ? run_refined<T, 16> : run_apply<T, 16>;
     case 32: return REF ? run_refined<T, 32> : run_apply<T, 32>;
+    case 64: return REF ? run_refined<T, 64> : run_apply<T, 64>;
   }
   return nullptr;
 }
@@ -431,7 +451,7 @@ int lrspike_factor(int64_t n, int32_t k, const double* bands, int32_t p, int32_t
   if (njmin < K) return -4;
   if (opts->precision != LRSPIKE_FP64 && opts->precision != LRSPIKE_FP32_REFINED) return -6;
   if (opts->max_nrhs < 1) return -6;
-  if (K > 32) return LRSPIKE_ERR_NOT_SUPPORTED;
+  if (K > 64) return LRSPIKE_ERR_NOT_SUPPORTED;
   // reduced-system blocks of order 2r are inverted in one workgroup's LDS
   if (p > 1 && 2 * ((r == k) ? K : r) > 64) return LRSPIKE_ERR_NOT_SUPPORTED;
   lrspike_plan P = new lrspike_plan_s();
@@ -605,7 +625,7 @@ int lrspike_factor_batched(int32_t count, const lrspike_batch_desc* descs, const
     const int K = kernel_K(d.k);
     const int64_t minrows = std::max<int64_t>(2 * (int64_t)d.k, K);
     if ((d.p > 0 ? d.n / d.p : d.n) < minrows) return -2;
-    if (K > 32 || 2 * ((d.r == d.k) ? K : d.r) > 64) return LRSPIKE_ERR_NOT_SUPPORTED;
+    if (K > 64 || 2 * ((d.r == d.k) ? K : d.r) > 64) return LRSPIKE_ERR_NOT_SUPPORTED;
   }
   lrspike_plan P = new lrspike_plan_s();
   P->batch = new BatchState();

@@ -47,7 +47,9 @@ template <int K>
 __global__ __launch_bounds__(LRS_NT) void eigen_kernel(RedArgs a) {
   constexpr int LD = K + 1;
   constexpr int KE = (K % 2) ? K + 1 : K;  // players in the tournament
-  __shared__ double G[K * LD], V[K * LD];
+  extern __shared__ __align__(16) double eig_lds[];  // G and V, K x LD each (dynamic: 66.5 KB at K = 64)
+  double* G = eig_lds;
+  double* V = eig_lds + K * LD;
   __shared__ double cs[KE / 2], sn[KE / 2];
   __shared__ int pa[KE / 2], pb[KE / 2];
   __shared__ int order[K];

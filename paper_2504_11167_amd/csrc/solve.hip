@@ -8,7 +8,7 @@
 //              (eqs. recovery1, recovery2 with the signs restored), in place.
 //   adjoint    nu_j = A_j^{-T} g_j (tips), and
 //              lambda_j = A_j^{-T} (g_j - [w_{j,t}; 0; w_{j,b}]).
-// One workgroup per (partition, chunk of <= MC right-hand-side columns).
+// One workgroup per (partition, chunk of <= mc_of<K>() right-hand-side columns).
 #include "sweep.h"
 
 namespace lrs {
@@ -25,7 +25,7 @@ struct SolveArgs {
 
 template <int K>
 struct SwLds {
-  static constexpr int LDK = K + 1, LDM = MC + 1;
+  static constexpr int LDK = K + 1, LDM = mc_of<K>() + 1;
   static constexpr int oW = 0;                  // [2K][LDM] window / x_b, x_{b+1}
   static constexpr int oW2 = oW + 2 * K * LDM;  // [K][LDM]  x_{b+2} / z_b
   static constexpr int oTmp = oW2 + K * LDM;    // [2K][LDM]
@@ -43,7 +43,7 @@ struct SwLds {
 template <typename T, int K>
 __device__ inline T rhs_at(const SolveArgs& a, const Geom& g, int q, int c, int c0, const T* Ct,
                            const T* Cb) {
-  constexpr int LDM = MC + 1;
+  constexpr int LDM = mc_of<K>() + 1;
   int lr = q - g.pad;
   if (lr < 0 || lr >= g.nj) return T(0);
   T v = (T)a.src[(g.s + lr) * (int64_t)a.ld + c0 + c];
@@ -58,7 +58,7 @@ __device__ inline T rhs_at(const SolveArgs& a, const Geom& g, int q, int c, int 
 // with a_i = z_i[0:r] (i <= p-2) and c_i = z_{i-1}[r:2r] (i >= 1).
 template <typename T, int K>
 __device__ inline void interface_tip(const SolveArgs& a, int i, bool top, int c0, int mc, T* X) {
-  constexpr int LDM = MC + 1;
+  constexpr int LDM = mc_of<K>() + 1;
   const Layout& L = a.L;
   const int r = L.r;
   const double* yt = wsp<double>(a.ws, L.ytip) + ((size_t)i * 2 + (top ? 0 : 1)) * K * L.mmax;
@@ -105,7 +105,7 @@ __device__ void forward_pass(const SolveArgs& a, const Geom& g, int j, int c0, i
   const T* gm = wsp<T>(a.ws, L.gmat) + (size_t)j * L.nbmax * K * K;
   const int* ipv = wsp<int>(a.ws, L.ipiv) + (size_t)j * L.nbmax * K;
   const int* flg = wsp<int>(a.ws, L.flag) + (size_t)j * L.nbmax;
-  constexpr int NACC = (K * MC + LRS_NT - 1) / LRS_NT;
+  constexpr int NACC = (K * mc_of<K>() + LRS_NT - 1) / LRS_NT;
   double acc[NACC];
 #pragma unroll
   for (int t = 0; t < NACC; ++t) acc[t] = 0.0;
@@ -247,8 +247,8 @@ __global__ __launch_bounds__(LRS_NT) void dstage_kernel(SolveArgs a) {
   extern __shared__ __align__(16) unsigned char lds_raw[];
   __shared__ int s_perm[2 * K];
   T* lds = reinterpret_cast<T*>(lds_raw);
-  const int j = blockIdx.x, c0 = blockIdx.y * MC;
-  const int mc = min(MC, a.m - c0);
+  const int j = blockIdx.x, c0 = blockIdx.y * mc_of<K>();
+  const int mc = min(mc_of<K>(), a.m - c0);
   const Geom g = part_geom(a.L, j, K);
   forward_pass<T, K, true>(a, g, j, c0, mc, lds, nullptr, nullptr, s_perm);
 }
@@ -262,8 +262,8 @@ __global__ __launch_bounds__(LRS_NT) void retrieve_kernel(SolveArgs a) {
   __shared__ int s_perm[2 * K];
   T* lds = reinterpret_cast<T*>(lds_raw);
   const Layout& L = a.L;
-  const int j = blockIdx.x, c0 = blockIdx.y * MC;
-  const int mc = min(MC, a.m - c0);
+  const int j = blockIdx.x, c0 = blockIdx.y * mc_of<K>();
+  const int mc = min(mc_of<K>(), a.m - c0);
   const Geom g = part_geom(L, j, K);
   T* Ct = lds + LD::oCt;
   T* Cb = lds + LD::oCb;
@@ -420,8 +420,8 @@ __global__ __launch_bounds__(LRS_NT) void adj_dstage_kernel(SolveArgs a) {
   __shared__ int s_perm[2 * K];
   T* lds = reinterpret_cast<T*>(lds_raw);
   const Layout& L = a.L;
-  const int j = blockIdx.x, c0 = blockIdx.y * MC;
-  const int mc = min(MC, a.m - c0);
+  const int j = blockIdx.x, c0 = blockIdx.y * mc_of<K>();
+  const int mc = min(mc_of<K>(), a.m - c0);
   const Geom g = part_geom(L, j, K);
   tforward_pass<T, K>(a, g, j, c0, mc, lds, nullptr, nullptr);
   __syncthreads();
@@ -447,8 +447,8 @@ __global__ __launch_bounds__(LRS_NT) void adj_retrieve_kernel(SolveArgs a) {
   __shared__ int s_perm[2 * K];
   T* lds = reinterpret_cast<T*>(lds_raw);
   const Layout& L = a.L;
-  const int j = blockIdx.x, c0 = blockIdx.y * MC;
-  const int mc = min(MC, a.m - c0);
+  const int j = blockIdx.x, c0 = blockIdx.y * mc_of<K>();
+  const int mc = min(mc_of<K>(), a.m - c0);
   const Geom g = part_geom(L, j, K);
   T* Ct = lds + LD::oCt;
   T* Cb = lds + LD::oCb;

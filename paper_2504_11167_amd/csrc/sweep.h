@@ -14,7 +14,11 @@
 
 namespace lrs {
 
-constexpr int MC = 32;  // right-hand-side columns per workgroup
+constexpr int MC = 32;  // right-hand-side columns per workgroup (K <= 32)
+// columns per workgroup of the generic sweeps: fewer at K = 64 so that the
+// three K x K factor blocks and the strips fit in LDS
+template <int K>
+constexpr int mc_of() { return K <= 32 ? MC : 8; }
 
 template <typename T>
 __device__ inline T* wsp(char* ws, size_t off) {

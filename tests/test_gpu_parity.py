@@ -349,3 +349,48 @@ def test_tiny_systems(gpu, n, k, p, r):
     bands, f = synth.make_problem(n, k, 2, seed=n + k, rule="strict")
     x, _ = run(gpu, bands, f, p, r)
     assert rel(x, oracle.band_solve(bands, f)) <= 1e-12
+
+
+@pytest.mark.parametrize("n,k,p,r,m", [
+    (4000, 64, 4, 32, 3),    # K = 64 with the Gram eigensolver and back-sweeps
+    (4000, 64, 5, 8, 2),
+    (2600, 50, 4, 25, 5),    # k padded to 64
+    (1000, 64, 1, 64, 2),    # a single partition: the exact band solve
+    (1200, 40, 2, 20, 1),    # padded, p = 2
+])
+def test_k64_matches_oracle(gpu, n, k, p, r, m):
+    bands, f = synth.make_problem(n, k, m, seed=n + k, rule="strict")
+    x, _ = run(gpu, bands, f, p, r)
+    assert rel(x, oracle.lrspike(bands, f, p, r)) <= 1e-12
+    xa, _ = run(gpu, bands, f, p, r, adjoint=True)
+    assert rel(xa, oracle.lrspike(bands, f, p, r, transpose=True)) <= 1e-12
+
+
+def test_k64_refined(gpu):
+    bands, f = synth.make_problem(4000, 64, 2, seed=9, rule="strict")
+    x, info = run(gpu, bands, f, 4, 32, precision="fp32_refined")
+    assert info["refine_iters"] >= 1
+    assert rel(x, oracle.band_solve_refined(bands, f)) <= 1e-11
+
+
+def test_k64_interchanges_reported_unsupported(gpu):
+    """At K = 64 partitions are factored without interchanges; one that would
+    need them latches NOT_SUPPORTED with its partition instead of a wrong result."""
+    bands, f = synth.make_problem(3000, 64, 1, seed=4, rule="theta", theta=0.05)
+    plan = gpu.factor(to_dev(bands), 3, 16, max_nrhs=1)
+    with pytest.raises(gpu.LRSpikeError) as e:
+        plan.status()
+    assert e.value.code == 6
+    assert 0 <= e.value.info["partition"] < 3
+
+
+def test_batched_with_k64_systems(gpu):
+    bl, fl = _batch(9, 3, ks=(4, 16, 64), nmax=6000)
+    bands, rhs, descs = gpu.pack_systems(bl, fl)
+    assert any(d[1] == 64 for d in descs)
+    plan = gpu.factor_batched(descs, to_dev(bands))
+    tr = to_dev(rhs)
+    plan.run(tr)
+    plan.status()
+    for s, xs in enumerate(_unpack(tr.cpu().numpy(), descs)):
+        assert rel(xs, oracle.lrspike(bl[s], fl[s], plan.partitions()[s], descs[s][3])) <= 1e-12, s
