@@ -1,13 +1,15 @@
 // Factorization for K = 64: one 256-thread workgroup per partition with every
 // K x K block resident in LDS (the single-wave kernels keep a 2K-row panel in
-// one wave's registers, which does not fit at this width).
+// one wave's registers, which does not fit at this width).  Uses the register
+// elimination steps FwdElim / BwdElim of the single-wave factor kernel.
 //
 // Per K-row block b (the same block formulation as the other factor kernels):
-//   panel [Dc_b; Lo_{b+1}] eliminated in place without interchanges; a
-//   multiplier above 1 in magnitude means partial pivoting would interchange
-//   rows, which this width does not support: NOT_SUPPORTED is latched for the
-//   partition;
-//   L11^{-1} and U11^{-1} in place by row sweeps;  U12 = L11^{-1} Up_b;
+//   panel [Dc_b; Lo_{b+1}] factored without interchanges, the diagonal block
+//   as 2 x 2 blocks of K/2 (register elimination of the K/2-column panels by
+//   one wave, block products by the workgroup), giving L11^{-1}, U11^{-1} and
+//   L21 = Lo_{b+1} U11^{-1}; a multiplier above 1 in magnitude means partial
+//   pivoting would interchange rows, which this width does not support:
+//   NOT_SUPPORTED is latched for the partition;  U12 = L11^{-1} Up_b;
 //   G step g_b = U11^{-T}(e_b + pending), pending = -U12^T g_b;
 //   records in the fragment order the sweeps read;  Dc_{b+1} = D_{b+1} - L21 U12.
 // The spikes are formed afterwards from the records (spike_lds_kernel) and,
@@ -28,6 +30,7 @@ struct LdsTile {
 template <int K, typename FA, typename FB>
 __device__ __forceinline__ void tile_mm(double (&acc)[4][4], FA a, FB b) {
   const int i0 = LdsTile<K>::i0(), j0 = LdsTile<K>::j0();
+#pragma unroll 4
   for (int l = 0; l < K; ++l) {
     double av[4], bv[4];
 #pragma unroll
@@ -45,6 +48,25 @@ __device__ __forceinline__ void tile_zero(double (&acc)[4][4]) {
   for (int u = 0; u < 4; ++u)
 #pragma unroll
     for (int v = 0; v < 4; ++v) acc[u][v] = 0.0;
+}
+
+// acc (2 x 2, this thread's tile of an N x N result, N = 32) += sum_{l<N} a(i, l) b(l, j)
+template <int N, typename FA, typename FB>
+__device__ __forceinline__ void tile2_mm(double (&acc)[2][2], FA a, FB b) {
+  static_assert(N == 32, "one 2 x 2 tile per thread of a 256-thread workgroup");
+  const int i0 = 2 * (threadIdx.x >> 4), j0 = 2 * (threadIdx.x & 15);
+#pragma unroll 8
+  for (int l = 0; l < N; ++l) {
+    const double a0 = (double)a(i0, l), a1 = (double)a(i0 + 1, l);
+    const double b0 = (double)b(l, j0), b1 = (double)b(l, j0 + 1);
+    acc[0][0] = fma(a0, b0, acc[0][0]);
+    acc[0][1] = fma(a0, b1, acc[0][1]);
+    acc[1][0] = fma(a1, b0, acc[1][0]);
+    acc[1][1] = fma(a1, b1, acc[1][1]);
+  }
+}
+__device__ __forceinline__ void tile_zero2(double (&acc)[2][2]) {
+  acc[0][0] = acc[0][1] = acc[1][0] = acc[1][1] = 0.0;
 }
 
 template <typename T, int K>
@@ -83,99 +105,191 @@ __global__ __launch_bounds__(LRS_NT) void factor_lds_kernel(FactorArgs a) {
     if (d < -k || d > k) return T(0);
     return (T)a.bands[(int64_t)(d + k) * L.n + g.s + lr];
   };
-  auto blk = [&](int R, int C, int i, int c) { return Aj(R * K + i - g.pad, C * K + c - g.pad); };
-  for (int o = tid; o < K * K; o += LRS_NT) {
-    const int i = o / K, c = o % K;
-    P[i * PT + c] = blk(0, 0, i, c);
-    Gp[i * PT + c] = T(0);
-  }
+  (void)Aj;
+  // K x K block (rows of block R, columns of block C) into dst (pitch PT).
+  // Lane = block row, so a wave reads one diagonal segment (coalesced); the
+  // waves take every fourth diagonal offset e = c - i; every load is issued
+  // (from a clamped, always valid address) before any store.
+  auto load_block = [&](T* dst, int R, int C) {
+    constexpr int NI = (2 * K - 1 + 3) / 4;
+    int i = tid & 63;  // opaque: keeps the per-diagonal addresses from being hoisted out of the block loop
+    asm volatile("" : "+v"(i));
+    const int w = tid >> 6;
+    const int lr = R * K + i - g.pad;
+    T vals[NI];
+#pragma unroll
+    for (int t = 0; t < NI; ++t) {
+      const int e = w + 4 * t - (K - 1), c = i + e, lc = C * K + c - g.pad, d = lc - lr;
+      const bool inb = e <= K - 1 && c >= 0 && c < K && lr >= 0 && lr < g.nj && lc >= 0 && lc < g.nj &&
+                       d >= -k && d <= k;
+      vals[t] = (T)a.bands[inb ? (int64_t)(d + k) * L.n + g.s + lr : 0];
+    }
+#pragma unroll
+    for (int t = 0; t < NI; ++t) {
+      const int e = w + 4 * t - (K - 1), c = i + e, lc = C * K + c - g.pad, d = lc - lr;
+      const bool inb = e <= K - 1 && c >= 0 && c < K && lr >= 0 && lr < g.nj && lc >= 0 && lc < g.nj &&
+                       d >= -k && d <= k;
+      const bool ident = (lr < 0 || lc < 0) && lr == lc;
+      if (e <= K - 1 && c >= 0 && c < K) dst[i * PT + c] = inb ? vals[t] : (ident ? T(1) : T(0));
+    }
+  };
+  load_block(P, 0, 0);
+  for (int o = tid; o < K * K; o += LRS_NT) Gp[(o / K) * PT + o % K] = T(0);
   if (tid == 0) s_bad = 0;
   const int i0 = LdsTile<K>::i0(), j0 = LdsTile<K>::j0();
   for (int b = 0; b < nb; ++b) {
     const bool last = (b == nb - 1);
     const int nr = last ? K : 2 * K;
-    if (!last)
-      for (int o = tid; o < K * K; o += LRS_NT) {
-        const int i = o / K, c = o % K;
-        P[(K + i) * PT + c] = blk(b + 1, b, i, c);
-        U[i * PT + c] = blk(b, b + 1, i, c);
-      }
+    if (!last) {
+      load_block(P + K * PT, b + 1, b);
+      load_block(U, b, b + 1);
+    }
     __syncthreads();
-    // ---- elimination without interchanges: lane = column, wave w rows w + 4q
+    // ---- the diagonal block D (panel top) as 2 x 2 blocks of H = K/2 columns:
+    //   [D11; D21] = [L1; L2'] U1 by the register elimination of one wave
+    //   (lane = row, no interchanges), with L1^{-1} riding along and U1^{-1}
+    //   by the upward Gauss-Jordan pass;  U1' = L1^{-1} D12;  S = D22 - L2' U1';
+    //   S = L2 U2 the same way;  then
+    //   L11^{-1} = [L1^{-1} 0; -L2^{-1} L2' L1^{-1}  L2^{-1}],
+    //   U11^{-1} = [U1^{-1}  -U1^{-1} U1' U2^{-1}; 0  U2^{-1}],
+    //   L21 = Lo U11^{-1}.
+    // These are the factors column-by-column elimination of [Dc_b; Lo_{b+1}]
+    // gives; each multiplier (L1, L2', L2 in the register passes, L21 after its
+    // product) is compared with 1 in magnitude, the same interchange test.
+    // The result is packed in place: L11^{-1} strictly below the diagonal of
+    // the panel top, U11^{-1} on and above it, L21 in the panel bottom.
     {
-      const int lane = tid & 63, w = tid >> 6;
-      for (int C = 0; C < K; ++C) {
-        const T piv = P[C * PT + C];
-        if (tid == 0 && !(piv != T(0))) {
-          s_bad = 1;
-          s_row = b * K + C - g.pad;
-        }
-        for (int i = C + 1 + tid; i < nr; i += LRS_NT) {
-          const T l = P[i * PT + C] / piv;
-          if (!(fabs(l) <= T(1)) && s_bad == 0) {
-            s_bad = 2;
-            s_row = b * K + C - g.pad;
-          }
-          P[i * PT + C] = l;
-        }
-        __syncthreads();
-        const int c = C + 1 + lane;
-        if (c < K) {
-          const T pc = P[C * PT + c];
-          T v[32], l[32];
+      constexpr int H = K / 2;
+      const int lane = tid & 63;
+      // register LU of the H x H block at (r0, r0) and the rows below it
+      // (nrow rows in all), wave 0 only
+      auto reg_lu = [&](int r0, int nrow) {
+        T pa[H], iv[H];
+        const int lr = lane < nrow ? lane : nrow - 1;
 #pragma unroll
-          for (int q = 0; q < 32; ++q) {
-            const int i = C + 1 + w + 4 * q;
-            v[q] = i < nr ? P[i * PT + c] : T(0);
-            l[q] = i < nr ? P[i * PT + C] : T(0);
-          }
-#pragma unroll
-          for (int q = 0; q < 32; ++q) {
-            const int i = C + 1 + w + 4 * q;
-            if (i < nr) P[i * PT + c] = fma(-l[q], pc, v[q]);
-          }
+        for (int c = 0; c < H; ++c) {
+          pa[c] = P[(r0 + lr) * PT + r0 + c];
+          iv[c] = T(0);
         }
+        T mx = T(0), dmin = T(1e30), dinv = T(0);
+        int ln1 = lane;  // opaque lane index (see factor_pass1_wave_kernel)
+        asm volatile("" : "+v"(ln1));
+        FwdElim<T, H, 0>::run(pa, iv, ln1, nrow, mx, dmin, dinv);
+        const unsigned long long zb = __ballot(lane < H && !isfinite(dinv));
+        const unsigned long long bb = __ballot(lane < nrow && !(mx <= T(1)));
+        if (lane == 0 && s_bad == 0 && (zb || bb || !(dmin > T(0)))) {
+          s_bad = (zb || !(dmin > T(0))) ? 1 : 2;
+          s_row = b * K + r0 + (zb ? __ffsll(zb) - 1 : (bb ? __ffsll(bb) - 1 : 0)) - g.pad;
+        }
+        if (lane < H) {
+#pragma unroll
+          for (int c = 0; c < H; ++c)
+            if (c < lane) P[(r0 + lane) * PT + r0 + c] = iv[c];
+        } else if (lane < nrow) {
+#pragma unroll
+          for (int c = 0; c < H; ++c) P[(r0 + lane) * PT + r0 + c] = pa[c];
+        }
+        int ln2 = lane;
+        asm volatile("" : "+v"(ln2));
+#pragma unroll
+        for (int c = 0; c < H; ++c) iv[c] = (c == ln2) ? T(1) : T(0);
+        BwdElim<T, H, H - 1>::run(pa, iv, ln2, dinv);
+        if (lane < H)
+#pragma unroll
+          for (int c = 0; c < H; ++c)
+            if (c >= lane) P[(r0 + lane) * PT + r0 + c] = iv[c];
+      };
+      // unit lower / upper parts of a packed H x H block at (r0, r0); loads
+      // are unconditional (valid addresses) so the products stay branch-free
+      auto lo = [&](int r0, int i, int l) -> T {
+        const T x = P[(r0 + i) * PT + r0 + l];
+        return l < i ? x : (l == i ? T(1) : T(0));
+      };
+      auto up = [&](int r0, int i, int l) -> T {
+        const T x = P[(r0 + i) * PT + r0 + l];
+        return l >= i ? x : T(0);
+      };
+      auto blk = [&](int r0, int c0, int i, int l) -> T { return P[(r0 + i) * PT + c0 + l]; };
+      const int h0 = 2 * (tid >> 4), k0 = 2 * (tid & 15);
+      double a1[2][2], a2[2][2];
+      auto put = [&](double (&acc)[2][2], int r0, int c0, double s) {
+#pragma unroll
+        for (int u = 0; u < 2; ++u)
+#pragma unroll
+          for (int v = 0; v < 2; ++v) P[(r0 + h0 + u) * PT + c0 + k0 + v] = (T)(s * acc[u][v]);
+      };
+      if (tid < 64) reg_lu(0, K);
+      __syncthreads();
+      // U1' = L1^{-1} D12 (in place)
+      tile_zero2(a1);
+      tile2_mm<H>(a1, [&](int i, int l) { return lo(0, i, l); }, [&](int l, int c) { return blk(0, H, l, c); });
+      __syncthreads();
+      put(a1, 0, H, 1.0);
+      __syncthreads();
+      // S = D22 - L2' U1' (reads other quadrants than it writes)
+      tile_zero2(a1);
+      tile2_mm<H>(a1, [&](int i, int l) { return blk(H, 0, i, l); }, [&](int l, int c) { return blk(0, H, l, c); });
+#pragma unroll
+      for (int u = 0; u < 2; ++u)
+#pragma unroll
+        for (int v = 0; v < 2; ++v) P[(H + h0 + u) * PT + H + k0 + v] -= (T)a1[u][v];
+      __syncthreads();
+      if (tid < 64) reg_lu(H, H);
+      __syncthreads();
+      // T1 = L2' L1^{-1},  T2 = U1^{-1} U1'
+      tile_zero2(a1);
+      tile_zero2(a2);
+      tile2_mm<H>(a1, [&](int i, int l) { return blk(H, 0, i, l); }, [&](int l, int c) { return lo(0, l, c); });
+      tile2_mm<H>(a2, [&](int i, int l) { return up(0, i, l); }, [&](int l, int c) { return blk(0, H, l, c); });
+      __syncthreads();
+      put(a1, H, 0, 1.0);
+      put(a2, 0, H, 1.0);
+      __syncthreads();
+      // lower-left of L11^{-1}: -L2^{-1} T1;  upper-right of U11^{-1}: -T2 U2^{-1}
+      tile_zero2(a1);
+      tile_zero2(a2);
+      tile2_mm<H>(a1, [&](int i, int l) { return lo(H, i, l); }, [&](int l, int c) { return blk(H, 0, l, c); });
+      tile2_mm<H>(a2, [&](int i, int l) { return blk(0, H, i, l); }, [&](int l, int c) { return up(H, l, c); });
+      __syncthreads();
+      put(a1, H, 0, -1.0);
+      put(a2, 0, H, -1.0);
+      __syncthreads();
+      // L21 = Lo U11^{-1} (in place in the panel bottom)
+      if (!last) {
+        double acc[4][4];
+        tile_zero(acc);
+        tile_mm<K>(acc, [&](int r, int l) { return P[(K + r) * PT + l]; }, [&](int l, int c) {
+          const T x = P[l * PT + c];
+          return l <= c ? x : T(0);
+        });
         __syncthreads();
+        bool big = false;
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            P[(K + i0 + u) * PT + j0 + v] = (T)acc[u][v];
+            big |= !(fabs(acc[u][v]) <= 1.0);
+          }
+        if (big && s_bad == 0) {  // every writer stores the same values
+          s_bad = 2;
+          s_row = (b + 1) * K - g.pad;
+        }
       }
+      __syncthreads();
     }
     if (s_bad) {
       if (tid == 0) latch_error(latch, s_bad == 1 ? LRSPIKE_ERR_ZERO_PIVOT : LRSPIKE_ERR_NOT_SUPPORTED, j, s_row);
       return;
     }
-    // ---- in-place inverses: L11^{-1} (strict lower, unit diagonal) by rows
-    // top-down and U11^{-1} (upper) by rows bottom-up, both in one loop (the
-    // two touch disjoint triangles); a column is split over four threads of
-    // one wave that reduce with lane shuffles.
-    //   L row i:   X[i][c] = -(L[i][c] + sum_{l=c+1}^{i-1} L[i][l] X[l][c]),  c < i
-    //   U row iu:  X[iu][c] = -(sum_{l=iu+1}^{c} U[iu][l] X[l][c]) / U[iu][iu], c > iu,
-    //              X[iu][iu] = 1 / U[iu][iu]
-    {
-      const int c = tid >> 2, part = tid & 3;
-      if (tid == 0) P[(K - 1) * PT + (K - 1)] = T(1) / P[(K - 1) * PT + (K - 1)];
-      __syncthreads();
-      for (int s = 1; s < K; ++s) {
-        const int i = s, iu = K - 1 - s;
-        T accl = T(0), accu = T(0);
-        if (c < i)
-          for (int l = c + 1 + part; l < i; l += 4) accl = fma(P[i * PT + l], P[l * PT + c], accl);
-        if (c > iu)
-          for (int l = iu + 1 + part; l <= c; l += 4) accu = fma(P[iu * PT + l], P[l * PT + c], accu);
-        accl += __shfl_xor(accl, 1);
-        accl += __shfl_xor(accl, 2);
-        accu += __shfl_xor(accu, 1);
-        accu += __shfl_xor(accu, 2);
-        const T dinv = T(1) / P[iu * PT + iu];
-        __syncthreads();
-        if (part == 0) {
-          if (c < i) P[i * PT + c] = -(P[i * PT + c] + accl);
-          if (c > iu) P[iu * PT + c] = -accu * dinv;
-          if (c == iu) P[iu * PT + iu] = dinv;
-        }
-        __syncthreads();
-      }
-    }
-    auto Li = [&](int r, int l) -> T { return r > l ? P[r * PT + l] : (r == l ? T(1) : T(0)); };
-    auto Ui = [&](int r, int l) -> T { return r <= l ? P[r * PT + l] : T(0); };
+    auto Li = [&](int r, int l) -> T {
+      const T x = P[r * PT + l];
+      return r > l ? x : (r == l ? T(1) : T(0));
+    };
+    auto Ui = [&](int r, int l) -> T {
+      const T x = P[r * PT + l];
+      return r <= l ? x : T(0);
+    };
     double acc[4][4];
     // ---- U12 = L11^{-1} Up_b (in place in U)
     if (!last) {
@@ -230,14 +344,17 @@ __global__ __launch_bounds__(LRS_NT) void factor_lds_kernel(FactorArgs a) {
     // ---- Dc_{b+1} = D_{b+1} - L21 U12 into the panel top
     if (!last) {
       tile_zero(acc);
-      tile_mm<K>(acc, [&](int r, int l) { return r <= l ? P[(K + r) * PT + l] : T(0); },
+      tile_mm<K>(acc, [&](int r, int l) {
+        const T x = P[(K + r) * PT + l];
+        return r <= l ? x : T(0);
+      },
                  [&](int l, int c) { return U[l * PT + c]; });
+      load_block(P, b + 1, b + 1);  // D_{b+1} (the panel top is free once the records are out)
       __syncthreads();
 #pragma unroll
       for (int u = 0; u < 4; ++u)
 #pragma unroll
-        for (int v = 0; v < 4; ++v)
-          P[(i0 + u) * PT + j0 + v] = blk(b + 1, b + 1, i0 + u, j0 + v) - (T)acc[u][v];
+        for (int v = 0; v < 4; ++v) P[(i0 + u) * PT + j0 + v] -= (T)acc[u][v];
       __syncthreads();
     }
   }

@@ -384,6 +384,22 @@ def test_k64_interchanges_reported_unsupported(gpu):
     assert 0 <= e.value.info["partition"] < 3
 
 
+def test_k64_zero_pivot_is_latched(gpu):
+    """A zero row makes A_1 singular: the K = 64 factor reaches an exact zero
+    pivot at that row and latches ZERO_PIVOT with the partition-local row."""
+    n, k, p = 3000, 64, 3
+    bands, f = synth.make_problem(n, k, 1, seed=2, rule="strict")
+    row = 1500  # partition 1 holds rows 1000..1999
+    for d in range(-k, k + 1):
+        bands[d + k, row] = 0.0
+    plan = gpu.factor(to_dev(bands), p, 32, max_nrhs=1)
+    with pytest.raises(gpu.LRSpikeError) as e:
+        plan.status()
+    assert e.value.code == 1
+    assert e.value.info["partition"] == 1
+    assert e.value.info["row"] == row - 1000
+
+
 def test_batched_with_k64_systems(gpu):
     bl, fl = _batch(9, 3, ks=(4, 16, 64), nmax=6000)
     bands, rhs, descs = gpu.pack_systems(bl, fl)
