@@ -28,6 +28,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "banded solve rows×RHS/s + HBM GB/s vs roofline, refined FP32 vs FP64 at rel.err 1e-11"
 HBM_PEAK_GBS = 8000.0
+REFINE_TOL = 1e-12  # refined-vs-FP64 comparison: a decade below the 1e-11 accuracy target
 
 
 def algorithmic_bytes(kernel, n, k, m, r, wf):
@@ -94,11 +95,13 @@ def rel_residual(bands, x, f):
 def refined_vs_fp64(lr, bands, f, x, ws_bytes_fn, p, steps, log):
     """Plain FP64 and FP32-factor + FP64-refinement LR-SPIKE at r = k on the same
     matrix and right-hand sides: whole factor + solve time each, and the accuracy
-    both reach (difference between the two results and relative residuals)."""
+    both reach (difference between the two results and relative residuals).
+    The accuracy target is rel.err <= 1e-11; the refinement runs to a tolerance
+    a decade below it (REFINE_TOL) and the reached accuracy is reported."""
     import torch
     k = (bands.shape[0] - 1) // 2
     m = f.shape[1]
-    out = {"r": k}
+    out = {"r": k, "refine_tol": REFINE_TOL}
     xs = {}
     for prec in ("fp64", "fp32_refined"):
         ws = torch.empty(ws_bytes_fn(prec), dtype=torch.uint8, device=bands.device)
@@ -106,7 +109,7 @@ def refined_vs_fp64(lr, bands, f, x, ws_bytes_fn, p, steps, log):
 
         def once():
             y.copy_(f)
-            plan = lr.Plan(bands, p, k, precision=prec, max_nrhs=m, workspace=ws)
+            plan = lr.Plan(bands, p, k, precision=prec, max_nrhs=m, workspace=ws, refine_tol=REFINE_TOL)
             plan.solve(y, inplace=True)
             return plan
 

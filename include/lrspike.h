@@ -56,17 +56,23 @@ enum {
   LRSPIKE_ERR_NOT_CONVERGED = 3,    /* refinement did not reach refine_tol */
   LRSPIKE_ERR_NONFINITE = 4,        /* Inf/NaN met in the band or the result */
   LRSPIKE_ERR_HIP = 5,              /* a HIP runtime call failed */
-  LRSPIKE_ERR_NOT_SUPPORTED = 6,    /* parameter combination not built (e.g. k > 32 in FP64) */
+  LRSPIKE_ERR_NOT_SUPPORTED = 6,    /* parameter combination not built (k > 64, 2r > 64), or a
+                                       partition at k > 32 that needs row interchanges */
   LRSPIKE_ERR_WORKSPACE = 7         /* workspace missing or too small */
 };
 
 typedef struct {
   int32_t precision;     /* LRSPIKE_FP64 (default) or LRSPIKE_FP32_REFINED */
   int32_t max_refine;    /* FP32_REFINED: max corrections (default 30) */
-  double refine_tol;     /* FP32_REFINED: stop when ||d_c||_2 <= tol ||x_c||_2 for all columns (default 1e-13).
-                            A correction that shrinks by less than half ends the iteration: converged if
-                            it is already <= 100 tol (the rounding level of an ill-conditioned system),
-                            else NOT_CONVERGED is latched */
+  double refine_tol;     /* FP32_REFINED: relative accuracy to reach (default 1e-13).  With
+                            c_i = max over columns of ||d_c||_2 / ||x_c||_2 for correction i, the
+                            iteration stops when c_i <= tol, or when the error left after the update,
+                            estimated as 10 rho c_i, is <= tol, where the contraction rho is
+                            c_i / c_{i-1} (c_0 itself for the first correction, the accuracy of the
+                            FP32 solve) and is trusted only below 1e-2.  A correction that shrinks
+                            by less than half ends the iteration: converged if it is already
+                            <= 100 tol (the rounding level of an ill-conditioned system), else
+                            NOT_CONVERGED is latched */
   void *stream;          /* hipStream_t to enqueue on; NULL = null stream */
   void *workspace;       /* device memory of >= lrspike_workspace_size bytes, caller-owned,
                             must outlive the plan */
@@ -95,13 +101,17 @@ int lrspike_workspace_size(int64_t n, int32_t k, int32_t p, int32_t r,
  * their tips in rank-r form (r = k keeps them whole and the method is exact),
  * and factors the reduced interface system.
  *   n      matrix order, n >= 1
- *   k      half-bandwidth, 1 <= k <= 32 (FP64) or 64 (FP32_REFINED)
+ *   k      half-bandwidth, 1 <= k <= 64.  Blocks are K x K with K the next power
+ *          of two >= k; for K = 64 the partitions are factored without row
+ *          interchanges, and one that would need an interchange (a multiplier
+ *          above 1 in magnitude) latches NOT_SUPPORTED for that partition
  *   bands  device pointer, (2k+1) x n band-major doubles; borrowed: it must
  *          stay valid (unchanged) for the plan's lifetime when precision is
  *          FP32_REFINED (the residual reads it) and for lrspike_band_grad
  *   p      number of partitions, 1 <= p <= n; each partition needs >= 2k rows
  *          when p > 1
- *   r      retained singular values per spike (the paper's n_svd), 0 <= r <= k
+ *   r      retained singular values per spike (the paper's n_svd), 0 <= r <= k;
+ *          with p > 1 the interface blocks need 2r <= 64 (2K <= 64 when r = k)
  *   opts   options; workspace required (see lrspike_workspace_size)
  *   plan_out  receives a new plan (host object) on success
  */
@@ -176,7 +186,7 @@ int lrspike_destroy(lrspike_plan plan);
  */
 typedef struct {
   int64_t n;            /* order, >= 1 */
-  int32_t k;            /* half-bandwidth, 1 <= k <= 32 */
+  int32_t k;            /* half-bandwidth, 1 <= k <= 64 */
   int32_t p;            /* partitions (n / p >= max(2k, K), K = next power of two >= k);
                            0 = chosen by the autotuner */
   int32_t r;            /* retained rank, 0 <= r <= k (2r <= 64) */
@@ -194,7 +204,7 @@ typedef struct {
  * partition count from the autotuner, which times candidate partition sizes
  * (and, for K >= 16, matrix-core against workgroup sweeps) on the systems
  * themselves and keeps the fastest; this synchronizes the stream.
- * Returns -2 for an invalid descriptor, NOT_SUPPORTED for k > 32 or 2r > 64.
+ * Returns -2 for an invalid descriptor, NOT_SUPPORTED for k > 64 or 2r > 64.
  */
 int lrspike_factor_batched(int32_t count, const lrspike_batch_desc *descs, const double *bands_base,
                            const lrspike_opts *opts, lrspike_plan *plan_out);

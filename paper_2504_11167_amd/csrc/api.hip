@@ -338,6 +338,12 @@ int run_refined(lrspike_plan P, double* rhs, int m, int transpose) {
     P->last_corr = worst;
     if (worst <= P->refine_tol) return 0;
     if (!(worst < INFINITY)) break;
+    // linear convergence: the error left after this update is about rho times
+    // the correction, rho the contraction factor (ratio of successive
+    // corrections; for the first one, its own relative size, i.e. the accuracy
+    // of the FP32 solve), with a safety factor of 10
+    const double rho = it == 0 ? worst : worst / prev;
+    if (rho < 1e-2 && 10.0 * rho * worst <= P->refine_tol) return 0;
     if (it > 0 && worst > 0.5 * prev) {
       // the corrections stopped shrinking: the rounding level of an
       // ill-conditioned system when they are already small, else failure
