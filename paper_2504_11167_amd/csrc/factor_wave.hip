@@ -194,23 +194,27 @@ __global__ __launch_bounds__(64) void factor_wave_kernel(FactorArgs a) {
 #pragma unroll
       for (int ct = 0; ct < RT; ++ct) x[t][ct] = V{0, 0, 0, 0};
   };
-  // out (+)= op(A) * in; A operand element (i, kk) from fa(i, kk); B from accumulator tiles
-  auto mul = [&](auto&& fa, const V (&in)[RT][RT], V (&out)[RT][RT], T sign) {
+  // out (+)= op(A) * in; A operand element (i, kk) from fa(i, kk); B from accumulator tiles.
+  // tri: 1 = A lower triangular, 2 = upper (the 16 x 16 tiles it leaves zero are skipped)
+  auto mul = [&](auto&& fa, const V (&in)[RT][RT], V (&out)[RT][RT], T sign, int tri) {
 #pragma unroll
     for (int t = 0; t < RT; ++t)
 #pragma unroll
       for (int step = 0; step < KS; ++step) {
+        if ((tri == 1 && (step >> 2) > t) || (tri == 2 && (step >> 2) < t)) continue;
         const T av = sign * fa(16 * t + (lane & 15), frag_k<T>(step, lane >> 4));
 #pragma unroll
         for (int ct = 0; ct < RT; ++ct) out[t][ct] = mfma_step(av, in[step >> 2][ct][step & 3], out[t][ct]);
       }
   };
-  // out += X^T * in with X in accumulator tiles (tile-transposed A operand)
+  // out += X^T * in with X in accumulator tiles (tile-transposed A operand); X lower
+  // triangular, so X^T leaves the tiles left of the row tile zero
   auto mul_tr = [&](const V (&X)[RT][RT], const V (&in)[RT][RT], V (&out)[RT][RT], T sign) {
 #pragma unroll
     for (int t = 0; t < RT; ++t)
 #pragma unroll
       for (int step = 0; step < KS; ++step) {
+        if ((step >> 2) < t) continue;
         const T av = sign * X[step >> 2][t][step & 3];
 #pragma unroll
         for (int ct = 0; ct < RT; ++ct) out[t][ct] = mfma_step(av, in[step >> 2][ct][step & 3], out[t][ct]);
@@ -288,7 +292,7 @@ __global__ __launch_bounds__(64) void factor_wave_kernel(FactorArgs a) {
     V u12[RT][RT], dn[RT][RT];
     if (!last) {
       zero(u12);
-      mul(Li, uc, u12, T(1));  // U12 = L11^{-1} Up_b
+      mul(Li, uc, u12, T(1), 1);  // U12 = L11^{-1} Up_b
     }
     // ---- G step (the columns of E_t met in this block enter the pending sum)
     {
@@ -297,7 +301,7 @@ __global__ __launch_bounds__(64) void factor_wave_kernel(FactorArgs a) {
         if (col == b * K + row - g.pad) gc[t][ct][v] += T(1);
       });
       zero(gb);
-      mul(UiT, gc, gb, T(1));
+      mul(UiT, gc, gb, T(1), 1);
       zero(gc);
       if (!last) mul_tr(u12, gb, gc, T(-1));  // pending(b+1) = -U12^T g_b
 #pragma unroll
@@ -308,7 +312,7 @@ __global__ __launch_bounds__(64) void factor_wave_kernel(FactorArgs a) {
     }
     if (!last) {
       for_elems([&](int t, int ct, int v, int row, int col) { dn[t][ct][v] = sl(row, col - row); });
-      mul(L21, u12, dn, T(-1));  // Dc_{b+1} = D_{b+1} - L21 U12
+      mul(L21, u12, dn, T(-1), 2);  // Dc_{b+1} = D_{b+1} - L21 U12
     }
     // ---- stores: LP, pivots, flags
     T* rec = fac + (size_t)b * L.rec;

@@ -143,6 +143,9 @@ __device__ void permute_strips(typename WaveSweep<T, K, MCT>::V (&w0)[K / 16][MC
 }
 
 // out[t][ct] (+)= sign * A(kind) * in  for one K x K block; A fragments from frag[].
+// The 16 x 16 tiles a triangular operand leaves zero are skipped (k-steps 4q..4q+3
+// cover columns 16q..16q+15): lower operands (kinds 0, 3) right of the row tile,
+// upper ones (kinds 1, 2) left of it.
 template <typename T, int K, int MCT, int kind>
 __device__ __forceinline__ void blk_mul(const T (&frag)[(K / 16) * (K / 4)], const T* dg, T sign,
                                         const typename WaveSweep<T, K, MCT>::V (&in)[K / 16][MCT],
@@ -152,6 +155,7 @@ __device__ __forceinline__ void blk_mul(const T (&frag)[(K / 16) * (K / 4)], con
   for (int t = 0; t < K / 16; ++t)
 #pragma unroll
     for (int step = 0; step < K / 4; ++step) {
+      if (((kind == 0 || kind == 3) && (step >> 2) > t) || ((kind == 1 || kind == 2) && (step >> 2) < t)) continue;
       const T av = sign * fmask<T, kind>(frag[t * (K / 4) + step], t, step, lane,
                                          kind == 3 ? dg[t * (K / 4) + step] : T(0));
 #pragma unroll
@@ -186,6 +190,7 @@ __device__ __forceinline__ void u12_mul(const T (&up)[(K / 16) * (K / 4)], const
   for (int t = 0; t < K / 16; ++t)
 #pragma unroll
     for (int step = 0; step < K / 4; ++step) {
+      if ((step >> 2) > t) continue;  // strictly lower: zero right of the row tile
       const int i = 16 * t + (lane & 15), kk = frag_k<T>(step, lane >> 4);
       const T av = (i > kk) ? -up[t * (K / 4) + step] : T(0);
 #pragma unroll
@@ -525,11 +530,11 @@ __global__ __launch_bounds__(64) void pass2_wave_kernel(FactorArgs a) {
     }
     zero_strip<T, K, MCT>(xb);
     blk_mul<T, K, MCT, 2>(up, nullptr, T(1), zb, xb);
-    // Gram += z_b^T z_b
+    // Gram += z_b^T z_b (tiles on and above the diagonal; mirrored when stored)
 #pragma unroll
     for (int ti = 0; ti < W::RT; ++ti)
 #pragma unroll
-      for (int tj = 0; tj < W::RT; ++tj)
+      for (int tj = ti; tj < W::RT; ++tj)
 #pragma unroll
         for (int step = 0; step < W::KS; ++step)
           gr[ti][tj] = mfma_step(xb[step >> 2][ti][step & 3], xb[step >> 2][tj][step & 3], gr[ti][tj]);
@@ -558,8 +563,12 @@ __global__ __launch_bounds__(64) void pass2_wave_kernel(FactorArgs a) {
 #pragma unroll
     for (int tj = 0; tj < W::RT; ++tj)
 #pragma unroll
-      for (int v = 0; v < 4; ++v)
-        gram[(16 * ti + acc_row<T>(lane, v)) * K + 16 * tj + (lane & 15)] = (double)gr[ti][tj][v];
+      for (int v = 0; v < 4; ++v) {
+        if (tj < ti) continue;
+        const int row = 16 * ti + acc_row<T>(lane, v), col = 16 * tj + (lane & 15);
+        gram[row * K + col] = (double)gr[ti][tj][v];
+        if (tj > ti) gram[col * K + row] = (double)gr[ti][tj][v];
+      }
 }
 
 }  // namespace lrs
