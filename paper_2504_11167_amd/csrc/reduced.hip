@@ -123,29 +123,31 @@ __global__ __launch_bounds__(LRS_NT) void eigen_kernel(RedArgs a) {
         sn[q] = s;
       }
       __syncthreads();
-      // columns: G <- G J, V <- V J
+      // G <- J^T G J one 2 x 2 block (rows of pair qa, columns of pair qb) per
+      // item: the column rotation of pair qb, then the row rotation of pair qa,
+      // in registers (one pass over G per step); V <- V J alongside
+      for (int o = tid; o < (KE / 2) * (KE / 2); o += blockDim.x) {
+        const int qa = o / (KE / 2), qb = o % (KE / 2);
+        const int r1 = pa[qa], r2 = pb[qa], c1 = pa[qb], c2 = pb[qb];
+        const bool hr = r2 < K, hc = c2 < K;  // false only for the idle player of odd K
+        const double cr = cs[qa], sr = sn[qa], cc = cs[qb], sc = sn[qb];
+        const double g11 = G[r1 * LD + c1], g12 = hc ? G[r1 * LD + c2] : 0.0;
+        const double g21 = hr ? G[r2 * LD + c1] : 0.0, g22 = (hr && hc) ? G[r2 * LD + c2] : 0.0;
+        const double a11 = cc * g11 - sc * g12, a12 = sc * g11 + cc * g12;
+        const double a21 = cc * g21 - sc * g22, a22 = sc * g21 + cc * g22;
+        G[r1 * LD + c1] = cr * a11 - sr * a21;
+        if (hc) G[r1 * LD + c2] = cr * a12 - sr * a22;
+        if (hr) G[r2 * LD + c1] = sr * a11 + cr * a21;
+        if (hr && hc) G[r2 * LD + c2] = sr * a12 + cr * a22;
+      }
       for (int o = tid; o < K * (KE / 2); o += blockDim.x) {
         int i = o / (KE / 2), q = o % (KE / 2);
         int p1 = pa[q], p2 = pb[q];
         if (p2 >= K) continue;
         double c = cs[q], s = sn[q];
-        double g1 = G[i * LD + p1], g2 = G[i * LD + p2];
-        G[i * LD + p1] = c * g1 - s * g2;
-        G[i * LD + p2] = s * g1 + c * g2;
         double v1 = V[i * LD + p1], v2 = V[i * LD + p2];
         V[i * LD + p1] = c * v1 - s * v2;
         V[i * LD + p2] = s * v1 + c * v2;
-      }
-      __syncthreads();
-      // rows: G <- J^T G
-      for (int o = tid; o < K * (KE / 2); o += blockDim.x) {
-        int i = o / (KE / 2), q = o % (KE / 2);
-        int p1 = pa[q], p2 = pb[q];
-        if (p2 >= K) continue;
-        double c = cs[q], s = sn[q];
-        double g1 = G[p1 * LD + i], g2 = G[p2 * LD + i];
-        G[p1 * LD + i] = c * g1 - s * g2;
-        G[p2 * LD + i] = s * g1 + c * g2;
       }
       __syncthreads();
     }
