@@ -243,15 +243,20 @@ __global__ __launch_bounds__(64) void factor_wave_kernel(FactorArgs a) {
     // row i of Lo_{b+1} (slab)
     {
       T pa[K], iv[K];
+      {
+        // one unconditional LDS read per element (no branch per column):
+        // lib[lane PT + c] for the top rows, slab[(c - i) K + i] (diagonal
+        // c - lane of row i = lane - K) for the bottom rows, zero outside the band
+        const bool top = lane < K;
+        const int i = lane - K;
 #pragma unroll
-      for (int c = 0; c < K; ++c) {
-        T v = T(0);
-        if (lane < K)
-          v = lib[lane * PT + c];
-        else if (lane < nr)
-          v = sl(lane - K, c - lane);
-        pa[c] = v;
-        iv[c] = T(0);
+        for (int c = 0; c < K; ++c) {
+          const bool ok = top || (lane < nr && c >= i);
+          const int off = top ? F::oLib + lane * PT + c : F::oSlab + (c - i) * K + i;
+          const T v = lds[ok ? off : 0];
+          pa[c] = ok ? v : T(0);
+          iv[c] = T(0);
+        }
       }
       if (b + 2 < nb) slab_fetch(b + 2, nx);
       T mx = T(0), dmin = T(1e30), dinv = T(0);
