@@ -71,6 +71,28 @@ struct FwdElim {
 // Upward Gauss-Jordan step C (counting down): lane i < K holds in uv[] the row
 // i of U11^{-1} being formed; U11 itself is read from pa[] (upper part) and
 // lane C scales its finished row by 1/U_CC (its dinv from the forward pass).
+// The same pass with a hook called at the start of every step (with the step
+// count as a compile-time constant), so that independent matrix-core work can
+// be issued between the lane reads and the updates of the step.
+template <typename T, int K, int C>
+struct BwdElimH {
+  template <typename H>
+  static __device__ __forceinline__ void run(const T (&pa)[K], T (&uv)[K], int lane, T dinv, H& hook) {
+    if constexpr (C >= 0) {
+      __builtin_amdgcn_sched_barrier(0);
+      hook(std::integral_constant<int, K - 1 - C>{});
+      if (lane == C) {
+#pragma unroll
+        for (int c = C; c < K; ++c) uv[c] *= dinv;
+      }
+      const T m = lane < C ? pa[C] : T(0);
+#pragma unroll
+      for (int c = C; c < K; ++c) uv[c] = fma(-m, bcast(uv[c], C), uv[c]);
+      BwdElimH<T, K, C - 1>::run(pa, uv, lane, dinv, hook);
+    }
+  }
+};
+
 template <typename T, int K, int C>
 struct BwdElim {
   static __device__ __forceinline__ void run(const T (&pa)[K], T (&uv)[K], int lane, T dinv) {
@@ -239,6 +261,11 @@ __global__ __launch_bounds__(64) void factor_wave_kernel(FactorArgs a) {
     const int nr = last ? K : 2 * K;
     asm volatile("" : "+v"(lane));  // (same: no lane-derived values kept across blocks)
     T nx[NS];  // band slab of block b + 2, fetched below and stored once this block is done with the slab
+    auto Li = [&](int i, int kk) -> T { return i > kk ? lib[i * PT + kk] : (i == kk ? T(1) : T(0)); };
+    auto Ui = [&](int i, int kk) -> T { return i <= kk ? lib[i * PT + kk] : T(0); };
+    auto UiT = [&](int i, int kk) -> T { return kk <= i ? lib[kk * PT + i] : T(0); };
+    auto L21 = [&](int i, int kk) -> T { return i <= kk ? l21b[i * PT + kk] : T(0); };
+    V u12[RT][RT], dn[RT][RT];
     // ---- panel [Dc_b; Lo_{b+1}]: lane i < K takes row i of Dc_b (lib), lane K + i
     // row i of Lo_{b+1} (slab)
     {
@@ -277,27 +304,62 @@ __global__ __launch_bounds__(64) void factor_wave_kernel(FactorArgs a) {
 #pragma unroll
         for (int c = 0; c < K; ++c) l21b[(lane - K) * PT + c] = pa[c];
       }
+      wave_fence();  // L11^{-1} and L21 visible to the products issued below
       // U11^{-1} rows, then lib <- U11^{-1} on and above the diagonal (a fresh
-      // opaque lane index: lane masks are not shared with the forward pass)
+      // opaque lane index: lane masks are not shared with the forward pass).
+      // The upward pass is a chain of lane reads and vector updates; the
+      // independent products U12 = L11^{-1} Up_b and Dc_{b+1} = D_{b+1} - L21 U12
+      // are issued one (tile, k-step) pair per step alongside it, so the matrix
+      // cores work while the chain waits.
       int ln2 = lane;
       asm volatile("" : "+v"(ln2));
 #pragma unroll
       for (int c = 0; c < K; ++c) iv[c] = (c == ln2) ? T(1) : T(0);
-      BwdElim<T, K, K - 1>::run(pa, iv, ln2, dinv);
+      if (!last) zero(u12);
+      constexpr int NPR = RT * KS;  // (tile, k-step) pairs of one product
+      // A operand of pair S: L11^{-1} (lower triangular) for U12, -L21 (upper) for Dc
+      auto opnd = [&](auto cst) -> T {
+        constexpr int S = decltype(cst)::value;
+        if constexpr (S < NPR) {
+          constexpr int t = S / KS, step = S % KS;
+          if constexpr ((step >> 2) <= t) return Li(16 * t + (lane & 15), frag_k<T>(step, lane >> 4));
+        } else if constexpr (S < 2 * NPR) {
+          constexpr int t = (S - NPR) / KS, step = (S - NPR) % KS;
+          if constexpr ((step >> 2) >= t) return -L21(16 * t + (lane & 15), frag_k<T>(step, lane >> 4));
+        }
+        return T(0);
+      };
+      // software-pipelined: step S issues pair S with the operand read during
+      // step S - 1 and reads the operand of pair S + 1
+      T avn = last ? T(0) : opnd(std::integral_constant<int, 0>{});
+      auto hook = [&](auto cst) {
+        constexpr int S = decltype(cst)::value;
+        if (last) return;
+        const T av = avn;
+        avn = opnd(std::integral_constant<int, S + 1>{});
+        if constexpr (S == NPR - 2)  // D_{b+1} read two steps before the first Dc pair
+          for_elems([&](int t2, int ct, int v, int row, int col) { dn[t2][ct][v] = sl(row, col - row); });
+        if constexpr (S < NPR) {
+          constexpr int t = S / KS, step = S % KS;
+          if constexpr ((step >> 2) <= t) {
+#pragma unroll
+            for (int ct = 0; ct < RT; ++ct) u12[t][ct] = mfma_step(av, uc[step >> 2][ct][step & 3], u12[t][ct]);
+          }
+        } else if constexpr (S < 2 * NPR) {
+          constexpr int t = (S - NPR) / KS, step = (S - NPR) % KS;
+          if constexpr ((step >> 2) >= t) {
+#pragma unroll
+            for (int ct = 0; ct < RT; ++ct) dn[t][ct] = mfma_step(av, u12[step >> 2][ct][step & 3], dn[t][ct]);
+          }
+        }
+      };
+      static_assert(2 * NPR <= K && NPR >= 2, "the products fit the steps of the pass");
+      BwdElimH<T, K, K - 1>::run(pa, iv, ln2, dinv, hook);
       if (lane < K)
 #pragma unroll
         for (int c = 0; c < K; ++c)
           if (c >= lane) lib[lane * PT + c] = iv[c];
       wave_sync();
-    }
-    auto Li = [&](int i, int kk) -> T { return i > kk ? lib[i * PT + kk] : (i == kk ? T(1) : T(0)); };
-    auto Ui = [&](int i, int kk) -> T { return i <= kk ? lib[i * PT + kk] : T(0); };
-    auto UiT = [&](int i, int kk) -> T { return kk <= i ? lib[kk * PT + i] : T(0); };
-    auto L21 = [&](int i, int kk) -> T { return i <= kk ? l21b[i * PT + kk] : T(0); };
-    V u12[RT][RT], dn[RT][RT];
-    if (!last) {
-      zero(u12);
-      mul(Li, uc, u12, T(1), 1);  // U12 = L11^{-1} Up_b
     }
     // ---- G step (the columns of E_t met in this block enter the pending sum)
     {
@@ -314,10 +376,6 @@ __global__ __launch_bounds__(64) void factor_wave_kernel(FactorArgs a) {
 #pragma unroll
         for (int step = 0; step < KS; ++step)
           gm[(size_t)b * K * K + ((t * KS + step) << 6) + lane] = gb[step >> 2][t][step & 3];
-    }
-    if (!last) {
-      for_elems([&](int t, int ct, int v, int row, int col) { dn[t][ct][v] = sl(row, col - row); });
-      mul(L21, u12, dn, T(-1), 2);  // Dc_{b+1} = D_{b+1} - L21 U12
     }
     // ---- stores: LP, pivots, flags
     T* rec = fac + (size_t)b * L.rec;
