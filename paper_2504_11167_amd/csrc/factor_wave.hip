@@ -45,7 +45,10 @@ __device__ __forceinline__ void wave_fence() {  // order LDS accesses of one wav
 // reaches the other lanes by lane reads into scalar registers (no LDS traffic,
 // so the waves sharing a CU do not contend); a scheduling barrier per step
 // keeps those reads next to their use.
-template <typename T, int K, int C>
+// BW < K restricts the ride-along to the BW x BW diagonal blocks of L11^{-1}
+// (columns [BW floor(C / BW), C) at step C); the blocks below the diagonal are
+// then formed by block products.
+template <typename T, int K, int C, int BW = K>
 struct FwdElim {
   static __device__ __forceinline__ void run(T (&pa)[K], T (&iv)[K], int lane, int nr, T& mx, T& dmin, T& dinv) {
     if constexpr (C < K) {
@@ -61,9 +64,9 @@ struct FwdElim {
 #pragma unroll
       for (int c = C + 1; c < K; ++c) pa[c] = fma(-l, bcast(pa[c], C), pa[c]);
 #pragma unroll
-      for (int c = 0; c < C; ++c) iv[c] = fma(-l, bcast(iv[c], C), iv[c]);
+      for (int c = (C / BW) * BW; c < C; ++c) iv[c] = fma(-l, bcast(iv[c], C), iv[c]);
       iv[C] -= l;
-      FwdElim<T, K, C + 1>::run(pa, iv, lane, nr, mx, dmin, dinv);
+      FwdElim<T, K, C + 1, BW>::run(pa, iv, lane, nr, mx, dmin, dinv);
     }
   }
 };
@@ -289,20 +292,47 @@ __global__ __launch_bounds__(64) void factor_wave_kernel(FactorArgs a) {
       T mx = T(0), dmin = T(1e30), dinv = T(0);
       int ln1 = lane;  // own opaque lane index (its masks are not kept for later use)
       asm volatile("" : "+v"(ln1));
-      FwdElim<T, K, 0>::run(pa, iv, ln1, nr, mx, dmin, dinv);
+      FwdElim<T, K, 0, 16>::run(pa, iv, ln1, nr, mx, dmin, dinv);
       const bool ok = !__any(!(mx <= T(1))) && (dmin > T(0));
       if (!ok) {
         if (lane == 0) npv[j] = 1;
         return;  // refactored with row interchanges by the general kernel
       }
-      // lib <- L11^{-1} strictly below the diagonal; l21b <- L21
+      // lib <- the 16 x 16 diagonal blocks of L11^{-1} strictly below the
+      // diagonal (and, at K = 32, the block L_{21} of L11 below them, for the
+      // products that follow); l21b <- L21
       if (lane < K) {
 #pragma unroll
         for (int c = 0; c < K; ++c)
-          if (c < lane) lib[lane * PT + c] = iv[c];
+          if (c < lane) lib[lane * PT + c] = (c >= (lane & ~15)) ? iv[c] : pa[c];
       } else if (lane < nr) {
 #pragma unroll
         for (int c = 0; c < K; ++c) l21b[(lane - K) * PT + c] = pa[c];
+      }
+      if constexpr (K == 32) {
+        // lower-left block of L11^{-1}: X = -L_{22}^{-1} (L_{21} L_{11}^{-1}) with
+        // the 16 x 16 blocks of L11 (two matrix-core products; the accumulator
+        // layout of a tile is the B operand layout of the next product)
+        wave_fence();
+        V ai, t1 = V{0, 0, 0, 0}, x = V{0, 0, 0, 0};
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int row = acc_row<T>(lane, v), col = lane & 15;
+          const T e = lib[row * PT + col];
+          ai[v] = row > col ? e : (row == col ? T(1) : T(0));
+        }
+#pragma unroll
+        for (int step = 0; step < 4; ++step)
+          t1 = mfma_step(lib[(16 + (lane & 15)) * PT + frag_k<T>(step, lane >> 4)], ai[step], t1);
+#pragma unroll
+        for (int step = 0; step < 4; ++step) {
+          const int i = lane & 15, kk = frag_k<T>(step, lane >> 4);
+          const T e = lib[(16 + i) * PT + 16 + kk];
+          x = mfma_step(-(kk < i ? e : (kk == i ? T(1) : T(0))), t1[step], x);
+        }
+        wave_fence();
+#pragma unroll
+        for (int v = 0; v < 4; ++v) lib[(16 + acc_row<T>(lane, v)) * PT + (lane & 15)] = x[v];
       }
       wave_fence();  // L11^{-1} and L21 visible to the products issued below
       // U11^{-1} rows, then lib <- U11^{-1} on and above the diagonal (a fresh
