@@ -77,21 +77,24 @@ struct FwdElim {
 // The same pass with a hook called at the start of every step (with the step
 // count as a compile-time constant), so that independent matrix-core work can
 // be issued between the lane reads and the updates of the step.
-template <typename T, int K, int C>
+// BW < K restricts the pass to the BW x BW diagonal blocks of U11^{-1}
+// (columns [C, BW (floor(C / BW) + 1)) at step C).
+template <typename T, int K, int C, int BW = K>
 struct BwdElimH {
   template <typename H>
   static __device__ __forceinline__ void run(const T (&pa)[K], T (&uv)[K], int lane, T dinv, H& hook) {
     if constexpr (C >= 0) {
+      constexpr int CE = (C / BW + 1) * BW;
       __builtin_amdgcn_sched_barrier(0);
       hook(std::integral_constant<int, K - 1 - C>{});
       if (lane == C) {
 #pragma unroll
-        for (int c = C; c < K; ++c) uv[c] *= dinv;
+        for (int c = C; c < CE; ++c) uv[c] *= dinv;
       }
       const T m = lane < C ? pa[C] : T(0);
 #pragma unroll
-      for (int c = C; c < K; ++c) uv[c] = fma(-m, bcast(uv[c], C), uv[c]);
-      BwdElimH<T, K, C - 1>::run(pa, uv, lane, dinv, hook);
+      for (int c = C; c < CE; ++c) uv[c] = fma(-m, bcast(uv[c], C), uv[c]);
+      BwdElimH<T, K, C - 1, BW>::run(pa, uv, lane, dinv, hook);
     }
   }
 };
@@ -384,11 +387,36 @@ __global__ __launch_bounds__(64) void factor_wave_kernel(FactorArgs a) {
         }
       };
       static_assert(2 * NPR <= K && NPR >= 2, "the products fit the steps of the pass");
-      BwdElimH<T, K, K - 1>::run(pa, iv, ln2, dinv, hook);
+      BwdElimH<T, K, K - 1, 16>::run(pa, iv, ln2, dinv, hook);
+      // lib <- the 16 x 16 diagonal blocks of U11^{-1} on and above the
+      // diagonal (and, at K = 32, the block U_{12} of U11 right of them)
       if (lane < K)
 #pragma unroll
         for (int c = 0; c < K; ++c)
-          if (c >= lane) lib[lane * PT + c] = iv[c];
+          if (c >= lane) lib[lane * PT + c] = (c < (lane | 15) + 1) ? iv[c] : pa[c];
+      if constexpr (K == 32) {
+        // upper-right block of U11^{-1}: Y = -U_{11}^{-1} (U_{12} U_{22}^{-1})
+        wave_fence();
+        V u2, t2 = V{0, 0, 0, 0}, y = V{0, 0, 0, 0};
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int row = acc_row<T>(lane, v), col = lane & 15;
+          const T e = lib[(16 + row) * PT + 16 + col];
+          u2[v] = col >= row ? e : T(0);
+        }
+#pragma unroll
+        for (int step = 0; step < 4; ++step)
+          t2 = mfma_step(lib[(lane & 15) * PT + 16 + frag_k<T>(step, lane >> 4)], u2[step], t2);
+#pragma unroll
+        for (int step = 0; step < 4; ++step) {
+          const int i = lane & 15, kk = frag_k<T>(step, lane >> 4);
+          const T e = lib[i * PT + kk];
+          y = mfma_step(-(kk >= i ? e : T(0)), t2[step], y);
+        }
+        wave_fence();
+#pragma unroll
+        for (int v = 0; v < 4; ++v) lib[acc_row<T>(lane, v) * PT + 16 + (lane & 15)] = y[v];
+      }
       wave_sync();
     }
     // ---- G step (the columns of E_t met in this block enter the pending sum)
