@@ -14,7 +14,8 @@
 //   records in the fragment order the sweeps read;  Dc_{b+1} = D_{b+1} - L21 U12.
 // The spikes are formed afterwards from the records (spike_lds_kernel) and,
 // for r < k, swept back with their Gram matrices (pass2_lds_kernel).
-// Block products: every thread owns one 4 x 4 tile of a 64 x 64 result.
+// Block products on the matrix cores (mm64 / mm32); the back-sweeps use 4 x 4
+// register tiles per thread (tile_mm).
 #include "sweep.h"
 
 namespace lrs {
@@ -50,23 +51,40 @@ __device__ __forceinline__ void tile_zero(double (&acc)[4][4]) {
     for (int v = 0; v < 4; ++v) acc[u][v] = 0.0;
 }
 
-// acc (2 x 2, this thread's tile of an N x N result, N = 32) += sum_{l<N} a(i, l) b(l, j)
-template <int N, typename FA, typename FB>
-__device__ __forceinline__ void tile2_mm(double (&acc)[2][2], FA a, FB b) {
-  static_assert(N == 32, "one 2 x 2 tile per thread of a 256-thread workgroup");
-  const int i0 = 2 * (threadIdx.x >> 4), j0 = 2 * (threadIdx.x & 15);
-#pragma unroll 8
-  for (int l = 0; l < N; ++l) {
-    const double a0 = (double)a(i0, l), a1 = (double)a(i0 + 1, l);
-    const double b0 = (double)b(l, j0), b1 = (double)b(l, j0 + 1);
-    acc[0][0] = fma(a0, b0, acc[0][0]);
-    acc[0][1] = fma(a0, b1, acc[0][1]);
-    acc[1][0] = fma(a1, b0, acc[1][0]);
-    acc[1][1] = fma(a1, b1, acc[1][1]);
+// Matrix-core block products from LDS operands for the 256-thread workgroup.
+// mm64: C (64 x 64) += A B, wave w owns rows 16w..16w+15 (four 16-column
+// tiles); per k-step s the A fragment is A(16w + lane mod 16, 4s + lane / 16)
+// and the B fragment B(4s + lane / 16, 16ct + lane mod 16).  TRI skips the
+// 16 x 16 tiles a triangular operand leaves zero: 1 A lower, 2 A upper,
+// 3 B upper, 4 B lower.
+template <typename T, int TRI, typename FA, typename FB>
+__device__ __forceinline__ void mm64(typename AccVec<T>::type (&acc)[4], FA a, FB b) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int i = 16 * w + (lane & 15), kq = lane >> 4, jl = lane & 15;
+#pragma unroll
+  for (int s = 0; s < 16; ++s) {
+    if (TRI == 1 && s >= 4 * (w + 1)) break;
+    if (TRI == 2 && s < 4 * w) continue;
+    const int kk = 4 * s + kq;
+    const T av = a(i, kk);
+#pragma unroll
+    for (int ct = 0; ct < 4; ++ct) {
+      if (TRI == 3 && s >= 4 * (ct + 1)) continue;
+      if (TRI == 4 && s < 4 * ct) continue;
+      acc[ct] = mfma_step(av, b(kk, 16 * ct + jl), acc[ct]);
+    }
   }
 }
-__device__ __forceinline__ void tile_zero2(double (&acc)[2][2]) {
-  acc[0][0] = acc[0][1] = acc[1][0] = acc[1][1] = 0.0;
+// mm32: C (32 x 32) += A B, wave w owns the 16 x 16 tile (w / 2, w mod 2).
+template <typename T, typename FA, typename FB>
+__device__ __forceinline__ void mm32(typename AccVec<T>::type& acc, FA a, FB b) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int i = 16 * (w >> 1) + (lane & 15), j = 16 * (w & 1) + (lane & 15), kq = lane >> 4;
+#pragma unroll
+  for (int s = 0; s < 8; ++s) {
+    const int kk = 4 * s + kq;
+    acc = mfma_step(a(i, kk), b(kk, j), acc);
+  }
 }
 
 template <typename T, int K>
@@ -136,7 +154,6 @@ __global__ __launch_bounds__(LRS_NT) void factor_lds_kernel(FactorArgs a) {
   load_block(P, 0, 0);
   for (int o = tid; o < K * K; o += LRS_NT) Gp[(o / K) * PT + o % K] = T(0);
   if (tid == 0) s_bad = 0;
-  const int i0 = LdsTile<K>::i0(), j0 = LdsTile<K>::j0();
   for (int b = 0; b < nb; ++b) {
     const bool last = (b == nb - 1);
     const int nr = last ? K : 2 * K;
@@ -210,66 +227,65 @@ __global__ __launch_bounds__(LRS_NT) void factor_lds_kernel(FactorArgs a) {
         return l >= i ? x : T(0);
       };
       auto blk = [&](int r0, int c0, int i, int l) -> T { return P[(r0 + i) * PT + c0 + l]; };
-      const int h0 = 2 * (tid >> 4), k0 = 2 * (tid & 15);
-      double a1[2][2], a2[2][2];
-      auto put = [&](double (&acc)[2][2], int r0, int c0, double s) {
+      using AV = typename AccVec<T>::type;
+      const int w = tid >> 6;
+      // 32 x 32 results: element v of wave w's tile at (row, col) of the quadrant
+      auto put32 = [&](const AV& acc, int r0, int c0, T sg) {
 #pragma unroll
-        for (int u = 0; u < 2; ++u)
-#pragma unroll
-          for (int v = 0; v < 2; ++v) P[(r0 + h0 + u) * PT + c0 + k0 + v] = (T)(s * acc[u][v]);
+        for (int v = 0; v < 4; ++v)
+          P[(r0 + 16 * (w >> 1) + acc_row<T>(lane, v)) * PT + c0 + 16 * (w & 1) + (lane & 15)] = sg * acc[v];
       };
+      AV a1, a2;
       if (tid < 64) reg_lu(0, K);
       __syncthreads();
       // U1' = L1^{-1} D12 (in place)
-      tile_zero2(a1);
-      tile2_mm<H>(a1, [&](int i, int l) { return lo(0, i, l); }, [&](int l, int c) { return blk(0, H, l, c); });
+      a1 = AV{0, 0, 0, 0};
+      mm32<T>(a1, [&](int i, int l) { return lo(0, i, l); }, [&](int l, int c) { return blk(0, H, l, c); });
       __syncthreads();
-      put(a1, 0, H, 1.0);
+      put32(a1, 0, H, T(1));
       __syncthreads();
       // S = D22 - L2' U1' (reads other quadrants than it writes)
-      tile_zero2(a1);
-      tile2_mm<H>(a1, [&](int i, int l) { return blk(H, 0, i, l); }, [&](int l, int c) { return blk(0, H, l, c); });
+      a1 = AV{0, 0, 0, 0};
+      mm32<T>(a1, [&](int i, int l) { return blk(H, 0, i, l); }, [&](int l, int c) { return blk(0, H, l, c); });
 #pragma unroll
-      for (int u = 0; u < 2; ++u)
-#pragma unroll
-        for (int v = 0; v < 2; ++v) P[(H + h0 + u) * PT + H + k0 + v] -= (T)a1[u][v];
+      for (int v = 0; v < 4; ++v)
+        P[(H + 16 * (w >> 1) + acc_row<T>(lane, v)) * PT + H + 16 * (w & 1) + (lane & 15)] -= a1[v];
       __syncthreads();
       if (tid < 64) reg_lu(H, H);
       __syncthreads();
       // T1 = L2' L1^{-1},  T2 = U1^{-1} U1'
-      tile_zero2(a1);
-      tile_zero2(a2);
-      tile2_mm<H>(a1, [&](int i, int l) { return blk(H, 0, i, l); }, [&](int l, int c) { return lo(0, l, c); });
-      tile2_mm<H>(a2, [&](int i, int l) { return up(0, i, l); }, [&](int l, int c) { return blk(0, H, l, c); });
+      a1 = AV{0, 0, 0, 0};
+      a2 = AV{0, 0, 0, 0};
+      mm32<T>(a1, [&](int i, int l) { return blk(H, 0, i, l); }, [&](int l, int c) { return lo(0, l, c); });
+      mm32<T>(a2, [&](int i, int l) { return up(0, i, l); }, [&](int l, int c) { return blk(0, H, l, c); });
       __syncthreads();
-      put(a1, H, 0, 1.0);
-      put(a2, 0, H, 1.0);
+      put32(a1, H, 0, T(1));
+      put32(a2, 0, H, T(1));
       __syncthreads();
       // lower-left of L11^{-1}: -L2^{-1} T1;  upper-right of U11^{-1}: -T2 U2^{-1}
-      tile_zero2(a1);
-      tile_zero2(a2);
-      tile2_mm<H>(a1, [&](int i, int l) { return lo(H, i, l); }, [&](int l, int c) { return blk(H, 0, l, c); });
-      tile2_mm<H>(a2, [&](int i, int l) { return blk(0, H, i, l); }, [&](int l, int c) { return up(H, l, c); });
+      a1 = AV{0, 0, 0, 0};
+      a2 = AV{0, 0, 0, 0};
+      mm32<T>(a1, [&](int i, int l) { return lo(H, i, l); }, [&](int l, int c) { return blk(H, 0, l, c); });
+      mm32<T>(a2, [&](int i, int l) { return blk(0, H, i, l); }, [&](int l, int c) { return up(H, l, c); });
       __syncthreads();
-      put(a1, H, 0, -1.0);
-      put(a2, 0, H, -1.0);
+      put32(a1, H, 0, T(-1));
+      put32(a2, 0, H, T(-1));
       __syncthreads();
       // L21 = Lo U11^{-1} (in place in the panel bottom)
       if (!last) {
-        double acc[4][4];
-        tile_zero(acc);
-        tile_mm<K>(acc, [&](int r, int l) { return P[(K + r) * PT + l]; }, [&](int l, int c) {
+        AV acc[4] = {AV{0, 0, 0, 0}, AV{0, 0, 0, 0}, AV{0, 0, 0, 0}, AV{0, 0, 0, 0}};
+        mm64<T, 3>(acc, [&](int r, int l) { return P[(K + r) * PT + l]; }, [&](int l, int c) {
           const T x = P[l * PT + c];
           return l <= c ? x : T(0);
         });
         __syncthreads();
         bool big = false;
 #pragma unroll
-        for (int u = 0; u < 4; ++u)
+        for (int ct = 0; ct < 4; ++ct)
 #pragma unroll
           for (int v = 0; v < 4; ++v) {
-            P[(K + i0 + u) * PT + j0 + v] = (T)acc[u][v];
-            big |= !(fabs(acc[u][v]) <= 1.0);
+            P[(K + 16 * w + acc_row<T>(lane, v)) * PT + 16 * ct + (lane & 15)] = acc[ct][v];
+            big |= !(fabs(acc[ct][v]) <= T(1));
           }
         if (big && s_bad == 0) {  // every writer stores the same values
           s_bad = 2;
@@ -290,16 +306,26 @@ __global__ __launch_bounds__(LRS_NT) void factor_lds_kernel(FactorArgs a) {
       const T x = P[r * PT + l];
       return r <= l ? x : T(0);
     };
-    double acc[4][4];
+    using AV = typename AccVec<T>::type;
+    const int lane = tid & 63, w = tid >> 6;
+    // (row, col) of element v of accumulator tile ct
+    auto each = [&](auto&& fn) {
+#pragma unroll
+      for (int ct = 0; ct < 4; ++ct)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) fn(ct, v, 16 * w + acc_row<T>(lane, v), 16 * ct + (lane & 15));
+    };
+    AV acc[4];
+    auto zero = [&]() {
+#pragma unroll
+      for (int ct = 0; ct < 4; ++ct) acc[ct] = AV{0, 0, 0, 0};
+    };
     // ---- U12 = L11^{-1} Up_b (in place in U)
     if (!last) {
-      tile_zero(acc);
-      tile_mm<K>(acc, Li, [&](int l, int c) { return U[l * PT + c]; });
+      zero();
+      mm64<T, 1>(acc, Li, [&](int l, int c) { return U[l * PT + c]; });
       __syncthreads();
-#pragma unroll
-      for (int u = 0; u < 4; ++u)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) U[(i0 + u) * PT + j0 + v] = (T)acc[u][v];
+      each([&](int ct, int v, int row, int col) { U[row * PT + col] = acc[ct][v]; });
       __syncthreads();
     }
     // ---- G step: g_b = U11^{-T} (e_b + pending); G^T record; pending = -U12^T g_b
@@ -308,25 +334,19 @@ __global__ __launch_bounds__(LRS_NT) void factor_lds_kernel(FactorArgs a) {
       if (c == b * K + i - g.pad) Gp[i * PT + c] += T(1);
     }
     __syncthreads();
-    tile_zero(acc);
-    tile_mm<K>(acc, [&](int r, int l) { return Ui(l, r); }, [&](int l, int c) { return Gp[l * PT + c]; });
+    zero();
+    mm64<T, 1>(acc, [&](int r, int l) { return Ui(l, r); }, [&](int l, int c) { return Gp[l * PT + c]; });
     __syncthreads();
-#pragma unroll
-    for (int u = 0; u < 4; ++u)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        Gp[(i0 + u) * PT + j0 + v] = (T)acc[u][v];
-        gm[(size_t)b * K * K + fidx<T, K>(j0 + v, i0 + u)] = (T)acc[u][v];  // G^T in operand order
-      }
+    each([&](int ct, int v, int row, int col) {
+      Gp[row * PT + col] = acc[ct][v];
+      gm[(size_t)b * K * K + fidx<T, K>(col, row)] = acc[ct][v];  // G^T in operand order
+    });
     __syncthreads();
     if (!last) {
-      tile_zero(acc);
-      tile_mm<K>(acc, [&](int r, int l) { return U[l * PT + r]; }, [&](int l, int c) { return Gp[l * PT + c]; });
+      zero();
+      mm64<T, 2>(acc, [&](int r, int l) { return U[l * PT + r]; }, [&](int l, int c) { return Gp[l * PT + c]; });
       __syncthreads();
-#pragma unroll
-      for (int u = 0; u < 4; ++u)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) Gp[(i0 + u) * PT + j0 + v] = (T)(-acc[u][v]);
+      each([&](int ct, int v, int row, int col) { Gp[row * PT + col] = -acc[ct][v]; });
     }
     // ---- records: LP = L11^{-1} strict lower | L21 upper;  UP = U11^{-1} upper | U12 strict lower; UD
     T* rec = fac + (size_t)b * L.rec;
@@ -343,18 +363,15 @@ __global__ __launch_bounds__(LRS_NT) void factor_lds_kernel(FactorArgs a) {
     __syncthreads();
     // ---- Dc_{b+1} = D_{b+1} - L21 U12 into the panel top
     if (!last) {
-      tile_zero(acc);
-      tile_mm<K>(acc, [&](int r, int l) {
+      zero();
+      mm64<T, 2>(acc, [&](int r, int l) {
         const T x = P[(K + r) * PT + l];
         return r <= l ? x : T(0);
       },
                  [&](int l, int c) { return U[l * PT + c]; });
       load_block(P, b + 1, b + 1);  // D_{b+1} (the panel top is free once the records are out)
       __syncthreads();
-#pragma unroll
-      for (int u = 0; u < 4; ++u)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) P[(i0 + u) * PT + j0 + v] -= (T)acc[u][v];
+      each([&](int ct, int v, int row, int col) { P[row * PT + col] -= acc[ct][v]; });
       __syncthreads();
     }
   }
