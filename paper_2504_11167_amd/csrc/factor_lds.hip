@@ -14,42 +14,11 @@
 //   records in the fragment order the sweeps read;  Dc_{b+1} = D_{b+1} - L21 U12.
 // The spikes are formed afterwards from the records (spike_lds_kernel) and,
 // for r < k, swept back with their Gram matrices (pass2_lds_kernel).
-// Block products on the matrix cores (mm64 / mm32); the back-sweeps use 4 x 4
-// register tiles per thread (tile_mm).
+// Every block product runs on the matrix cores from LDS operands (mm64, mm32,
+// and the 64 x 16 products of the spike sweeps).
 #include "sweep.h"
 
 namespace lrs {
-
-template <int K>
-struct LdsTile {
-  static_assert(K == 64, "one 4 x 4 tile per thread of a 256-thread workgroup");
-  static __device__ __forceinline__ int i0() { return 4 * (threadIdx.x >> 4); }
-  static __device__ __forceinline__ int j0() { return 4 * (threadIdx.x & 15); }
-};
-
-// acc (4 x 4, this thread's tile) += sum_l a(i, l) b(l, j)
-template <int K, typename FA, typename FB>
-__device__ __forceinline__ void tile_mm(double (&acc)[4][4], FA a, FB b) {
-  const int i0 = LdsTile<K>::i0(), j0 = LdsTile<K>::j0();
-#pragma unroll 4
-  for (int l = 0; l < K; ++l) {
-    double av[4], bv[4];
-#pragma unroll
-    for (int u = 0; u < 4; ++u) av[u] = (double)a(i0 + u, l);
-#pragma unroll
-    for (int v = 0; v < 4; ++v) bv[v] = (double)b(l, j0 + v);
-#pragma unroll
-    for (int u = 0; u < 4; ++u)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) acc[u][v] = fma(av[u], bv[v], acc[u][v]);
-  }
-}
-__device__ __forceinline__ void tile_zero(double (&acc)[4][4]) {
-#pragma unroll
-  for (int u = 0; u < 4; ++u)
-#pragma unroll
-    for (int v = 0; v < 4; ++v) acc[u][v] = 0.0;
-}
 
 // Matrix-core block products from LDS operands for the 256-thread workgroup.
 // mm64: C (64 x 64) += A B, wave w owns rows 16w..16w+15 (four 16-column
@@ -430,27 +399,41 @@ __global__ __launch_bounds__(LRS_NT) void spike_lds_kernel(FactorArgs a) {
       Gb[c * PT + i] = gm[(size_t)b * K * K + fidx<T, K>(i, c)];  // stored G^T(i, c) = G(c, i)
     }
   };
-  // out (K x MS) = M (K x K, pitch PT) x X (K x MS, pitch PM), 4 rows x 1 column per thread
+  // out (K x MS) = sign M X (+ out), M K x K (pitch PT, or its transpose),
+  // X K x MS (pitch PM): matrix cores, wave w computes rows 16w..16w+15
+  using AV = typename AccVec<T>::type;
+  const int lane = tid & 63, w = tid >> 6, col = lane & 15;
   auto mm = [&](const T* M, bool trans, const T* X, T* out, T sign, bool accumulate) {
-    const int col = tid & 15, r0 = 4 * (tid >> 4);
-    double s[4] = {0.0, 0.0, 0.0, 0.0};
-    for (int l = 0; l < K; ++l) {
-      const double x = (double)X[l * PM + col];
+    AV acc = AV{0, 0, 0, 0};
+    const int i = 16 * w + (lane & 15);
 #pragma unroll
-      for (int u = 0; u < 4; ++u) s[u] = fma((double)(trans ? M[l * PT + r0 + u] : M[(r0 + u) * PT + l]), x, s[u]);
+    for (int s2 = 0; s2 < K / 4; ++s2) {
+      const int kk = 4 * s2 + (lane >> 4);
+      acc = mfma_step(trans ? M[kk * PT + i] : M[i * PT + kk], X[kk * PM + col], acc);
     }
     __syncthreads();
 #pragma unroll
-    for (int u = 0; u < 4; ++u)
-      out[(r0 + u) * PM + col] = (T)((accumulate ? (double)out[(r0 + u) * PM + col] : 0.0) + sign * s[u]);
+    for (int v = 0; v < 4; ++v) {
+      const int row = 16 * w + acc_row<T>(lane, v);
+      out[row * PM + col] = (accumulate ? out[row * PM + col] : T(0)) + sign * acc[v];
+    }
     __syncthreads();
   };
-  double acc[4] = {0.0, 0.0, 0.0, 0.0};  // top tip: rows r0..r0+3 of column col
-  const int col = tid & 15, r0 = 4 * (tid >> 4);
-  auto put_tip = [&](int which, const T* X, bool dbl_acc) {
+  AV tacc = AV{0, 0, 0, 0};  // top tip: rows 16w.., the chunk's 16 columns
+  auto gt_acc = [&]() {  // tacc += G_b^T z_b (Gb holds G_b^T transposed: Gb[l][r] = G_b(l, r))
+    const int i = 16 * w + (lane & 15);
 #pragma unroll
-    for (int u = 0; u < 4; ++u)
-      tips[(size_t)which * K * K + (r0 + u) * K + c0 + col] = dbl_acc ? acc[u] : (double)X[(r0 + u) * PM + col];
+    for (int s2 = 0; s2 < K / 4; ++s2) {
+      const int kk = 4 * s2 + (lane >> 4);
+      tacc = mfma_step(Gb[kk * PT + i], Z[kk * PM + col], tacc);
+    }
+  };
+  auto put_tip = [&](int which, const T* X, bool from_acc) {
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int row = 16 * w + acc_row<T>(lane, v);
+      tips[(size_t)which * K * K + row * K + c0 + col] = from_acc ? (double)tacc[v] : (double)X[row * PM + col];
+    }
   };
   auto store_y = [&](int b) {
     if (!ym) return;
@@ -470,12 +453,7 @@ __global__ __launch_bounds__(LRS_NT) void spike_lds_kernel(FactorArgs a) {
       __syncthreads();
       mm(A, false, Rw, Z, T(1), false);  // z_b
       if (!last) mm(B, false, Z, Rw + K * PM, T(-1), true);
-      // W_t += G_b^T z_b
-      for (int l = 0; l < K; ++l) {
-        const double z = (double)Z[l * PM + col];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) acc[u] = fma((double)Gb[l * PT + r0 + u], z, acc[u]);
-      }
+      gt_acc();  // W_t += G_b^T z_b
       store_y(b);
       if (last) {
         const T* up = fac + (size_t)b * L.rec + K * K;
@@ -502,11 +480,7 @@ __global__ __launch_bounds__(LRS_NT) void spike_lds_kernel(FactorArgs a) {
     load_L(b, false);
     __syncthreads();
     mm(A, false, Rw, Z, T(1), false);  // z = L11^{-1} B_j (last block)
-    for (int l = 0; l < K; ++l) {
-      const double z = (double)Z[l * PM + col];
-#pragma unroll
-      for (int u = 0; u < 4; ++u) acc[u] = fma((double)Gb[l * PT + r0 + u], z, acc[u]);
-    }
+    gt_acc();
     store_y(b);
     const T* up = fac + (size_t)b * L.rec + K * K;
     for (int o = tid; o < K * K; o += LRS_NT) {
@@ -537,9 +511,17 @@ __global__ __launch_bounds__(LRS_NT) void pass2_lds_kernel(FactorArgs a) {
   const T* fac = wsT<T>(a.ws, L.fac) + (size_t)j * L.nbmax * L.rec;
   const T* ym = wsT<T>(a.ws, L.ymat) + (size_t)j * L.nbmax * 2 * K * K;
   const int coff = spike == 0 ? 0 : K;
-  const int i0 = LdsTile<K>::i0(), j0 = LdsTile<K>::j0();
-  double gr[4][4], acc[4][4];
-  tile_zero(gr);
+  using AV = typename AccVec<T>::type;
+  const int lane = tid & 63, w = tid >> 6;
+  auto each = [&](auto&& fn) {  // (tile, element, row, col) of this wave's accumulators
+#pragma unroll
+    for (int ct = 0; ct < 4; ++ct)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) fn(ct, v, 16 * w + acc_row<T>(lane, v), 16 * ct + (lane & 15));
+  };
+  AV gr[4], acc[4];
+#pragma unroll
+  for (int ct = 0; ct < 4; ++ct) gr[ct] = AV{0, 0, 0, 0};
   for (int o = tid; o < K * PT; o += LRS_NT) Zn[o] = T(0);
   for (int b = g.nb - 1; b >= 0; --b) {
     const bool last = (b == g.nb - 1);
@@ -551,33 +533,28 @@ __global__ __launch_bounds__(LRS_NT) void pass2_lds_kernel(FactorArgs a) {
       U12[i * PT + c] = last ? T(0) : (i > c ? x : (i == c ? rec[2 * K * K + i] : T(0)));
     }
     __syncthreads();
-    // Tm = Y_b - U12 z_{b+1}
-    tile_zero(acc);
-    if (!last) tile_mm<K>(acc, [&](int r, int l) { return U12[r * PT + l]; }, [&](int l, int c) { return Zn[l * PT + c]; });
+    // Tm = Y_b - U12 z_{b+1}  (U12 lower triangular)
+#pragma unroll
+    for (int ct = 0; ct < 4; ++ct) acc[ct] = AV{0, 0, 0, 0};
+    if (!last) mm64<T, 1>(acc, [&](int r, int l) { return U12[r * PT + l]; }, [&](int l, int c) { return Zn[l * PT + c]; });
     const bool ynz = spike == 0 || last;
-#pragma unroll
-    for (int u = 0; u < 4; ++u)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const double y = ynz ? (double)ym[(size_t)b * 2 * K * K + (i0 + u) * 2 * K + coff + j0 + v] : 0.0;
-        Tm[(i0 + u) * PT + j0 + v] = (T)(y - acc[u][v]);
-      }
+    each([&](int ct, int v, int row, int col) {
+      const T y = ynz ? ym[(size_t)b * 2 * K * K + row * 2 * K + coff + col] : T(0);
+      Tm[row * PT + col] = y - acc[ct][v];
+    });
     __syncthreads();
-    tile_zero(acc);
-    tile_mm<K>(acc, [&](int r, int l) { return Ui[r * PT + l]; }, [&](int l, int c) { return Tm[l * PT + c]; });
+    // z_b = U11^{-1} Tm  (upper triangular)
 #pragma unroll
-    for (int u = 0; u < 4; ++u)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) Zn[(i0 + u) * PT + j0 + v] = (T)acc[u][v];
+    for (int ct = 0; ct < 4; ++ct) acc[ct] = AV{0, 0, 0, 0};
+    mm64<T, 2>(acc, [&](int r, int l) { return Ui[r * PT + l]; }, [&](int l, int c) { return Tm[l * PT + c]; });
+    each([&](int ct, int v, int row, int col) { Zn[row * PT + col] = acc[ct][v]; });
     __syncthreads();
-    tile_mm<K>(gr, [&](int r, int l) { return Zn[l * PT + r]; }, [&](int l, int c) { return Zn[l * PT + c]; });
+    // Gram += z_b^T z_b
+    mm64<T, 0>(gr, [&](int r, int l) { return Zn[l * PT + r]; }, [&](int l, int c) { return Zn[l * PT + c]; });
     __syncthreads();
   }
   double* gram = wsT<double>(a.ws, L.gram) + ((size_t)j * 2 + (spike == 0 ? 1 : 0)) * K * K;
-#pragma unroll
-  for (int u = 0; u < 4; ++u)
-#pragma unroll
-    for (int v = 0; v < 4; ++v) gram[(i0 + u) * K + j0 + v] = gr[u][v];
+  each([&](int ct, int v, int row, int col) { gram[row * K + col] = (double)gr[ct][v]; });
 }
 
 }  // namespace lrs
