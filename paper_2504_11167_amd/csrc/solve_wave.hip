@@ -499,20 +499,29 @@ __global__ __launch_bounds__(64) void pass2_wave_kernel(FactorArgs a) {
   for (int ti = 0; ti < W::RT; ++ti)
 #pragma unroll
     for (int tj = 0; tj < W::RT; ++tj) gr[ti][tj] = V{0, 0, 0, 0};
-  T up[NF], upn[NF], ud[W::RT][4], udn[W::RT][4];
+  // records and Y strips are fetched two blocks ahead (one wave per SIMD:
+  // one block of work does not cover the memory latency)
+  T up[NF], upn[NF], up2[NF], ud[W::RT][4], udn[W::RT][4], ud2[W::RT][4];
+  V zn2[W::RT][MCT];
   int b = g.nb - 1;
   load_frags<T, K>(up, fac + (size_t)b * L.rec + K * K);
   load_udrows<T, K>(ud, fac + (size_t)b * L.rec + 2 * K * K);
   int fl = flg[b];
   load_y(b, zb);
+  int fln = 0, fl2 = 0;
+  if (b > 0) {
+    load_frags<T, K>(upn, fac + (size_t)(b - 1) * L.rec + K * K);
+    load_udrows<T, K>(udn, fac + (size_t)(b - 1) * L.rec + 2 * K * K);
+    fln = flg[b - 1];
+    load_y(b - 1, zn);
+  }
   for (; b >= 0; --b) {
     const bool last = (b == g.nb - 1);
-    int fln = 0;
-    if (b > 0) {
-      load_frags<T, K>(upn, fac + (size_t)(b - 1) * L.rec + K * K);
-      load_udrows<T, K>(udn, fac + (size_t)(b - 1) * L.rec + 2 * K * K);
-      fln = flg[b - 1];
-      load_y(b - 1, zn);
+    if (b > 1) {
+      load_frags<T, K>(up2, fac + (size_t)(b - 2) * L.rec + K * K);
+      load_udrows<T, K>(ud2, fac + (size_t)(b - 2) * L.rec + 2 * K * K);
+      fl2 = flg[b - 2];
+      load_y(b - 2, zn2);
     }
     if (!last) {
       if (fl & 2) {
@@ -545,16 +554,22 @@ __global__ __launch_bounds__(64) void pass2_wave_kernel(FactorArgs a) {
         x2[t][ct] = x1[t][ct];
         x1[t][ct] = xb[t][ct];
         zb[t][ct] = zn[t][ct];
+        zn[t][ct] = zn2[t][ct];
       }
-    if (b > 0) {
 #pragma unroll
-      for (int f = 0; f < NF; ++f) up[f] = upn[f];
-#pragma unroll
-      for (int t = 0; t < W::RT; ++t)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) ud[t][v] = udn[t][v];
-      fl = fln;
+    for (int f = 0; f < NF; ++f) {
+      up[f] = upn[f];
+      upn[f] = up2[f];
     }
+#pragma unroll
+    for (int t = 0; t < W::RT; ++t)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        ud[t][v] = udn[t][v];
+        udn[t][v] = ud2[t][v];
+      }
+    fl = fln;
+    fln = fl2;
   }
   // gram layout [GV | GW], K x K row-major each
   double* gram = wsT<double>(a.ws, L.gram) + ((size_t)j * 2 + (spike == 0 ? 1 : 0)) * K * K;
