@@ -15,10 +15,11 @@
 namespace lrs {
 
 constexpr int MC = 32;  // right-hand-side columns per workgroup (K <= 32)
-// columns per workgroup of the generic sweeps: fewer at K = 64 so that the
-// three K x K factor blocks and the strips fit in LDS
+// columns per workgroup of the generic sweeps: 16 at K = 64, so that the
+// three K x K factor blocks and the strips fit in LDS (157 KB in FP64) and a
+// strip is one matrix-core tile wide
 template <int K>
-constexpr int mc_of() { return K <= 32 ? MC : 8; }
+constexpr int mc_of() { return K <= 32 ? MC : 16; }
 
 template <typename T>
 __device__ inline T* wsp(char* ws, size_t off) {

@@ -357,6 +357,7 @@ def test_tiny_systems(gpu, n, k, p, r):
     (2600, 50, 4, 25, 5),    # k padded to 64
     (1000, 64, 1, 64, 2),    # a single partition: the exact band solve
     (1200, 40, 2, 20, 1),    # padded, p = 2
+    (2000, 64, 3, 16, 20),   # two column chunks (the second ragged)
 ])
 def test_k64_matches_oracle(gpu, n, k, p, r, m):
     bands, f = synth.make_problem(n, k, m, seed=n + k, rule="strict")
