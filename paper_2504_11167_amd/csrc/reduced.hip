@@ -274,11 +274,36 @@ __device__ inline void block_mm_ts(int R, int N, int Kd, FA a, FB b, FO out) {
         if (i0 + u < R && j0 + v < N) out(i0 + u, j0 + v, acc[u][v]);
   }
 }
+// Matrix cores for R, N multiples of 16 up to 64 and Kd a multiple of 4: wave
+// w takes the 16-row tile w (and every 16-column tile), the A fragment
+// a(16 tr + lane mod 16, 4s + lane / 16) shared by the column tiles.
+template <typename FA, typename FB, typename FO>
+__device__ inline void block_mm_mfma(int R, int N, int Kd, FA a, FB b, FO out) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  const int ntr = R / 16, ntc = N / 16;
+  for (int tr = w; tr < ntr; tr += nw) {
+    lrs_d4 acc[4] = {lrs_d4{0, 0, 0, 0}, lrs_d4{0, 0, 0, 0}, lrs_d4{0, 0, 0, 0}, lrs_d4{0, 0, 0, 0}};
+    for (int s = 0; s < Kd / 4; ++s) {
+      const int kk = 4 * s + (lane >> 4);
+      const double av = a(16 * tr + (lane & 15), kk);
+#pragma unroll
+      for (int ct = 0; ct < 4; ++ct)
+        if (ct < ntc) acc[ct] = mfma_step(av, (double)b(kk, 16 * ct + (lane & 15)), acc[ct]);
+    }
+#pragma unroll
+    for (int ct = 0; ct < 4; ++ct)
+      if (ct < ntc)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) out(16 * tr + acc_row<double>(lane, v), 16 * ct + (lane & 15), acc[ct][v]);
+  }
+}
 // register tile chosen so that the tiles cover about one workgroup
 template <typename FA, typename FB, typename FO>
 __device__ inline void block_mm(int R, int N, int Kd, FA a, FB b, FO out) {
   const int rn = R * N;
-  if (rn <= 256)
+  if (R % 16 == 0 && N % 16 == 0 && Kd % 4 == 0 && R <= 64 && N <= 64)
+    block_mm_mfma(R, N, Kd, a, b, out);
+  else if (rn <= 256)
     block_mm_ts<1>(R, N, Kd, a, b, out);
   else if (rn <= 1024)
     block_mm_ts<2>(R, N, Kd, a, b, out);
