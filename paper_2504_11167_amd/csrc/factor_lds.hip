@@ -160,7 +160,9 @@ __global__ __launch_bounds__(LRS_NT) void factor_lds_kernel(FactorArgs a) {
         T mx = T(0), dmin = T(1e30), dinv = T(0);
         int ln1 = lane;  // opaque lane index (see factor_pass1_wave_kernel)
         asm volatile("" : "+v"(ln1));
-        FwdElim<T, H, 0>::run(pa, iv, ln1, nrow, mx, dmin, dinv);
+        // the L1^{-1} ride-along and the U1^{-1} pass cover the 16 x 16
+        // diagonal blocks; their off-diagonal blocks come from block products
+        FwdElim<T, H, 0, 16>::run(pa, iv, ln1, nrow, mx, dmin, dinv);
         const unsigned long long zb = __ballot(lane < H && !isfinite(dinv));
         const unsigned long long bb = __ballot(lane < nrow && !(mx <= T(1)));
         if (lane == 0 && s_bad == 0 && (zb || bb || !(dmin > T(0)))) {
@@ -170,20 +172,22 @@ __global__ __launch_bounds__(LRS_NT) void factor_lds_kernel(FactorArgs a) {
         if (lane < H) {
 #pragma unroll
           for (int c = 0; c < H; ++c)
-            if (c < lane) P[(r0 + lane) * PT + r0 + c] = iv[c];
+            if (c < lane) P[(r0 + lane) * PT + r0 + c] = (c >= (lane & ~15)) ? iv[c] : pa[c];
         } else if (lane < nrow) {
 #pragma unroll
           for (int c = 0; c < H; ++c) P[(r0 + lane) * PT + r0 + c] = pa[c];
         }
+        lower_offdiag_inverse<T>(P + r0 * PT + r0, PT, lane);
         int ln2 = lane;
         asm volatile("" : "+v"(ln2));
 #pragma unroll
         for (int c = 0; c < H; ++c) iv[c] = (c == ln2) ? T(1) : T(0);
-        BwdElim<T, H, H - 1>::run(pa, iv, ln2, dinv);
+        BwdElim<T, H, H - 1, 16>::run(pa, iv, ln2, dinv);
         if (lane < H)
 #pragma unroll
           for (int c = 0; c < H; ++c)
-            if (c >= lane) P[(r0 + lane) * PT + r0 + c] = iv[c];
+            if (c >= lane) P[(r0 + lane) * PT + r0 + c] = (c < (lane | 15) + 1) ? iv[c] : pa[c];
+        upper_offdiag_inverse<T>(P + r0 * PT + r0, PT, lane);
       };
       // unit lower / upper parts of a packed H x H block at (r0, r0); loads
       // are unconditional (valid addresses) so the products stay branch-free

@@ -99,19 +99,20 @@ struct BwdElimH {
   }
 };
 
-template <typename T, int K, int C>
+template <typename T, int K, int C, int BW = K>
 struct BwdElim {
   static __device__ __forceinline__ void run(const T (&pa)[K], T (&uv)[K], int lane, T dinv) {
     if constexpr (C >= 0) {
+      constexpr int CE = (C / BW + 1) * BW;
       __builtin_amdgcn_sched_barrier(0);
       if (lane == C) {
 #pragma unroll
-        for (int c = C; c < K; ++c) uv[c] *= dinv;
+        for (int c = C; c < CE; ++c) uv[c] *= dinv;
       }
       const T m = lane < C ? pa[C] : T(0);
 #pragma unroll
-      for (int c = C; c < K; ++c) uv[c] = fma(-m, bcast(uv[c], C), uv[c]);
-      BwdElim<T, K, C - 1>::run(pa, uv, lane, dinv);
+      for (int c = C; c < CE; ++c) uv[c] = fma(-m, bcast(uv[c], C), uv[c]);
+      BwdElim<T, K, C - 1, BW>::run(pa, uv, lane, dinv);
     }
   }
 };
@@ -120,6 +121,63 @@ __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
   __builtin_amdgcn_s_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+
+// Off-diagonal 16 x 16 blocks of the inverses of a 32 x 32 packed block M
+// (pitch pm) whose passes covered only the 16 x 16 diagonal blocks; one wave,
+// two matrix-core products each (the accumulator layout of a tile is the B
+// operand layout of the next product).
+//   lower: M holds L11^{-1} (strict lower) in the diagonal blocks and the block
+//   L_{21} of L11 below them; it becomes X = -L_{22}^{-1} (L_{21} L_{11}^{-1}).
+//   upper: M holds U11^{-1} (upper) in the diagonal blocks and the block U_{12}
+//   of U11 right of them; it becomes Y = -U_{11}^{-1} (U_{12} U_{22}^{-1}).
+template <typename T>
+__device__ __forceinline__ void lower_offdiag_inverse(T* M, int pm, int lane) {
+  using V = typename AccVec<T>::type;
+  wave_fence();
+  V ai, t1 = V{0, 0, 0, 0}, x = V{0, 0, 0, 0};
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int row = acc_row<T>(lane, v), col = lane & 15;
+    const T e = M[row * pm + col];
+    ai[v] = row > col ? e : (row == col ? T(1) : T(0));
+  }
+#pragma unroll
+  for (int step = 0; step < 4; ++step)
+    t1 = mfma_step(M[(16 + (lane & 15)) * pm + frag_k<T>(step, lane >> 4)], ai[step], t1);
+#pragma unroll
+  for (int step = 0; step < 4; ++step) {
+    const int i = lane & 15, kk = frag_k<T>(step, lane >> 4);
+    const T e = M[(16 + i) * pm + 16 + kk];
+    x = mfma_step(-(kk < i ? e : (kk == i ? T(1) : T(0))), t1[step], x);
+  }
+  wave_fence();
+#pragma unroll
+  for (int v = 0; v < 4; ++v) M[(16 + acc_row<T>(lane, v)) * pm + (lane & 15)] = x[v];
+}
+template <typename T>
+__device__ __forceinline__ void upper_offdiag_inverse(T* M, int pm, int lane) {
+  using V = typename AccVec<T>::type;
+  wave_fence();
+  V u2, t2 = V{0, 0, 0, 0}, y = V{0, 0, 0, 0};
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int row = acc_row<T>(lane, v), col = lane & 15;
+    const T e = M[(16 + row) * pm + 16 + col];
+    u2[v] = col >= row ? e : T(0);
+  }
+#pragma unroll
+  for (int step = 0; step < 4; ++step)
+    t2 = mfma_step(M[(lane & 15) * pm + 16 + frag_k<T>(step, lane >> 4)], u2[step], t2);
+#pragma unroll
+  for (int step = 0; step < 4; ++step) {
+    const int i = lane & 15, kk = frag_k<T>(step, lane >> 4);
+    const T e = M[i * pm + kk];
+    y = mfma_step(-(kk >= i ? e : T(0)), t2[step], y);
+  }
+  wave_fence();
+#pragma unroll
+  for (int v = 0; v < 4; ++v) M[acc_row<T>(lane, v) * pm + 16 + (lane & 15)] = y[v];
 }
 
 template <typename T, int K>
@@ -312,31 +370,7 @@ __global__ __launch_bounds__(64) void factor_wave_kernel(FactorArgs a) {
 #pragma unroll
         for (int c = 0; c < K; ++c) l21b[(lane - K) * PT + c] = pa[c];
       }
-      if constexpr (K == 32) {
-        // lower-left block of L11^{-1}: X = -L_{22}^{-1} (L_{21} L_{11}^{-1}) with
-        // the 16 x 16 blocks of L11 (two matrix-core products; the accumulator
-        // layout of a tile is the B operand layout of the next product)
-        wave_fence();
-        V ai, t1 = V{0, 0, 0, 0}, x = V{0, 0, 0, 0};
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const int row = acc_row<T>(lane, v), col = lane & 15;
-          const T e = lib[row * PT + col];
-          ai[v] = row > col ? e : (row == col ? T(1) : T(0));
-        }
-#pragma unroll
-        for (int step = 0; step < 4; ++step)
-          t1 = mfma_step(lib[(16 + (lane & 15)) * PT + frag_k<T>(step, lane >> 4)], ai[step], t1);
-#pragma unroll
-        for (int step = 0; step < 4; ++step) {
-          const int i = lane & 15, kk = frag_k<T>(step, lane >> 4);
-          const T e = lib[(16 + i) * PT + 16 + kk];
-          x = mfma_step(-(kk < i ? e : (kk == i ? T(1) : T(0))), t1[step], x);
-        }
-        wave_fence();
-#pragma unroll
-        for (int v = 0; v < 4; ++v) lib[(16 + acc_row<T>(lane, v)) * PT + (lane & 15)] = x[v];
-      }
+      if constexpr (K == 32) lower_offdiag_inverse<T>(lib, PT, lane);
       wave_fence();  // L11^{-1} and L21 visible to the products issued below
       // U11^{-1} rows, then lib <- U11^{-1} on and above the diagonal (a fresh
       // opaque lane index: lane masks are not shared with the forward pass).
@@ -394,29 +428,7 @@ __global__ __launch_bounds__(64) void factor_wave_kernel(FactorArgs a) {
 #pragma unroll
         for (int c = 0; c < K; ++c)
           if (c >= lane) lib[lane * PT + c] = (c < (lane | 15) + 1) ? iv[c] : pa[c];
-      if constexpr (K == 32) {
-        // upper-right block of U11^{-1}: Y = -U_{11}^{-1} (U_{12} U_{22}^{-1})
-        wave_fence();
-        V u2, t2 = V{0, 0, 0, 0}, y = V{0, 0, 0, 0};
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const int row = acc_row<T>(lane, v), col = lane & 15;
-          const T e = lib[(16 + row) * PT + 16 + col];
-          u2[v] = col >= row ? e : T(0);
-        }
-#pragma unroll
-        for (int step = 0; step < 4; ++step)
-          t2 = mfma_step(lib[(lane & 15) * PT + 16 + frag_k<T>(step, lane >> 4)], u2[step], t2);
-#pragma unroll
-        for (int step = 0; step < 4; ++step) {
-          const int i = lane & 15, kk = frag_k<T>(step, lane >> 4);
-          const T e = lib[i * PT + kk];
-          y = mfma_step(-(kk >= i ? e : T(0)), t2[step], y);
-        }
-        wave_fence();
-#pragma unroll
-        for (int v = 0; v < 4; ++v) lib[acc_row<T>(lane, v) * PT + 16 + (lane & 15)] = y[v];
-      }
+      if constexpr (K == 32) upper_offdiag_inverse<T>(lib, PT, lane);
       wave_sync();
     }
     // ---- G step (the columns of E_t met in this block enter the pending sum)
