@@ -250,14 +250,14 @@ def test_full_size_large_workload(gpu):
     assert rel(x, ref) <= 1e-12
 
 
-def _batch(count, seed, ks=(4, 16, 32), nmax=3000):
-    """count systems of the batched workload's kind: k drawn from ks, n up to nmax, 1..6 right-hand sides."""
+def _batch(count, seed, ks=(4, 16, 32), nmax=3000, mmax=6):
+    """count systems of the batched workload's kind: k drawn from ks, n up to nmax, 1..mmax right-hand sides."""
     rng = np.random.default_rng(seed)
     bl, fl = [], []
     for s in range(count):
         k = int(rng.choice(ks))
         n = int(rng.integers(max(8 * k, 100), nmax))
-        m = int(rng.integers(1, 7))
+        m = int(rng.integers(1, mmax + 1))
         b, f = synth.make_problem(n, k, m, seed=1000 * seed + s, rule="strict")
         bl.append(b)
         fl.append(f)
@@ -399,6 +399,19 @@ def test_k64_zero_pivot_is_latched(gpu):
     assert e.value.code == 1
     assert e.value.info["partition"] == 1
     assert e.value.info["row"] == row - 1000
+
+
+def test_batched_many_rhs(gpu):
+    """Up to 32 right-hand sides per system: several column chunks in every sweep kind."""
+    bl, fl = _batch(8, 7, ks=(4, 16, 32, 64), nmax=4000, mmax=32)
+    bands, rhs, descs = gpu.pack_systems(bl, fl)
+    assert max(d[4] for d in descs) > 16
+    plan = gpu.factor_batched(descs, to_dev(bands))
+    tr = to_dev(rhs)
+    plan.run(tr)
+    plan.status()
+    for s, xs in enumerate(_unpack(tr.cpu().numpy(), descs)):
+        assert rel(xs, oracle.lrspike(bl[s], fl[s], plan.partitions()[s], descs[s][3])) <= 1e-12, s
 
 
 def test_batched_with_k64_systems(gpu):
