@@ -317,7 +317,7 @@ int run_refined(lrspike_plan P, double* rhs, int m, int transpose) {
   P->refine_iters = 0;
   P->last_corr = INFINITY;
   double prev = INFINITY;
-  const size_t bres = (size_t)(RES_ROWS + 2 * L.k) * (RES_MC + 2) * 8;
+  const size_t bres = (size_t)(RES_ROWS + 2 * L.k) * (RES_MC + 1) * 8;
   if (!set_lds((const void*)residual_kernel, bres)) return LRSPIKE_ERR_NOT_SUPPORTED;
   for (int it = 0; it < P->max_refine; ++it) {
     LRS_LAUNCH("residual_kernel", residual_kernel, dim3((unsigned)((L.n + RES_ROWS - 1) / RES_ROWS)), dim3(RES_ROWS),

@@ -504,7 +504,8 @@ __global__ __launch_bounds__(RES_ROWS) void residual_kernel(const double* __rest
                                                             double* __restrict__ out, int ld, int m,
                                                             int transpose) {
   extern __shared__ double xs[];  // (RES_ROWS + 2k) x PX
-  constexpr int PX = RES_MC + 2;
+  // odd pitch: the rows the lanes of a wave read lie in different LDS banks
+  constexpr int PX = RES_MC + 1;
   const int t = threadIdx.x;
   const int64_t i0 = (int64_t)blockIdx.x * RES_ROWS, i = i0 + t;
   const int rows = RES_ROWS + 2 * k;
@@ -521,13 +522,26 @@ __global__ __launch_bounds__(RES_ROWS) void residual_kernel(const double* __rest
 #pragma unroll
     for (int cc = 0; cc < RES_MC; ++cc) acc[cc] = 0.0;
     if (i < n) {
-      for (int d = -k; d <= k; ++d) {
-        const int64_t jj = i + d;
-        double a = 0.0;
-        if (jj >= 0 && jj < n) a = transpose ? bands[(int64_t)(-d + k) * n + jj] : bands[(int64_t)(d + k) * n + i];
-        const double* xr = xs + (t + d + k) * PX;
+      // band entries in groups of RES_DG diagonals: the group's loads are
+      // issued together (unconditional, from clamped addresses) before use
+      constexpr int RES_DG = 8;
+      for (int d0 = -k; d0 <= k; d0 += RES_DG) {
+        double av[RES_DG];
 #pragma unroll
-        for (int cc = 0; cc < RES_MC; ++cc) acc[cc] = fma(-a, xr[cc], acc[cc]);
+        for (int u = 0; u < RES_DG; ++u) {
+          const int d = min(d0 + u, k);
+          const int64_t jj = min(max(i + d, (int64_t)0), n - 1);
+          av[u] = transpose ? bands[(int64_t)(-d + k) * n + jj] : bands[(int64_t)(d + k) * n + i];
+        }
+#pragma unroll
+        for (int u = 0; u < RES_DG; ++u) {
+          const int d = d0 + u;
+          const int64_t jj = i + d;
+          const double a = (d <= k && jj >= 0 && jj < n) ? av[u] : 0.0;
+          const double* xr = xs + (t + min(d, k) + k) * PX;
+#pragma unroll
+          for (int cc = 0; cc < RES_MC; ++cc) acc[cc] = fma(-a, xr[cc], acc[cc]);
+        }
       }
     }
     __syncthreads();
