@@ -3,14 +3,17 @@
 //
 // Per K-row block b (see factor.hip for the block formulation):
 //   panel [Dc_b; Lo_{b+1}] eliminated in registers (lane = row, the pivot row
-//   broadcast through LDS) WITHOUT row interchanges, an identity block riding
-//   along so that the first K lanes end with the rows of L11^{-1};  if any
-//   multiplier exceeds 1 in magnitude (or a pivot is zero) partial pivoting
-//   would have interchanged rows: the partition is flagged and refactored by
-//   the interchanging kernel, so the result is always the partial-pivoting
-//   factorization;
-//   U11^{-1} by an upward Gauss-Jordan pass over the same registers;
-//   U12 = L11^{-1} Up_b, Dc_{b+1} = D_{b+1} - L21 U12          (matrix cores)
+//   reaching the other lanes by lane reads) WITHOUT row interchanges, an
+//   identity block riding along so that the first K lanes end with the rows of
+//   L11^{-1} (its 16 x 16 diagonal blocks; at K = 32 the block below them by
+//   two matrix-core products);  if any multiplier exceeds 1 in magnitude (or a
+//   pivot is zero) partial pivoting would have interchanged rows: the
+//   partition is flagged and refactored by the interchanging kernel, so the
+//   result is always the partial-pivoting factorization;
+//   U11^{-1} by an upward Gauss-Jordan pass over the same registers (again on
+//   the 16 x 16 diagonal blocks, the block right of them by products), with
+//   U12 = L11^{-1} Up_b and Dc_{b+1} = D_{b+1} - L21 U12 issued on the matrix
+//   cores alongside it;
 //   G step:    g_b = U11^{-T} (e_b + pending), pending' = -U12^T g_b (matrix cores)
 // The spike forward sweeps run afterwards in spike_wave_kernel over the
 // stored factors (same structure as the D-stage of the solve).
