@@ -236,18 +236,24 @@ __device__ void fwd_wave(const SolveArgs& a, const Geom& g, int j, int c0, T* ld
     load_strip<T, K, MCT>(w1, a.src, a.ld, g, 1, c0, a.m, Ct, Cb);
   else
     zero_strip<T, K, MCT>(w1);
-  T lp[NF], gt[NF], lpn[NF], gtn[NF];
+  // factor fragments, flags and right-hand-side rows are fetched two blocks
+  // ahead (one wave per SIMD: one block of work does not cover the memory
+  // latency)
+  T lp[NF], gt[NF], lpn[NF], gtn[NF], lp2[NF], gt2[NF];
   load_frags<T, K>(lp, fac);
   if (DSTAGE) load_frags<T, K>(gt, gm);
-  int fl = flg[0];
+  int fl = flg[0], fln = 0, fl2 = 0;
+  if (g.nb > 1) {
+    load_frags<T, K>(lpn, fac + (size_t)L.rec);
+    if (DSTAGE) load_frags<T, K>(gtn, gm + (size_t)K * K);
+    fln = flg[1];
+  }
   for (int b = 0; b < g.nb; ++b) {
     const bool last = (b == g.nb - 1);
-    int fln = 0;
-    // prefetch: next block's fragments and flag, rows of block b + 2
-    if (!last) {
-      load_frags<T, K>(lpn, fac + (size_t)(b + 1) * L.rec);
-      if (DSTAGE) load_frags<T, K>(gtn, gm + (size_t)(b + 1) * K * K);
-      fln = flg[b + 1];
+    if (b + 2 < g.nb) {
+      load_frags<T, K>(lp2, fac + (size_t)(b + 2) * L.rec);
+      if (DSTAGE) load_frags<T, K>(gt2, gm + (size_t)(b + 2) * K * K);
+      fl2 = flg[b + 2];
     }
     if (b + 2 < g.nb)
       load_strip<T, K, MCT>(nx, a.src, a.ld, g, b + 2, c0, a.m, Ct, Cb);
@@ -298,14 +304,17 @@ __device__ void fwd_wave(const SolveArgs& a, const Geom& g, int j, int c0, T* ld
         w0[t][ct] = w1[t][ct];
         w1[t][ct] = nx[t][ct];
       }
-    if (!last) {
 #pragma unroll
-      for (int f = 0; f < NF; ++f) {
-        lp[f] = lpn[f];
-        if (DSTAGE) gt[f] = gtn[f];
+    for (int f = 0; f < NF; ++f) {
+      lp[f] = lpn[f];
+      lpn[f] = lp2[f];
+      if (DSTAGE) {
+        gt[f] = gtn[f];
+        gtn[f] = gt2[f];
       }
-      fl = fln;
     }
+    fl = fln;
+    fln = fl2;
   }
 }
 
@@ -322,20 +331,27 @@ __device__ void bwd_wave(const SolveArgs& a, const Geom& g, int j, int c0) {
   V x1[W::RT][MCT], x2[W::RT][MCT], zb[W::RT][MCT], zn[W::RT][MCT], xb[W::RT][MCT];
   zero_strip<T, K, MCT>(x1);
   zero_strip<T, K, MCT>(x2);
-  T up[NF], upn[NF], ud[W::RT][4], udn[W::RT][4];
+  // records, flags and z rows are fetched two blocks ahead
+  T up[NF], upn[NF], up2[NF], ud[W::RT][4], udn[W::RT][4], ud2[W::RT][4];
+  V zn2[W::RT][MCT];
   int b = g.nb - 1;
   load_frags<T, K>(up, fac + (size_t)b * L.rec + K * K);
   load_udrows<T, K>(ud, fac + (size_t)b * L.rec + 2 * K * K);
-  int fl = flg[b];
+  int fl = flg[b], fln = 0, fl2 = 0;
   load_strip<T, K, MCT>(zb, a.dst, a.ld, g, b, c0, a.m, nullptr, nullptr);
+  if (b > 0) {
+    load_frags<T, K>(upn, fac + (size_t)(b - 1) * L.rec + K * K);
+    load_udrows<T, K>(udn, fac + (size_t)(b - 1) * L.rec + 2 * K * K);
+    fln = flg[b - 1];
+    load_strip<T, K, MCT>(zn, a.dst, a.ld, g, b - 1, c0, a.m, nullptr, nullptr);
+  }
   for (; b >= 0; --b) {
     const bool last = (b == g.nb - 1);
-    int fln = 0;
-    if (b > 0) {
-      load_frags<T, K>(upn, fac + (size_t)(b - 1) * L.rec + K * K);
-      load_udrows<T, K>(udn, fac + (size_t)(b - 1) * L.rec + 2 * K * K);
-      fln = flg[b - 1];
-      load_strip<T, K, MCT>(zn, a.dst, a.ld, g, b - 1, c0, a.m, nullptr, nullptr);
+    if (b > 1) {
+      load_frags<T, K>(up2, fac + (size_t)(b - 2) * L.rec + K * K);
+      load_udrows<T, K>(ud2, fac + (size_t)(b - 2) * L.rec + 2 * K * K);
+      fl2 = flg[b - 2];
+      load_strip<T, K, MCT>(zn2, a.dst, a.ld, g, b - 2, c0, a.m, nullptr, nullptr);
     }
     if (!last) {
       if (fl & 2) {
@@ -361,16 +377,22 @@ __device__ void bwd_wave(const SolveArgs& a, const Geom& g, int j, int c0) {
         x2[t][ct] = x1[t][ct];
         x1[t][ct] = xb[t][ct];
         zb[t][ct] = zn[t][ct];
+        zn[t][ct] = zn2[t][ct];
       }
-    if (b > 0) {
 #pragma unroll
-      for (int f = 0; f < NF; ++f) up[f] = upn[f];
-#pragma unroll
-      for (int t = 0; t < W::RT; ++t)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) ud[t][v] = udn[t][v];
-      fl = fln;
+    for (int f = 0; f < NF; ++f) {
+      up[f] = upn[f];
+      upn[f] = up2[f];
     }
+#pragma unroll
+    for (int t = 0; t < W::RT; ++t)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        ud[t][v] = udn[t][v];
+        udn[t][v] = ud2[t][v];
+      }
+    fl = fln;
+    fln = fl2;
   }
 }
 
