@@ -147,7 +147,6 @@ template <typename T, int K>
 int run_factor(lrspike_plan P) {
   const Layout& L = P->L;
   FactorArgs fa{P->bands, P->ws, L};
-  hipStream_t st = P->stream;
   size_t b1 = 0;
   if constexpr (K <= 32) {
     b1 = lds_p1<T, K>();
@@ -225,7 +224,6 @@ template <int K>
 int run_reduced(lrspike_plan P, int m, int transpose) {
   const Layout& L = P->L;
   if (L.NI <= 0 || L.r <= 0) return 0;
-  hipStream_t st = P->stream;
   RedArgs ra{P->ws, L, 0, m, transpose};
   size_t bz = (size_t)4 * K * m * 8;
   if (!set_lds((const void*)zrhs_kernel<K>, bz)) return LRSPIKE_ERR_NOT_SUPPORTED;
@@ -255,7 +253,6 @@ int run_reduced(lrspike_plan P, int m, int transpose) {
 template <typename T, int K>
 int run_apply(lrspike_plan P, double* rhs, int m, int transpose) {
   const Layout& L = P->L;
-  hipStream_t st = P->stream;
   SolveArgs sa{P->bands, P->ws, L, rhs, rhs, m, m};
   dim3 grid(L.p, (m + mc_of<K>() - 1) / mc_of<K>());
   size_t bs = lds_sw<T, K>();

@@ -125,7 +125,6 @@ __global__ __launch_bounds__(LRS_NT) void factor_lds_kernel(FactorArgs a) {
   if (tid == 0) s_bad = 0;
   for (int b = 0; b < nb; ++b) {
     const bool last = (b == nb - 1);
-    const int nr = last ? K : 2 * K;
     if (!last) {
       load_block(P + K * PT, b + 1, b);
       load_block(U, b, b + 1);

@@ -32,8 +32,7 @@ struct FWave {
   static constexpr int oSlab = 0;                    // (2K+1) x K, diagonal-major
   static constexpr int oLib = oSlab + (2 * K + 1) * K;  // K x PT
   static constexpr int oL21 = oLib + K * PT;         // K x PT
-  static constexpr int oRow = oL21 + K * PT;         // broadcast pivot row, 2K
-  static constexpr int total = oRow + 2 * K;
+  static constexpr int total = oL21 + K * PT;
 };
 
 __device__ __forceinline__ void wave_fence() {  // order LDS accesses of one wave
@@ -193,7 +192,6 @@ __global__ __launch_bounds__(64) void factor_wave_kernel(FactorArgs a) {
   T* slab = lds + F::oSlab;
   T* lib = lds + F::oLib;
   T* l21b = lds + F::oL21;
-  T* prow = lds + F::oRow;
   const Layout& L = a.L;
   const int j = blockIdx.x, k = L.k;
   int lane = threadIdx.x & 63;
@@ -329,7 +327,6 @@ __global__ __launch_bounds__(64) void factor_wave_kernel(FactorArgs a) {
     asm volatile("" : "+v"(lane));  // (same: no lane-derived values kept across blocks)
     T nx[NS];  // band slab of block b + 2, fetched below and stored once this block is done with the slab
     auto Li = [&](int i, int kk) -> T { return i > kk ? lib[i * PT + kk] : (i == kk ? T(1) : T(0)); };
-    auto Ui = [&](int i, int kk) -> T { return i <= kk ? lib[i * PT + kk] : T(0); };
     auto UiT = [&](int i, int kk) -> T { return kk <= i ? lib[kk * PT + i] : T(0); };
     auto L21 = [&](int i, int kk) -> T { return i <= kk ? l21b[i * PT + kk] : T(0); };
     V u12[RT][RT], dn[RT][RT];
