@@ -44,9 +44,23 @@ extern "C" {
 typedef struct lrspike_plan_s *lrspike_plan; /* opaque host object */
 
 enum {
-  LRSPIKE_FP64 = 0,         /* factors, spikes and sweeps in FP64 */
-  LRSPIKE_FP32_REFINED = 1  /* FP32 factors/spikes/sweeps; FP64 reduced system,
+  LRSPIKE_FP64 = 0,         /* factors, spikes and sweeps in FP64; one application of M_r^{-1} */
+  LRSPIKE_FP32_REFINED = 1, /* FP32 factors/spikes/sweeps; FP64 reduced system,
                                residual and update in iterative refinement */
+  LRSPIKE_FP64_REFINED = 2  /* FP64 factors; M_r^{-1} as the preconditioner of an iterative
+                               refinement with FP64 residual: x = A^{-1} rhs to refine_tol for
+                               any r (and A^{-T} for the adjoint) */
+};
+
+/* Reduced interface system (the variant table of section "Selected LR-SPIKE
+ * Algorithms"). */
+enum {
+  LRSPIKE_VARIANT_FULL = 0, /* the whole truncated reduced system S~_red, solved directly */
+  LRSPIKE_VARIANT_T = 1     /* LR-SPIKE-T: the truncated-SPIKE form of it, S~~_red (eqs.
+                               truncated_redsys, red_sys_prec_mid_1/2): only the 2 x 2 interface
+                               blocks [[I, V~_{j,b}], [W~_{j+1,t}, I]] are kept, solved
+                               independently per interface (eqs. red_sys_1, red_sys_mid,
+                               red_sys_3); the tips V~_{j,t}, W~_{j,b} are dropped */
 };
 
 enum {
@@ -54,7 +68,9 @@ enum {
   LRSPIKE_ERR_ZERO_PIVOT = 1,       /* a partition LU met an exactly zero pivot */
   LRSPIKE_ERR_REDUCED_SINGULAR = 2, /* zero pivot in the reduced system */
   LRSPIKE_ERR_NOT_CONVERGED = 3,    /* refinement did not reach refine_tol */
-  LRSPIKE_ERR_NONFINITE = 4,        /* Inf/NaN met in the band or the result */
+  LRSPIKE_ERR_NONFINITE = 4,        /* Inf/NaN met in a pivot of a partition LU (partition, row),
+                                       in the reduced system (interface, -1), or in a correction
+                                       of a refined solve (-1, -1) */
   LRSPIKE_ERR_HIP = 5,              /* a HIP runtime call failed */
   LRSPIKE_ERR_NOT_SUPPORTED = 6,    /* parameter combination not built (k > 64, 2r > 64), or a
                                        partition at k > 32 that needs row interchanges */
@@ -62,17 +78,20 @@ enum {
 };
 
 typedef struct {
-  int32_t precision;     /* LRSPIKE_FP64 (default) or LRSPIKE_FP32_REFINED */
-  int32_t max_refine;    /* FP32_REFINED: max corrections (default 30) */
-  double refine_tol;     /* FP32_REFINED: relative accuracy to reach (default 1e-13).  With
-                            c_i = max over columns of ||d_c||_2 / ||x_c||_2 for correction i, the
+  int32_t precision;     /* LRSPIKE_FP64 (default), LRSPIKE_FP32_REFINED or LRSPIKE_FP64_REFINED */
+  int32_t max_refine;    /* refined precisions: max corrections (default 30).  The stopping rule
+                            runs on the device; under stream capture all max_refine corrections
+                            are recorded (those after the stop do nothing), so keep it small there */
+  double refine_tol;     /* refined precisions: relative accuracy to reach (default 1e-13).  With
+                            c_i = max over (system, column) of ||d_c||_2 / ||x_c||_2 for correction i, the
                             iteration stops when c_i <= tol, or when the error left after the update,
                             estimated as 10 rho c_i, is <= tol, where the contraction rho is
                             c_i / c_{i-1} (c_0 itself for the first correction, the accuracy of the
                             FP32 solve) and is trusted only below 1e-2.  A correction that shrinks
                             by less than half ends the iteration: converged if it is already
                             <= 100 tol (the rounding level of an ill-conditioned system), else
-                            NOT_CONVERGED is latched */
+                            NOT_CONVERGED is latched (also after max_refine corrections); a
+                            non-finite correction latches NONFINITE */
   void *stream;          /* hipStream_t to enqueue on; NULL = null stream */
   void *workspace;       /* device memory of >= lrspike_workspace_size bytes, caller-owned,
                             must outlive the plan */
@@ -81,6 +100,7 @@ typedef struct {
                             sizes the per-solve vectors inside the workspace */
   int32_t profile;       /* nonzero: time every kernel launch of this plan with a HIP
                             event pair on the plan's stream (see lrspike_profile_read) */
+  int32_t variant;       /* LRSPIKE_VARIANT_FULL (default) or LRSPIKE_VARIANT_T */
 } lrspike_opts;
 
 /* Fill *opts with the defaults above (no workspace, null stream). */
@@ -107,7 +127,8 @@ int lrspike_workspace_size(int64_t n, int32_t k, int32_t p, int32_t r,
  *          above 1 in magnitude) latches NOT_SUPPORTED for that partition
  *   bands  device pointer, (2k+1) x n band-major doubles; borrowed: it must
  *          stay valid (unchanged) for the plan's lifetime when precision is
- *          FP32_REFINED (the residual reads it) and for lrspike_band_grad
+ *          refined (the residual reads it), for LRSPIKE_VARIANT_T and the
+ *          retrieval (the coupling blocks are read from it) and for lrspike_band_grad
  *   p      number of partitions, 1 <= p <= n; each partition needs >= 2k rows
  *          when p > 1
  *   r      retained singular values per spike (the paper's n_svd), 0 <= r <= k;
@@ -121,7 +142,7 @@ int lrspike_factor(int64_t n, int32_t k, const double *bands, int32_t p, int32_t
 /*
  * Solve stage (D-stage, reduced system, recovery; the summary of the SPIKE
  * solve).  In place: rhs (n x nrhs, row-major) is overwritten by
- * x = M_r^{-1} rhs, which is A^{-1} rhs at r = k.  With FP32_REFINED the
+ * x = M_r^{-1} rhs, which is A^{-1} rhs at r = k.  With a refined precision the
  * solve iterates x += M_r^{-1}(rhs - A x) with the residual in FP64 until the
  * tolerance (then x is A^{-1} rhs to that tolerance for any r).
  *   nrhs   1 <= nrhs <= opts.max_nrhs of the factor call
@@ -130,7 +151,7 @@ int lrspike_solve(lrspike_plan plan, double *rhs, int32_t nrhs);
 
 /*
  * Adjoint solve: rhs is overwritten by M_r^{-T} rhs, the exact transpose of
- * the operator lrspike_solve applies (A^{-T} rhs at r = k; with FP32_REFINED
+ * the operator lrspike_solve applies (A^{-T} rhs at r = k; with a refined precision
  * refined against A^T to the same tolerance).
  */
 int lrspike_solve_adjoint(lrspike_plan plan, double *rhs, int32_t nrhs);
@@ -148,9 +169,18 @@ typedef struct {
   int32_t error;          /* first latched LRSPIKE_ERR_* code, 0 if none */
   int32_t partition;      /* partition (or interface) of the first error, -1 if none */
   int64_t row;            /* partition-local row of the first error, -1 if none */
-  int32_t refine_iters;   /* corrections used by the last refined solve */
+  int32_t refine_iters;   /* corrections applied by the last refined solve */
   int32_t swapped_blocks; /* k-row blocks whose LU needed a row interchange */
-  double last_correction; /* max_c ||d_c|| / ||x_c|| of the last correction */
+  double last_correction; /* max over (system, column) of ||d_c|| / ||x_c|| of the last correction */
+  /* diagnostics of the factorization (the failure flags of the paper's
+     experiments made quantitative): */
+  double min_pivot;       /* min |pivot| over all partition LUs */
+  double max_abs_entry;   /* max |a_ij| over the band: min_pivot / max_abs_entry small = near-singular A_j */
+  double min_sigma_gap;   /* min over the truncated spikes of (sigma_r - sigma_{r+1}) / sigma_1; the
+                             rank-r truncation is well defined (unique) only when it is >> 1e-16;
+                             +inf when nothing is truncated (r = k or p = 1) */
+  double reduced_growth;  /* max |entry| of the reduced-system blocks inverted during its
+                             elimination / max |entry| of the reduced system (0 without one) */
 } lrspike_info;
 
 /* Synchronizes the plan's stream and returns (and reports) the latched state. */
@@ -217,8 +247,8 @@ int lrspike_solve_batched(lrspike_plan plan, double *rhs_base);
  * Factor (from the current contents of bands_base) and solve every system, as
  * one HIP graph: the first call with a given rhs_base runs eagerly and
  * captures the sequence; later calls with the same rhs_base replay the graph
- * (a new rhs_base captures again).  FP64 plans only (the refinement loop
- * reads norms on the host): NOT_SUPPORTED otherwise.
+ * (a new rhs_base captures again).  Refined plans record max_refine gated
+ * corrections per group (the device stopping rule makes the surplus no-ops).
  */
 int lrspike_run_batched(lrspike_plan plan, double *rhs_base);
 

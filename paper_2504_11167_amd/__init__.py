@@ -24,8 +24,10 @@ from . import build as _build
 __all__ = ["factor", "solve", "Plan", "BatchedPlan", "factor_batched", "pack_systems", "LRSpikeError",
            "library_path", "load_library"]
 
-FP64, FP32_REFINED = 0, 1
-_PRECISIONS = {"fp64": FP64, "fp32_refined": FP32_REFINED}
+FP64, FP32_REFINED, FP64_REFINED = 0, 1, 2
+_PRECISIONS = {"fp64": FP64, "fp32_refined": FP32_REFINED, "fp64_refined": FP64_REFINED}
+VARIANT_FULL, VARIANT_T = 0, 1
+_VARIANTS = {"full": VARIANT_FULL, "t": VARIANT_T}
 _ERRORS = {
     1: "ZERO_PIVOT", 2: "REDUCED_SINGULAR", 3: "NOT_CONVERGED", 4: "NONFINITE",
     5: "HIP_ERROR", 6: "NOT_SUPPORTED", 7: "WORKSPACE",
@@ -49,6 +51,7 @@ class _Opts(ctypes.Structure):
         ("workspace_bytes", ctypes.c_size_t),
         ("max_nrhs", ctypes.c_int32),
         ("profile", ctypes.c_int32),
+        ("variant", ctypes.c_int32),
     ]
 
 
@@ -60,6 +63,10 @@ class _Info(ctypes.Structure):
         ("refine_iters", ctypes.c_int32),
         ("swapped_blocks", ctypes.c_int32),
         ("last_correction", ctypes.c_double),
+        ("min_pivot", ctypes.c_double),
+        ("max_abs_entry", ctypes.c_double),
+        ("min_sigma_gap", ctypes.c_double),
+        ("reduced_growth", ctypes.c_double),
     ]
 
 
@@ -145,7 +152,7 @@ class Plan:
     """A factored LR-SPIKE plan: the factors live in a caller-owned workspace tensor."""
 
     def __init__(self, bands, p, r, precision="fp64", max_nrhs=32, max_refine=30, refine_tol=1e-13,
-                 workspace=None, profile=False):
+                 workspace=None, profile=False, variant="full"):
         lib = load_library()
         if not isinstance(bands, torch.Tensor) or bands.device.type != "cuda" or bands.dtype != torch.float64:
             raise TypeError("bands must be a float64 CUDA tensor of shape (2k+1, n)")
@@ -155,6 +162,7 @@ class Plan:
         self.n = bands.shape[1]
         self.p, self.r = int(p), int(r)
         self.precision = precision
+        self.variant = variant
         self.max_nrhs = int(max_nrhs)
         self.bands = bands  # borrowed by the library for the plan's lifetime
         nbytes = workspace_bytes(self.n, self.k, self.p, self.r, precision, self.max_nrhs)
@@ -173,6 +181,7 @@ class Plan:
         opts.workspace_bytes = nbytes
         opts.max_nrhs = self.max_nrhs
         opts.profile = 1 if profile else 0
+        opts.variant = _VARIANTS[variant]
         handle = ctypes.c_void_p()
         rc = lib.lrspike_factor(self.n, self.k, bands.data_ptr(), self.p, self.r, ctypes.byref(opts),
                                 ctypes.byref(handle))
@@ -187,7 +196,7 @@ class Plan:
             self._lib.lrspike_destroy(h)
             self._h = None
 
-    def _apply(self, b, inplace, adjoint):
+    def _apply(self, b, inplace, adjoint, check=False):
         _check_vec(b, self.n, "rhs")
         x = b if inplace else b.clone()
         m = 1 if x.dim() == 1 else x.shape[1]
@@ -202,15 +211,18 @@ class Plan:
                 x[:, c0:c0 + cols] = blk
             if rc:
                 raise LRSpikeError(rc, "lrspike_solve_adjoint" if adjoint else "lrspike_solve")
+        if check:
+            self.status()
         return x
 
-    def solve(self, b, inplace=False):
-        """x = M_r^{-1} b (A^{-1} b at r = k, or refined to tolerance with fp32_refined)."""
-        return self._apply(b, inplace, False)
+    def solve(self, b, inplace=False, check=False):
+        """x = M_r^{-1} b (A^{-1} b at r = k, or refined to tolerance with a refined precision).
+        check=True synchronizes and raises LRSpikeError on any device-latched error."""
+        return self._apply(b, inplace, False, check)
 
-    def solve_adjoint(self, g, inplace=False):
-        """M_r^{-T} g, the exact transpose of solve."""
-        return self._apply(g, inplace, True)
+    def solve_adjoint(self, g, inplace=False, check=False):
+        """M_r^{-T} g, the exact transpose of solve (refined against A^T with a refined precision)."""
+        return self._apply(g, inplace, True, check)
 
     def band_grad(self, lam, x):
         """-lam x^T restricted to the band, shape (2k+1, n)."""
@@ -257,17 +269,28 @@ class Plan:
 
 
 def factor(bands, p, r, precision="fp64", max_nrhs=32, **kw):
+    """Factor A (bands: (2k+1, n) float64 CUDA tensor) into p partitions at rank r.
+    precision: "fp64", "fp32_refined" or "fp64_refined"; variant: "full" (LR-SPIKE) or "t" (LR-SPIKE-T)."""
     return Plan(bands, p, r, precision=precision, max_nrhs=max_nrhs, **kw)
 
 
 class LRSpikeSolve(torch.autograd.Function):
     """x = A^{-1} b through LR-SPIKE; backward through the adjoint solve:
-    grad_b = A^{-T} grad_x, grad_bands = -lam x^T on the band."""
+    grad_b = A^{-T} grad_x, grad_bands = -lam x^T on the band.
+
+    These are the gradients of the converged solve x = A^{-1} b.  At r = k one
+    application of the FP64 plan is that solve; at r < k the plan's operator
+    M_r^{-1} differs from A^{-1} (and depends on A through the truncated
+    spikes), so the plan is FP64_REFINED: M_r^{-1} preconditions an iterative
+    refinement with FP64 residual, forward against A and backward against A^T,
+    to refine_tol.  Any device-latched error (zero pivot, non-convergence,
+    non-finite data) raises LRSpikeError in forward or backward."""
 
     @staticmethod
-    def forward(ctx, bands, b, p, r, precision):
-        plan = Plan(bands.detach(), p, r, precision=precision, max_nrhs=max(1, 1 if b.dim() == 1 else b.shape[1]))
-        x = plan.solve(b.detach())
+    def forward(ctx, bands, b, p, r, precision, refine_tol):
+        m = 1 if b.dim() == 1 else b.shape[1]
+        plan = Plan(bands.detach(), p, r, precision=precision, max_nrhs=max(1, m), refine_tol=refine_tol)
+        x = plan.solve(b.detach(), check=True)
         ctx.plan = plan
         ctx.save_for_backward(x)
         return x
@@ -276,16 +299,27 @@ class LRSpikeSolve(torch.autograd.Function):
     def backward(ctx, gx):
         (x,) = ctx.saved_tensors
         plan = ctx.plan
-        lam = plan.solve_adjoint(gx.contiguous())
+        lam = plan.solve_adjoint(gx.contiguous(), check=True)
         gbands = plan.band_grad(lam, x) if ctx.needs_input_grad[0] else None
-        return gbands, (lam if ctx.needs_input_grad[1] else None), None, None, None
+        return gbands, (lam if ctx.needs_input_grad[1] else None), None, None, None, None
 
 
-def solve(bands, b, p, r=None, precision="fp64"):
-    """Differentiable x = A^{-1} b (r defaults to k, where LR-SPIKE is exact)."""
+def solve(bands, b, p, r=None, precision=None, refine_tol=1e-13):
+    """Differentiable x = A^{-1} b (r defaults to k, where LR-SPIKE is exact).
+
+    precision defaults to "fp64" at r = k and to "fp64_refined" at r < k, so
+    that forward and gradients are those of A^{-1} b; "fp32_refined" is also
+    accepted.  A plain "fp64" plan at r < k would apply M_r^{-1}, whose band
+    gradient is not -lam x^T, and is refused."""
+    k = (bands.shape[0] - 1) // 2
     if r is None:
-        r = (bands.shape[0] - 1) // 2
-    return LRSpikeSolve.apply(bands, b, p, r, precision)
+        r = k
+    if precision is None:
+        precision = "fp64" if r == k else "fp64_refined"
+    if precision == "fp64" and r != k:
+        raise ValueError("solve(): at r < k the gradient of the one-shot operator is not -lam x^T; "
+                         "use precision='fp64_refined' (the default) or 'fp32_refined'")
+    return LRSpikeSolve.apply(bands, b, p, r, precision, refine_tol)
 
 
 def pack_systems(bands_list, rhs_list, p=None, r=None):

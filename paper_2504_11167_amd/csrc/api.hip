@@ -37,9 +37,9 @@ struct lrspike_plan_s {
   hipStream_t stream;
   const double* bands;
   char* ws;
-  int refine_iters;
-  double last_corr;
-  int last_error;
+  int variant = 0;                // LRSPIKE_VARIANT_*
+  int* hstate = nullptr;          // pinned host slots: refinement state copied back per correction
+  hipEvent_t hev[2] = {nullptr, nullptr};
   // opt-in per-launch timing: an event pair around every kernel on the plan's stream
   int profiling;
   std::vector<std::pair<const char*, std::pair<hipEvent_t, hipEvent_t>>> prof;
@@ -55,43 +55,137 @@ __global__ void zero_kernel(int* p, int n) {
   if (i < n) p[i] = 0;
 }
 
-// x += d over `total` elements of an n x m row-major block, and the per-column
-// squared norms of the new x and of d added into out[2c], out[2c+1].  When
-// the grid stride is a multiple of m every thread stays in one column and
-// accumulates in registers; otherwise each element goes to an LDS atomic.
-__global__ void axpy_norms_kernel(double* x, const double* d, int64_t total, int m, double* out) {
+// State block at factor time: everything 0, the running minima +inf.
+__global__ void state_init_kernel(int* st) {
+  const int i = threadIdx.x;
+  if (i < STATE_INTS) st[i] = 0;
+  __syncthreads();
+  if (i == 0) {
+    const unsigned long long inf = 0x7FF0000000000000ull;
+    *reinterpret_cast<unsigned long long*>(st + S_PIVMIN) = inf;
+    *reinterpret_cast<unsigned long long*>(st + S_GAPMIN) = inf;
+  }
+}
+
+// Start of a refined solve: control slots cleared, norms zeroed.
+__global__ void refine_reset_kernel(int* st, double* norms, int nslots) {
+  const int i = threadIdx.x;
+  if (i == 0) {
+    st[S_STOP] = 0;
+    st[S_ITERS] = 0;
+    st[S_RSTATE] = 0;
+    *reinterpret_cast<double*>(st + S_CORR) = 0.0;
+    *reinterpret_cast<double*>(st + S_CPREV) = 0.0;
+  }
+  for (int o = i; o < 2 * nslots; o += blockDim.x) norms[o] = 0.0;
+}
+
+// x += d on the rows of one partition (blockIdx.x) and chunk of REF_ROWS rows
+// (blockIdx.y), and the squared norms of the new x and of d per (system slot
+// of the partition, column) added into norms[(slot mmax + c) 2 + {0, 1}].
+// When the block size is a multiple of m every thread stays in one column
+// and accumulates in registers; otherwise each element goes to an LDS atomic.
+#define REF_ROWS 2048
+__global__ __launch_bounds__(256) void refine_update_kernel(double* x, const double* d, Layout L, int m,
+                                                            double* norms, const int* gate) {
+  if (gate && *gate) return;
   extern __shared__ double red[];  // 2m
+  const int j = blockIdx.x;
+  int64_t s0, nj;
+  if (L.offs) {
+    s0 = L.offs[j];
+    nj = L.offs[j + 1] - s0;
+  } else {
+    const int64_t base = L.n / L.p, extra = L.n % L.p;
+    nj = base + (j < extra ? 1 : 0);
+    s0 = (int64_t)j * base + (j < extra ? j : extra);
+  }
+  const int64_t r0 = (int64_t)blockIdx.y * REF_ROWS;
+  if (r0 >= nj) return;
+  const int64_t rows = min((int64_t)REF_ROWS, nj - r0);
   for (int c = threadIdx.x; c < 2 * m; c += blockDim.x) red[c] = 0.0;
   __syncthreads();
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  const bool fixed = (stride % m) == 0;
+  const bool fixed = (blockDim.x % m) == 0;
+  const int64_t e0 = (s0 + r0) * m, total = rows * m;
   double sx = 0.0, sd = 0.0;
-  int cfix = -1;
-  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += stride) {
-    const double dv = d[e], xv = x[e] + dv;
-    x[e] = xv;
+  for (int64_t e = threadIdx.x; e < total; e += blockDim.x) {
+    const double dv = d[e0 + e], xv = x[e0 + e] + dv;
+    x[e0 + e] = xv;
     if (fixed) {
       sx = fma(xv, xv, sx);
       sd = fma(dv, dv, sd);
-      cfix = (int)(e % m);
     } else {
       const int c = (int)(e % m);
       atomicAdd(&red[2 * c], xv * xv);
       atomicAdd(&red[2 * c + 1], dv * dv);
     }
   }
-  if (cfix >= 0) {
-    atomicAdd(&red[2 * cfix], sx);
-    atomicAdd(&red[2 * cfix + 1], sd);
+  if (fixed && threadIdx.x < total) {
+    const int c = (int)(threadIdx.x % m);
+    atomicAdd(&red[2 * c], sx);
+    atomicAdd(&red[2 * c + 1], sd);
   }
   __syncthreads();
+  const int slot = L.psys ? L.psys[j] : 0;
   for (int c = threadIdx.x; c < 2 * m; c += blockDim.x)
-    if (red[c] != 0.0) atomicAdd(out + c, red[c]);
+    if (red[c] != 0.0) atomicAdd(norms + (size_t)slot * 2 * L.mmax + c, red[c]);
 }
 
-__global__ void zero_d_kernel(double* p, int n) {
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) p[i] = 0.0;
+// Stopping rule of the refinement, on the device (no host round trip per
+// correction).  With c_i = max over (system, column) of ||d|| / ||x|| for
+// correction i: stop converged when c_i <= tol, or when the error left after
+// the update, estimated by linear convergence as 10 rho c_i, is <= tol
+// (rho = c_i / c_{i-1}, or c_0 itself for the first correction, trusted only
+// below 1e-2); a correction that shrinks by less than half stops the
+// iteration, converged if c_i <= 100 tol (the rounding level of an
+// ill-conditioned system), else NOT_CONVERGED; a non-finite correction
+// latches NONFINITE; the last allowed correction without convergence latches
+// NOT_CONVERGED.  A stop sets the gate that turns the later corrections into
+// no-ops.  The norms are cleared for the next correction.
+__global__ void refine_ctl_kernel(int* st, double* norms, int nsys, int m, int mmax, double tol, int it,
+                                  int max_it) {
+  if (st[S_STOP]) return;
+  const int lane = threadIdx.x;  // one wave
+  double worst = 0.0;
+  bool bad = false;
+  for (int o = lane; o < nsys * m; o += 64) {
+    const int sy = o / m, c = o % m;
+    const double nx = sqrt(norms[((size_t)sy * mmax + c) * 2]), nd = sqrt(norms[((size_t)sy * mmax + c) * 2 + 1]);
+    double rel = nd == 0.0 ? 0.0 : nd / (nx > 0.0 ? nx : 1.0);
+    bad |= !(rel <= 1.7976931348623157e308);
+    worst = fmax(worst, rel);
+  }
+  worst = wave_max(worst);
+  bad = __any(bad);
+  __syncthreads();
+  for (int o = lane; o < 2 * nsys * mmax; o += 64) norms[o] = 0.0;
+  if (lane != 0) return;
+  double* corr = reinterpret_cast<double*>(st + S_CORR);
+  double* cprev = reinterpret_cast<double*>(st + S_CPREV);
+  const double prev = *corr;
+  *cprev = prev;
+  *corr = bad ? INFINITY : worst;
+  st[S_ITERS] = it + 1;
+  int verdict = 0;  // 1 converged, 2 failed
+  if (bad) {
+    verdict = 2;
+    latch_error(st, 4, -1, -1);
+  } else if (worst <= tol) {
+    verdict = 1;
+  } else {
+    const double rho = it == 0 ? worst : worst / prev;
+    if (rho < 1e-2 && 10.0 * rho * worst <= tol)
+      verdict = 1;
+    else if (it > 0 && worst > 0.5 * prev)
+      verdict = worst <= 100.0 * tol ? 1 : 2;
+    else if (it + 1 >= max_it)
+      verdict = 2;
+    if (verdict == 2) latch_error(st, 3, -1, -1);
+  }
+  if (verdict) {
+    st[S_RSTATE] = verdict;
+    st[S_STOP] = 1;
+  }
 }
 
 template <typename T, int K>
@@ -221,10 +315,10 @@ int run_factor(lrspike_plan P) {
 
 // Reduced solve on the compressed vectors (Z or Z^T), in place in zg.
 template <int K>
-int run_reduced(lrspike_plan P, int m, int transpose) {
+int run_reduced(lrspike_plan P, int m, int transpose, const int* gate) {
   const Layout& L = P->L;
   if (L.NI <= 0 || L.r <= 0) return 0;
-  RedArgs ra{P->ws, L, 0, m, transpose};
+  RedArgs ra{P->ws, L, 0, m, transpose, gate};
   size_t bz = (size_t)4 * K * m * 8;
   if (!set_lds((const void*)zrhs_kernel<K>, bz)) return LRSPIKE_ERR_NOT_SUPPORTED;
   LRS_LAUNCH("zrhs_kernel", zrhs_kernel<K>, dim3(L.NI), dim3(256), bz, ra, P->bands);
@@ -250,10 +344,11 @@ int run_reduced(lrspike_plan P, int m, int transpose) {
 }
 
 // One application of M_r^{-1} (transpose = 0) or M_r^{-T} (transpose = 1), in place.
+// gate: refinement gate (null outside refinement), see refine_ctl_kernel.
 template <typename T, int K>
-int run_apply(lrspike_plan P, double* rhs, int m, int transpose) {
+int run_apply(lrspike_plan P, double* rhs, int m, int transpose, const int* gate = nullptr) {
   const Layout& L = P->L;
-  SolveArgs sa{P->bands, P->ws, L, rhs, rhs, m, m};
+  SolveArgs sa{P->bands, P->ws, L, rhs, rhs, m, m, gate};
   dim3 grid(L.p, (m + mc_of<K>() - 1) / mc_of<K>());
   size_t bs = lds_sw<T, K>();
   int rc;
@@ -269,7 +364,7 @@ int run_apply(lrspike_plan P, double* rhs, int m, int transpose) {
           LRS_LAUNCH("dstage_kernel", dstage_wave_kernel<T, K, 1>, gw, dim3(64), bw, sa);
         else
           LRS_LAUNCH("dstage_kernel", dstage_wave_kernel<T, K, 2>, gw, dim3(64), bw, sa);
-        if ((rc = run_reduced<K>(P, m, 0))) return rc;
+        if ((rc = run_reduced<K>(P, m, 0, gate))) return rc;
       }
       if (one)
         LRS_LAUNCH("retrieve_kernel", retrieve_wave_kernel<T, K, 1>, gw, dim3(64), bw, sa);
@@ -281,7 +376,7 @@ int run_apply(lrspike_plan P, double* rhs, int m, int transpose) {
       return LRSPIKE_ERR_NOT_SUPPORTED;
     if (L.p > 1) {
       LRS_LAUNCH("dstage_kernel", dstage_kernel<T, K>, grid, dim3(LRS_NT), bs, sa);
-      if ((rc = run_reduced<K>(P, m, 0))) return rc;
+      if ((rc = run_reduced<K>(P, m, 0, gate))) return rc;
     }
     LRS_LAUNCH("retrieve_kernel", retrieve_kernel<T, K>, grid, dim3(LRS_NT), bs, sa);
   } else {
@@ -291,14 +386,22 @@ int run_apply(lrspike_plan P, double* rhs, int m, int transpose) {
       SolveArgs sd = sa;
       sd.dst = reinterpret_cast<double*>(P->ws + L.scr);
       LRS_LAUNCH("adj_dstage_kernel", adj_dstage_kernel<T, K>, grid, dim3(LRS_NT), bs, sd);
-        if ((rc = run_reduced<K>(P, m, 1))) return rc;
+        if ((rc = run_reduced<K>(P, m, 1, gate))) return rc;
     }
     LRS_LAUNCH("adj_retrieve_kernel", adj_retrieve_kernel<T, K>, grid, dim3(LRS_NT), bs, sa);
   }
   return 0;
 }
 
-// Iterative refinement around run_apply (FP32 factors, FP64 residual/update).
+// Iterative refinement around run_apply: x_0 = M^{-1} f, then corrections
+// x += M^{-1}(f - A x) with the residual, the update and the norms in FP64
+// (M from FP32 factors in FP32_REFINED plans, from FP64 factors in
+// FP64_REFINED ones).  Every correction is a fixed kernel sequence gated by
+// the device stopping rule (refine_ctl_kernel), so the whole solve can be
+// captured into a graph: under capture all max_refine corrections are
+// enqueued (the ones after the stop are no-ops).  Run eagerly, the host
+// enqueues one correction ahead and stops enqueueing once the state copied
+// back from the previous one shows the stop, so the GPU never waits for it.
 template <typename T, int K>
 int run_refined(lrspike_plan P, double* rhs, int m, int transpose) {
   const Layout& L = P->L;
@@ -307,61 +410,47 @@ int run_refined(lrspike_plan P, double* rhs, int m, int transpose) {
   double* fcopy = reinterpret_cast<double*>(P->ws + L.fcopy);
   double* scr = reinterpret_cast<double*>(P->ws + L.res);  // not the adjoint D-stage scratch
   double* norms = reinterpret_cast<double*>(P->ws + L.norms);
+  int* state = reinterpret_cast<int*>(P->ws + L.latch);
+  const int* gate = state + S_STOP;
+  hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(st, &cap) != hipSuccess) return LRSPIKE_ERR_HIP;
+  const bool capturing = cap != hipStreamCaptureStatusNone;
   if (hipMemcpyAsync(fcopy, rhs, nm * 8, hipMemcpyDeviceToDevice, st) != hipSuccess) return LRSPIKE_ERR_HIP;
+  LRS_LAUNCH("refine_reset_kernel", refine_reset_kernel, dim3(1), dim3(256), 0, state, norms, L.nsys * L.mmax);
   int rc = run_apply<T, K>(P, rhs, m, transpose);
   if (rc) return rc;
-  std::vector<double> hn(2 * m);
-  P->refine_iters = 0;
-  P->last_corr = INFINITY;
-  double prev = INFINITY;
   const size_t bres = (size_t)(RES_ROWS + 2 * L.k) * (RES_MC + 1) * 8;
   if (!set_lds((const void*)residual_kernel, bres)) return LRSPIKE_ERR_NOT_SUPPORTED;
+  const dim3 gu(L.p, (unsigned)((L.nbmax * (int64_t)L.K + REF_ROWS - 1) / REF_ROWS));
   for (int it = 0; it < P->max_refine; ++it) {
     LRS_LAUNCH("residual_kernel", residual_kernel, dim3((unsigned)((L.n + RES_ROWS - 1) / RES_ROWS)), dim3(RES_ROWS),
-               bres, P->bands, L.n, L.k, fcopy, rhs, scr, m, m, transpose);
-    if ((rc = run_apply<T, K>(P, scr, m, transpose))) return rc;
-    LRS_LAUNCH("zero_d_kernel", zero_d_kernel, dim3(1), dim3(256), 0, norms, 2 * m);
-    LRS_LAUNCH("axpy_norms_kernel", axpy_norms_kernel, dim3(1024), dim3(256), (size_t)2 * m * 8, rhs, scr, nm, m,
-               norms);
-    if (hipMemcpyAsync(hn.data(), norms, 2 * m * 8, hipMemcpyDeviceToHost, st) != hipSuccess) return LRSPIKE_ERR_HIP;
-    if (hipStreamSynchronize(st) != hipSuccess) return LRSPIKE_ERR_HIP;
-    double worst = 0.0;
-    for (int c = 0; c < m; ++c) {
-      double rel = sqrt(hn[2 * c + 1]) / (sqrt(hn[2 * c]) > 0 ? sqrt(hn[2 * c]) : 1.0);
-      if (!(rel == rel)) rel = INFINITY;
-      if (rel > worst) worst = rel;
+               bres, P->bands, L.n, L.k, fcopy, rhs, scr, m, m, transpose, gate);
+    if ((rc = run_apply<T, K>(P, scr, m, transpose, gate))) return rc;
+    LRS_LAUNCH("refine_update_kernel", refine_update_kernel, gu, dim3(256), (size_t)2 * m * 8, rhs, scr, L, m,
+               norms, gate);
+    LRS_LAUNCH("refine_ctl_kernel", refine_ctl_kernel, dim3(1), dim3(64), 0, state, norms, L.nsys, m, L.mmax,
+               P->refine_tol, it, P->max_refine);
+    if (capturing) continue;
+    int* slot = P->hstate + 4 * (it & 1);
+    if (hipMemcpyAsync(slot, state + S_STOP, 4, hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipEventRecord(P->hev[it & 1], st) != hipSuccess)
+      return LRSPIKE_ERR_HIP;
+    if (it >= 1) {
+      if (hipEventSynchronize(P->hev[(it - 1) & 1]) != hipSuccess) return LRSPIKE_ERR_HIP;
+      if (P->hstate[4 * ((it - 1) & 1)] != 0) break;  // stopped: this correction was a no-op
     }
-    P->refine_iters = it + 1;
-    P->last_corr = worst;
-    if (worst <= P->refine_tol) return 0;
-    if (!(worst < INFINITY)) break;
-    // linear convergence: the error left after this update is about rho times
-    // the correction, rho the contraction factor (ratio of successive
-    // corrections; for the first one, its own relative size, i.e. the accuracy
-    // of the FP32 solve), with a safety factor of 10
-    const double rho = it == 0 ? worst : worst / prev;
-    if (rho < 1e-2 && 10.0 * rho * worst <= P->refine_tol) return 0;
-    if (it > 0 && worst > 0.5 * prev) {
-      // the corrections stopped shrinking: the rounding level of an
-      // ill-conditioned system when they are already small, else failure
-      if (worst <= 100.0 * P->refine_tol) return 0;
-      break;
-    }
-    prev = worst;
-  }
-  int* latch = reinterpret_cast<int*>(P->ws + L.latch);
-  int code = LRSPIKE_ERR_NOT_CONVERGED;
-  // latch from the host only if nothing is latched yet
-  int cur = 0;
-  if (hipMemcpy(&cur, latch, 4, hipMemcpyDeviceToHost) == hipSuccess && cur == 0) {
-    int rec[2] = {code, -1};
-    if (hipMemcpy(latch, rec, 8, hipMemcpyHostToDevice) != hipSuccess) return LRSPIKE_ERR_HIP;
   }
   return 0;
 }
 
 typedef int (*factor_fn)(lrspike_plan);
 typedef int (*apply_fn)(lrspike_plan, double*, int, int);
+
+// one ungated application of M_r^{-1} (or M_r^{-T})
+template <typename T, int K>
+int run_plain(lrspike_plan P, double* rhs, int m, int transpose) {
+  return run_apply<T, K>(P, rhs, m, transpose, nullptr);
+}
 
 template <typename T>
 factor_fn pick_factor(int K) {
@@ -380,15 +469,48 @@ factor_fn pick_factor(int K) {
 template <typename T, bool REF>
 apply_fn pick_apply(int K) {
   switch (K) {
-    case 1: return REF ? run_refined<T, 1> : run_apply<T, 1>;
-    case 2: return REF ? run_refined<T, 2> : run_apply<T, 2>;
-    case 4: return REF ? run_refined<T, 4> : run_apply<T, 4>;
-    case 8: return REF ? run_refined<T, 8> : run_apply<T, 8>;
-    case 16: return REF ? run_refined<T, 16> : run_apply<T, 16>;
-    case 32: return REF ? run_refined<T, 32> : run_apply<T, 32>;
-    case 64: return REF ? run_refined<T, 64> : run_apply<T, 64>;
+    case 1: return REF ? run_refined<T, 1> : run_plain<T, 1>;
+    case 2: return REF ? run_refined<T, 2> : run_plain<T, 2>;
+    case 4: return REF ? run_refined<T, 4> : run_plain<T, 4>;
+    case 8: return REF ? run_refined<T, 8> : run_plain<T, 8>;
+    case 16: return REF ? run_refined<T, 16> : run_plain<T, 16>;
+    case 32: return REF ? run_refined<T, 32> : run_plain<T, 32>;
+    case 64: return REF ? run_refined<T, 64> : run_plain<T, 64>;
   }
   return nullptr;
+}
+
+bool prec_valid(int prec) {
+  return prec == LRSPIKE_FP64 || prec == LRSPIKE_FP32_REFINED || prec == LRSPIKE_FP64_REFINED;
+}
+int prec_tsize(int prec) { return prec == LRSPIKE_FP32_REFINED ? 4 : 8; }
+int prec_refined(int prec) { return prec != LRSPIKE_FP64; }
+factor_fn factor_for(int prec, int K) { return prec_tsize(prec) == 8 ? pick_factor<double>(K) : pick_factor<float>(K); }
+apply_fn apply_for(int prec, int K) {
+  if (prec == LRSPIKE_FP64) return pick_apply<double, false>(K);
+  if (prec == LRSPIKE_FP64_REFINED) return pick_apply<double, true>(K);
+  return pick_apply<float, true>(K);
+}
+
+// Pinned host slots and events of the eager refinement loop (refined plans).
+int alloc_refine_host(lrspike_plan P) {
+  if (hipHostMalloc((void**)&P->hstate, 8 * sizeof(int), hipHostMallocDefault) != hipSuccess) {
+    P->hstate = nullptr;
+    return LRSPIKE_ERR_HIP;
+  }
+  for (int i = 0; i < 2; ++i)
+    if (hipEventCreateWithFlags(&P->hev[i], hipEventDisableTiming) != hipSuccess) {
+      P->hev[i] = nullptr;
+      return LRSPIKE_ERR_HIP;
+    }
+  return 0;
+}
+void free_refine_host(lrspike_plan P) {
+  if (P->hstate) (void)hipHostFree(P->hstate);
+  for (int i = 0; i < 2; ++i)
+    if (P->hev[i]) (void)hipEventDestroy(P->hev[i]);
+  P->hstate = nullptr;
+  P->hev[0] = P->hev[1] = nullptr;
 }
 
 void prof_clear(lrspike_plan P) {
@@ -430,11 +552,11 @@ int lrspike_workspace_size(int64_t n, int32_t k, int32_t p, int32_t r, int32_t p
   if (k < 1) return -2;
   if (p < 1 || p > n) return -3;
   if (r < 0 || r > k) return -4;
-  if (precision != LRSPIKE_FP64 && precision != LRSPIKE_FP32_REFINED) return -5;
+  if (!prec_valid(precision)) return -5;
   if (max_nrhs < 1) return -6;
   if (!bytes) return -7;
   Layout L;
-  make_layout(L, n, k, p, r, precision == LRSPIKE_FP64 ? 8 : 4, max_nrhs);
+  make_layout(L, n, k, p, r, prec_tsize(precision), max_nrhs, prec_refined(precision));
   *bytes = L.total;
   return 0;
 }
@@ -452,31 +574,34 @@ int lrspike_factor(int64_t n, int32_t k, const double* bands, int32_t p, int32_t
   int64_t njmin = n / p;
   if (p > 1 && njmin < 2 * (int64_t)k) return -4;
   if (njmin < K) return -4;
-  if (opts->precision != LRSPIKE_FP64 && opts->precision != LRSPIKE_FP32_REFINED) return -6;
+  if (!prec_valid(opts->precision)) return -6;
+  if (opts->variant != LRSPIKE_VARIANT_FULL && opts->variant != LRSPIKE_VARIANT_T) return -6;
   if (opts->max_nrhs < 1) return -6;
   if (K > 64) return LRSPIKE_ERR_NOT_SUPPORTED;
   // reduced-system blocks of order 2r are inverted in one workgroup's LDS
   if (p > 1 && 2 * ((r == k) ? K : r) > 64) return LRSPIKE_ERR_NOT_SUPPORTED;
   lrspike_plan P = new lrspike_plan_s();
-  make_layout(P->L, n, k, p, r, opts->precision == LRSPIKE_FP64 ? 8 : 4, opts->max_nrhs);
+  make_layout(P->L, n, k, p, r, prec_tsize(opts->precision), opts->max_nrhs, prec_refined(opts->precision),
+              opts->variant);
   if (!opts->workspace || opts->workspace_bytes < P->L.total || !is_device_ptr(opts->workspace)) {
     delete P;
     return LRSPIKE_ERR_WORKSPACE;
   }
   P->precision = opts->precision;
+  P->variant = opts->variant;
   P->max_refine = opts->max_refine > 0 ? opts->max_refine : 30;
   P->refine_tol = opts->refine_tol > 0 ? opts->refine_tol : 1e-13;
   P->stream = reinterpret_cast<hipStream_t>(opts->stream);
   P->bands = bands;
   P->ws = reinterpret_cast<char*>(opts->workspace);
-  P->refine_iters = 0;
-  P->last_corr = 0.0;
   P->profiling = opts->profile ? 1 : 0;
-  LRS_LAUNCH("zero_kernel", zero_kernel, dim3(1), dim3(64), 0, reinterpret_cast<int*>(P->ws + P->L.latch), 16);
-  factor_fn f = P->precision == LRSPIKE_FP64 ? pick_factor<double>(K) : pick_factor<float>(K);
-  int rc = f ? f(P) : LRSPIKE_ERR_NOT_SUPPORTED;
+  int rc = prec_refined(P->precision) ? alloc_refine_host(P) : 0;
+  if (!rc) rc = launch(P, "state_init_kernel", state_init_kernel, dim3(1), dim3(64), 0,
+                       reinterpret_cast<int*>(P->ws + P->L.latch));
+  factor_fn f = factor_for(P->precision, K);
+  if (!rc) rc = f ? f(P) : LRSPIKE_ERR_NOT_SUPPORTED;
   if (rc) {
-    delete P;
+    lrspike_destroy(P);
     return rc;
   }
   *plan_out = P;
@@ -487,11 +612,7 @@ static int solve_common(lrspike_plan P, double* rhs, int32_t nrhs, int transpose
   if (!P || P->batch) return -1;
   if (!is_device_ptr(rhs)) return -2;
   if (nrhs < 1 || nrhs > P->L.mmax) return -3;
-  apply_fn f;
-  if (P->precision == LRSPIKE_FP64)
-    f = pick_apply<double, false>(P->L.K);
-  else
-    f = pick_apply<float, true>(P->L.K);
+  apply_fn f = apply_for(P->precision, P->L.K);
   if (!f) return LRSPIKE_ERR_NOT_SUPPORTED;
   return f(P, rhs, nrhs, transpose);
 }
@@ -518,11 +639,14 @@ int lrspike_band_grad(lrspike_plan P, const double* lam, const double* x, int32_
 int lrspike_status(lrspike_plan P, lrspike_info* info) {
   if (!P) return -1;
   if (P->batch) {
-    // first latched error over the groups; partition reports the system index
+    // first latched error over the groups (partition = that system's index);
+    // counters summed, diagnostics combined (min of minima, max of maxima)
     lrspike_info gi, out;
     memset(&out, 0, sizeof(out));
     out.partition = -1;
     out.row = -1;
+    out.min_pivot = INFINITY;
+    out.min_sigma_gap = INFINITY;
     int first = 0;
     for (BatchGroup& G : P->batch->groups) {
       int rc = lrspike_status(G.plan, &gi);
@@ -530,6 +654,10 @@ int lrspike_status(lrspike_plan P, lrspike_info* info) {
       out.swapped_blocks += gi.swapped_blocks;
       out.refine_iters = std::max(out.refine_iters, gi.refine_iters);
       out.last_correction = std::max(out.last_correction, gi.last_correction);
+      out.min_pivot = std::min(out.min_pivot, gi.min_pivot);
+      out.max_abs_entry = std::max(out.max_abs_entry, gi.max_abs_entry);
+      out.min_sigma_gap = std::min(out.min_sigma_gap, gi.min_sigma_gap);
+      out.reduced_growth = std::max(out.reduced_growth, gi.reduced_growth);
       if (rc && !first) {
         first = rc;
         out.error = rc;
@@ -541,20 +669,29 @@ int lrspike_status(lrspike_plan P, lrspike_info* info) {
     return first;
   }
   if (hipStreamSynchronize(P->stream) != hipSuccess) return LRSPIKE_ERR_HIP;
-  int latch[16];
-  if (hipMemcpy(latch, P->ws + P->L.latch, sizeof(latch), hipMemcpyDeviceToHost) != hipSuccess)
-    return LRSPIKE_ERR_HIP;
+  int st[STATE_INTS];
+  if (hipMemcpy(st, P->ws + P->L.latch, sizeof(st), hipMemcpyDeviceToHost) != hipSuccess) return LRSPIKE_ERR_HIP;
+  auto dbl = [&](int slot) {
+    double v;
+    memcpy(&v, st + slot, 8);
+    return v;
+  };
   if (info) {
-    info->error = latch[0];
-    info->partition = latch[0] ? latch[1] : -1;
+    info->error = st[S_CODE];
+    info->partition = st[S_CODE] ? st[S_PART] : -1;
     int64_t row;
-    memcpy(&row, latch + 2, 8);
-    info->row = latch[0] ? row : -1;
-    info->refine_iters = P->refine_iters;
-    info->swapped_blocks = latch[8];
-    info->last_correction = P->last_corr;
+    memcpy(&row, st + S_ROW, 8);
+    info->row = st[S_CODE] ? row : -1;
+    info->refine_iters = st[S_ITERS];
+    info->swapped_blocks = st[S_SWAPPED];
+    info->last_correction = dbl(S_CORR);
+    info->min_pivot = dbl(S_PIVMIN);
+    info->max_abs_entry = dbl(S_AMAX);
+    info->min_sigma_gap = dbl(S_GAPMIN);
+    const double zmax = dbl(S_ZMAX), zgrow = dbl(S_ZGROW);
+    info->reduced_growth = zmax > 0.0 ? zgrow / zmax : 0.0;
   }
-  return latch[0];
+  return st[S_CODE];
 }
 
 int lrspike_profile(lrspike_plan P, int32_t enable) {
@@ -601,6 +738,7 @@ int lrspike_profile_read(lrspike_plan P, int32_t max, char* names, double* total
 int lrspike_destroy(lrspike_plan P) {
   if (P) {
     prof_clear(P);
+    free_refine_host(P);
     if (P->batch) {
       for (BatchGroup& G : P->batch->groups) free_group(G);
       if (P->batch->graph) (void)hipGraphExecDestroy(P->batch->graph);
@@ -619,7 +757,7 @@ int lrspike_factor_batched(int32_t count, const lrspike_batch_desc* descs, const
   if (!is_device_ptr(bands_base)) return -3;
   if (!opts) return -4;
   if (!plan_out) return -5;
-  if (opts->precision != LRSPIKE_FP64 && opts->precision != LRSPIKE_FP32_REFINED) return -4;
+  if (!prec_valid(opts->precision)) return -4;
   for (int s = 0; s < count; ++s) {
     const lrspike_batch_desc& d = descs[s];
     if (d.n < 1 || d.k < 1 || d.r < 0 || d.r > d.k || d.nrhs < 1 || d.p < 0 || d.p > d.n || d.band_offset < 0 ||
@@ -673,7 +811,6 @@ int lrspike_run_batched(lrspike_plan P, double* rhs_base) {
   if (!P || !P->batch) return -1;
   if (!is_device_ptr(rhs_base)) return -2;
   BatchState& B = *P->batch;
-  if (B.precision != LRSPIKE_FP64) return LRSPIKE_ERR_NOT_SUPPORTED;
   hipStream_t st = P->stream;
   if (B.graph && B.graph_rhs == rhs_base) return hipGraphLaunch(B.graph, st) == hipSuccess ? 0 : LRSPIKE_ERR_HIP;
   if (B.graph) {

@@ -35,6 +35,7 @@ struct BatchGroup {
   double* band = nullptr;    // (2k+1) x N concatenated band
   double* rhs = nullptr;     // N x mb concatenated right-hand sides
   int64_t* offs_dev = nullptr;
+  int* psys_dev = nullptr;   // partition -> system slot within the group (refinement norms per system)
   char* ws = nullptr;
   BatchSys* sys_dev = nullptr;
   BatchChunk* chunks_dev = nullptr;
@@ -89,11 +90,14 @@ __global__ void pack_rhs_kernel(const BatchSys* __restrict__ sys, const BatchChu
 static void free_group(BatchGroup& G) {
   if (G.plan) {
     prof_clear(G.plan);
+    free_refine_host(G.plan);
     delete G.plan;
   }
   (void)hipFree(G.band);
   (void)hipFree(G.rhs);
   (void)hipFree(G.offs_dev);
+  (void)hipFree(G.psys_dev);
+  G.psys_dev = nullptr;
   (void)hipFree(G.ws);
   (void)hipFree(G.sys_dev);
   (void)hipFree(G.chunks_dev);
@@ -124,6 +128,7 @@ static int build_group(BatchState& B, BatchGroup& G, int64_t target, int wave, c
   G.part_sys.clear();
   std::vector<BatchSys> st;
   std::vector<BatchChunk> ch;
+  std::vector<int> pslot;
   int64_t row0 = 0;
   for (size_t q = 0; q < G.sys.size(); ++q) {
     const lrspike_batch_desc& d = B.descs[G.sys[q]];
@@ -132,6 +137,7 @@ static int build_group(BatchState& B, BatchGroup& G, int64_t target, int wave, c
     for (int j = 0; j < p; ++j) {
       G.offs.push_back(G.offs.back() + base + (j < extra ? 1 : 0));
       G.part_sys.push_back(G.sys[q]);
+      pslot.push_back((int)q);
     }
     st.push_back({d.n, d.band_offset, d.rhs_offset, row0, d.nrhs, 0});
     for (int64_t r = 0; r < d.n; r += 256) ch.push_back({(int32_t)q, 0, r});
@@ -141,27 +147,29 @@ static int build_group(BatchState& B, BatchGroup& G, int64_t target, int wave, c
   G.nchunks = (int)ch.size();
   const int P = (int)G.part_sys.size();
   if (hipMalloc(&G.offs_dev, (P + 1) * sizeof(int64_t)) != hipSuccess ||
+      hipMalloc(&G.psys_dev, P * sizeof(int)) != hipSuccess ||
       hipMalloc(&G.sys_dev, st.size() * sizeof(BatchSys)) != hipSuccess ||
       hipMalloc(&G.chunks_dev, ch.size() * sizeof(BatchChunk)) != hipSuccess ||
       hipMalloc(&G.band, (size_t)(2 * G.k + 1) * G.N * 8) != hipSuccess ||
       hipMalloc(&G.rhs, (size_t)G.N * G.mb * 8) != hipSuccess)
     return LRSPIKE_ERR_HIP;
   if (hipMemcpy(G.offs_dev, G.offs.data(), (P + 1) * sizeof(int64_t), hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(G.psys_dev, pslot.data(), P * sizeof(int), hipMemcpyHostToDevice) != hipSuccess ||
       hipMemcpy(G.sys_dev, st.data(), st.size() * sizeof(BatchSys), hipMemcpyHostToDevice) != hipSuccess ||
       hipMemcpy(G.chunks_dev, ch.data(), ch.size() * sizeof(BatchChunk), hipMemcpyHostToDevice) != hipSuccess)
     return LRSPIKE_ERR_HIP;
   lrspike_plan Q = new lrspike_plan_s();
   G.plan = Q;
-  make_layout(Q->L, G.N, G.k, P, G.r, B.precision == LRSPIKE_FP64 ? 8 : 4, G.mb, G.offs.data(), G.offs_dev);
+  make_layout(Q->L, G.N, G.k, P, G.r, prec_tsize(B.precision), G.mb, prec_refined(B.precision), 0, G.offs.data(),
+              G.offs_dev, (int)G.sys.size(), G.psys_dev);
   if (hipMalloc(&G.ws, Q->L.total) != hipSuccess) return LRSPIKE_ERR_HIP;
+  if (prec_refined(B.precision) && alloc_refine_host(Q)) return LRSPIKE_ERR_HIP;
   Q->precision = B.precision;
   Q->max_refine = opts->max_refine > 0 ? opts->max_refine : 30;
   Q->refine_tol = opts->refine_tol > 0 ? opts->refine_tol : 1e-13;
   Q->stream = reinterpret_cast<hipStream_t>(opts->stream);
   Q->bands = G.band;
   Q->ws = G.ws;
-  Q->refine_iters = 0;
-  Q->last_corr = 0.0;
   Q->profiling = 0;
   Q->wave = wave;
   return 0;
@@ -171,8 +179,8 @@ static int factor_group(BatchState& B, BatchGroup& G) {
   lrspike_plan P = G.plan;
   LRS_LAUNCH("pack_band_kernel", pack_band_kernel, dim3(G.nchunks), dim3(256), 0, G.sys_dev, G.chunks_dev,
              B.bands_base, G.band, G.N, G.k);
-  LRS_LAUNCH("zero_kernel", zero_kernel, dim3(1), dim3(64), 0, reinterpret_cast<int*>(P->ws + P->L.latch), 16);
-  factor_fn f = B.precision == LRSPIKE_FP64 ? pick_factor<double>(P->L.K) : pick_factor<float>(P->L.K);
+  LRS_LAUNCH("state_init_kernel", state_init_kernel, dim3(1), dim3(64), 0, reinterpret_cast<int*>(P->ws + P->L.latch));
+  factor_fn f = factor_for(B.precision, P->L.K);
   return f ? f(P) : LRSPIKE_ERR_NOT_SUPPORTED;
 }
 
@@ -180,7 +188,7 @@ static int solve_group(BatchState& B, BatchGroup& G, double* rhs_base) {
   lrspike_plan P = G.plan;
   LRS_LAUNCH("pack_rhs_kernel", pack_rhs_kernel, dim3(G.nchunks), dim3(256), 0, G.sys_dev, G.chunks_dev, rhs_base,
              G.rhs, G.mb, 0);
-  apply_fn f = B.precision == LRSPIKE_FP64 ? pick_apply<double, false>(P->L.K) : pick_apply<float, true>(P->L.K);
+  apply_fn f = apply_for(B.precision, P->L.K);
   if (!f) return LRSPIKE_ERR_NOT_SUPPORTED;
   int rc = f(P, G.rhs, G.mb, 0);
   if (rc) return rc;
@@ -217,7 +225,7 @@ static int autotune(BatchState& B, const lrspike_opts* opts) {
         for (int rep = 0; rep < 2 && !rc; ++rep) {  // the first repetition warms up
           if (hipEventRecord(e0, st) != hipSuccess) { rc = LRSPIKE_ERR_HIP; break; }
           if ((rc = factor_group(B, G))) break;
-          apply_fn f = B.precision == LRSPIKE_FP64 ? pick_apply<double, false>(K) : pick_apply<float, true>(K);
+          apply_fn f = apply_for(B.precision, K);
           if (!f) { rc = LRSPIKE_ERR_NOT_SUPPORTED; break; }
           if ((rc = f(G.plan, G.rhs, G.mb, 0))) break;
           if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||

@@ -12,6 +12,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <limits>
+
 #include "layout.h"
 
 #define LRS_NT 256  // threads per workgroup (4 wave64)
@@ -110,6 +112,28 @@ __device__ inline void latch_error(int* latch, int code, int part, int64_t row) 
     latch[1] = part;
     reinterpret_cast<int64_t*>(latch + 2)[0] = row;
   }
+}
+
+// Running min / max of non-negative doubles in the state block: the IEEE bit
+// patterns of non-negative doubles are ordered like their values, so 64-bit
+// integer atomics on the patterns keep the extreme (+inf is the min's start).
+__device__ inline void state_min(int* st, int slot, double v) {
+  atomicMin(reinterpret_cast<unsigned long long*>(st + slot), (unsigned long long)__double_as_longlong(v));
+}
+__device__ inline void state_max(int* st, int slot, double v) {
+  atomicMax(reinterpret_cast<unsigned long long*>(st + slot), (unsigned long long)__double_as_longlong(v));
+}
+
+// Wave-wide min / max (all 64 lanes; every lane gets the result).
+template <typename T>
+__device__ inline T wave_min(T v) {
+  for (int off = 32; off >= 1; off >>= 1) v = fmin(v, __shfl_xor(v, off));
+  return v;
+}
+template <typename T>
+__device__ inline T wave_max(T v) {
+  for (int off = 32; off >= 1; off >>= 1) v = fmax(v, __shfl_xor(v, off));
+  return v;
 }
 
 // ------------------------------------------------------------------------
@@ -220,74 +244,6 @@ __device__ inline void gemm(int M, int N, int KD, T alpha, const T* A, int lda,
     gemm_valu<T, TA>(M, N, KD, alpha, A, lda, B, ldb, beta, C, ldc);
 }
 
-// ------------------------------------------------------------------------
-// Partial-pivoting LU of an nr x K panel held in LDS (row pitch ld), nr in
-// {K, 2K}, nr <= 64: the pivot of column c is the first row of largest
-// magnitude among rows c .. nr-1 (first-max tie-break).  Interchanges move
-// whole rows: the first ncols columns of P (the panel and the block columns
-// to its right) and the first ncx columns of X (right-hand sides riding
-// along), so on exit the panel holds L (unit, strictly below the diagonal, in
-// final row order) and U.  ipiv[c] = row swapped with c.
-// Returns (uniformly) whether any interchange happened.  A zero pivot is
-// latched with the partition-local row `row0 + c` and the factorization
-// continues (the result is then non-finite).
-// ------------------------------------------------------------------------
-template <typename T, int K>
-__device__ inline bool panel_lu(T* P, int ld, int nr, int ncols, T* X, int ldx, int ncx,
-                                int* ipiv, int* latch, int part, int64_t row0, int* s_flag) {
-  const int tid = threadIdx.x;
-  if (tid == 0) *s_flag = 0;
-  __syncthreads();
-  for (int c = 0; c < K; ++c) {
-    if (tid < 64) {
-      // wave 0: argmax over candidate rows (value, index), first max wins ties
-      T v = (tid >= c && tid < nr) ? fabs(P[tid * ld + c]) : T(-1);
-      int idx = tid;
-      for (int off = 32; off >= 1; off >>= 1) {
-        T ov = __shfl_xor(v, off);
-        int oi = __shfl_xor(idx, off);
-        if (ov > v || (ov == v && oi < idx)) {
-          v = ov;
-          idx = oi;
-        }
-      }
-      if (tid == 0) {
-        ipiv[c] = idx;
-        if (idx != c) *s_flag = 1;
-      }
-    }
-    __syncthreads();
-    const int piv = ipiv[c];
-    if (piv != c) {
-      for (int col = tid; col < ncols; col += blockDim.x) {
-        T t = P[c * ld + col];
-        P[c * ld + col] = P[piv * ld + col];
-        P[piv * ld + col] = t;
-      }
-      for (int col = tid; col < ncx; col += blockDim.x) {
-        T t = X[c * ldx + col];
-        X[c * ldx + col] = X[piv * ldx + col];
-        X[piv * ldx + col] = t;
-      }
-      __syncthreads();
-    }
-    const T d = P[c * ld + c];
-    if (d == T(0)) {
-      if (tid == 0) latch_error(latch, 1, part, row0 + c);
-    }
-    // multipliers
-    for (int r = c + 1 + tid; r < nr; r += blockDim.x) P[r * ld + c] = P[r * ld + c] / d;
-    __syncthreads();
-    const int w = K - c - 1;
-    for (int o = tid; o < (nr - c - 1) * w; o += blockDim.x) {
-      int r = c + 1 + o / w, col = c + 1 + o % w;
-      P[r * ld + col] -= P[r * ld + c] * P[c * ld + col];
-    }
-    __syncthreads();
-  }
-  return *s_flag != 0;
-}
-
 // Broadcast lane `l`'s value of v to the whole wave (uniform result).
 __device__ __forceinline__ double bcast(double v, int l) {
   int lo = __builtin_amdgcn_readlane(__double2loint(v), l);
@@ -304,7 +260,7 @@ template <typename T, int K, int C>
 struct PanelCol {
   static __device__ __forceinline__ void run(T (&a)[K], int lane, bool act, T* P, int ld, int ncols,
                                              T* X, int ldx, int ncx, int* ipiv, int* latch, int part,
-                                             int64_t row0, bool& any_swap) {
+                                             int64_t row0, bool& any_swap, T& pmin) {
     if constexpr (C < K) {
       T d = bcast(a[C], C);
       const bool beats = act && lane > C && fabs(a[C]) > fabs(d);
@@ -344,7 +300,15 @@ struct PanelCol {
         }
         d = bcast(a[C], C);
       }
-      if (d == T(0) && lane == 0) latch_error(latch, 1, part, row0 + C);
+      // an exactly zero pivot, or a non-finite one (Inf/NaN in the band reach
+      // some pivot of the elimination), is latched with its row
+      if (lane == 0) {
+        if (d == T(0))
+          latch_error(latch, 1, part, row0 + C);
+        else if (!isfinite(d))
+          latch_error(latch, 4, part, row0 + C);
+      }
+      if (row0 + C >= 0) pmin = fmin(pmin, fabs(d));  // not the unit pivots of virtual rows
       const bool below = act && lane > C;
       const T inv = T(1) / d;
       const T l = a[C] * inv;
@@ -354,7 +318,7 @@ struct PanelCol {
         const T pj = bcast(a[jj], C);
         if (below) a[jj] -= l * pj;
       }
-      PanelCol<T, K, C + 1>::run(a, lane, act, P, ld, ncols, X, ldx, ncx, ipiv, latch, part, row0, any_swap);
+      PanelCol<T, K, C + 1>::run(a, lane, act, P, ld, ncols, X, ldx, ncx, ipiv, latch, part, row0, any_swap, pmin);
     }
   }
 };
@@ -371,25 +335,29 @@ struct PanelCol {
 // records the largest multiplier magnitude of the lane in mx.
 template <typename T, int K, int C>
 struct PanelColNoPiv {
-  static __device__ __forceinline__ void run(T (&a)[K], int lane, bool act, T& mx, T& dmin) {
+  static __device__ __forceinline__ void run(T (&a)[K], int lane, bool act, T& mx, T& dmin, int64_t row0) {
     if constexpr (C < K) {
       const T d = bcast(a[C], C);
       const T inv = T(1) / d;
       const bool below = act && lane > C;
       const T l = below ? a[C] * inv : T(0);
-      mx = fmax(mx, fabs(l));
-      dmin = fmin(dmin, fabs(d));
+      // sticky on NaN (an Inf pivot counts as NaN): a non-finite panel fails
+      // the no-interchange test and goes to the pivoting pass, which latches it
+      const T al = fabs(l), ad = fabs(d), adc = ad <= std::numeric_limits<T>::max() ? ad : T(NAN);
+      mx = (mx != mx || mx >= al) ? mx : al;
+      if (row0 + C >= 0) dmin = (dmin != dmin || dmin <= adc) ? dmin : adc;
       if (below) a[C] = l;
 #pragma unroll
       for (int jj = C + 1; jj < K; ++jj) a[jj] -= l * bcast(a[jj], C);
-      PanelColNoPiv<T, K, C + 1>::run(a, lane, act, mx, dmin);
+      PanelColNoPiv<T, K, C + 1>::run(a, lane, act, mx, dmin, row0);
     }
   }
 };
 
 template <typename T, int K>
+// pmin: running min |pivot| (updated, uniform over the wave).
 __device__ inline bool panel_lu_wave(T* P, int ld, int nr, int ncols, T* X, int ldx, int ncx,
-                                     int* ipiv, int* latch, int part, int64_t row0) {
+                                     int* ipiv, int* latch, int part, int64_t row0, T& pmin) {
   const int lane = threadIdx.x & 63;
   const bool act = lane < nr;
   T a[K];
@@ -399,11 +367,12 @@ __device__ inline bool panel_lu_wave(T* P, int ld, int nr, int ncols, T* X, int 
   // interchanges at column c exactly when some row below has |a_rc| > |a_cc|,
   // i.e. when a multiplier exceeds 1 in magnitude; if none does, this IS the
   // partial-pivoting factorization (same operations, same order).
-  T mx = T(0), dmin = T(1);
-  PanelColNoPiv<T, K, 0>::run(a, lane, act, mx, dmin);
+  T mx = T(0), dmin = T(INFINITY);
+  PanelColNoPiv<T, K, 0>::run(a, lane, act, mx, dmin, row0);
   const bool ok = !__any(!(mx <= T(1))) && __all(dmin > T(0));
   if (ok) {
     if (lane < K) ipiv[lane] = lane;
+    pmin = fmin(pmin, dmin);
 #pragma unroll
     for (int c = 0; c < K; ++c)
       if (act) P[lane * ld + c] = a[c];
@@ -412,7 +381,7 @@ __device__ inline bool panel_lu_wave(T* P, int ld, int nr, int ncols, T* X, int 
 #pragma unroll
   for (int c = 0; c < K; ++c) a[c] = act ? P[lane * ld + c] : T(0);
   bool any_swap = false;
-  PanelCol<T, K, 0>::run(a, lane, act, P, ld, ncols, X, ldx, ncx, ipiv, latch, part, row0, any_swap);
+  PanelCol<T, K, 0>::run(a, lane, act, P, ld, ncols, X, ldx, ncx, ipiv, latch, part, row0, any_swap, pmin);
 #pragma unroll
   for (int c = 0; c < K; ++c)
     if (act) P[lane * ld + c] = a[c];

@@ -114,6 +114,7 @@ __global__ __launch_bounds__(LRS_NT) void factor_pass1(FactorArgs a) {
   // into the window after the shift.
   constexpr int NPRE = ((2 * K + 1) * K + LRS_NT - 1) / LRS_NT;
   T pre[NPRE];
+  T amax_run = T(0), pmin_run = T(INFINITY);  // diagnostics: largest band entry read, smallest pivot (wave 0)
   auto prefetch_rowblock = [&](int R) {
 #pragma unroll
     for (int t = 0; t < NPRE; ++t) {
@@ -130,6 +131,7 @@ __global__ __launch_bounds__(LRS_NT) void factor_pass1(FactorArgs a) {
         }
       }
       pre[t] = v;
+      amax_run = fmax(amax_run, fabs(v));
     }
   };
   // write the prefetched row block R into window rows K..2K-1 (zeroed first)
@@ -155,8 +157,11 @@ __global__ __launch_bounds__(LRS_NT) void factor_pass1(FactorArgs a) {
         if (d == 0) Wn[(wrow0 + i) * LDW + wc] = T(1);
       } else if (lr < g.nj) {
         const int lc = lr + d;
-        if (lc >= 0 && lc < g.nj && wc >= 0 && wc < wcols)
-          Wn[(wrow0 + i) * LDW + wc] = (T)a.bands[(int64_t)(d + k) * L.n + g.s + lr];
+        if (lc >= 0 && lc < g.nj && wc >= 0 && wc < wcols) {
+          const T v = (T)a.bands[(int64_t)(d + k) * L.n + g.s + lr];
+          Wn[(wrow0 + i) * LDW + wc] = v;
+          amax_run = fmax(amax_run, fabs(v));
+        }
       }
     }
   };
@@ -211,7 +216,7 @@ __global__ __launch_bounds__(LRS_NT) void factor_pass1(FactorArgs a) {
     const int ncs = (b >= nb - 2) ? 2 * K : K;
     if (b + 2 < nb) prefetch_rowblock(b + 2);
     if (tid < 64) {
-      bool sw = panel_lu_wave<T, K>(Wn, LDW, nr, last ? K : 3 * K, Wv, LD2, 2 * K, s_ipiv, latch, j, row0);
+      bool sw = panel_lu_wave<T, K>(Wn, LDW, nr, last ? K : 3 * K, Wv, LD2, 2 * K, s_ipiv, latch, j, row0, pmin_run);
       if (tid == 0) s_flag = sw ? 1 : 0;
     }
     __syncthreads();
@@ -375,7 +380,10 @@ __global__ __launch_bounds__(LRS_NT) void factor_pass1(FactorArgs a) {
       if (o < 2 * K * K) put_top(o / (2 * K), o % (2 * K), tacc[t]);
     }
   }
-  if (tid == 0 && nswapped) atomicAdd(latch + 8, nswapped);
+  if (tid == 0 && nswapped) atomicAdd(latch + S_SWAPPED, nswapped);
+  const T am = wave_max(amax_run);
+  if (lane == 0) state_max(latch, S_AMAX, (double)am);
+  if (tid == 0) state_min(latch, S_PIVMIN, (double)pmin_run);
 }
 
 // ------------------------------------------------------------------------

@@ -84,6 +84,7 @@ __global__ __launch_bounds__(LRS_NT) void factor_lds_kernel(FactorArgs a) {
   int* ipv = wsT<int>(a.ws, L.ipiv) + (size_t)j * L.nbmax * K;
   int* flg = wsT<int>(a.ws, L.flag) + (size_t)j * L.nbmax;
   int* latch = wsT<int>(a.ws, L.latch);
+  T amax_run = T(0), pmin_run = T(INFINITY);  // diagnostics: largest band entry, smallest pivot
   // A_j(lr, lc) in partition-local rows/columns (identity on the padding rows)
   auto Aj = [&](int lr, int lc) -> T {
     if (lr < 0 || lc < 0) return (lr == lc) ? T(1) : T(0);
@@ -118,6 +119,7 @@ __global__ __launch_bounds__(LRS_NT) void factor_lds_kernel(FactorArgs a) {
                        d >= -k && d <= k;
       const bool ident = (lr < 0 || lc < 0) && lr == lc;
       if (e <= K - 1 && c >= 0 && c < K) dst[i * PT + c] = inb ? vals[t] : (ident ? T(1) : T(0));
+      if (inb) amax_run = fmax(amax_run, fabs(vals[t]));
     }
   };
   load_block(P, 0, 0);
@@ -156,18 +158,21 @@ __global__ __launch_bounds__(LRS_NT) void factor_lds_kernel(FactorArgs a) {
           pa[c] = P[(r0 + lr) * PT + r0 + c];
           iv[c] = T(0);
         }
-        T mx = T(0), dmin = T(1e30), dinv = T(0);
+        T mx = T(0), dmin = T(INFINITY), dinv = T(0);
         int ln1 = lane;  // opaque lane index (see factor_pass1_wave_kernel)
         asm volatile("" : "+v"(ln1));
         // the L1^{-1} ride-along and the U1^{-1} pass cover the 16 x 16
         // diagonal blocks; their off-diagonal blocks come from block products
-        FwdElim<T, H, 0, 16>::run(pa, iv, ln1, nrow, mx, dmin, dinv);
-        const unsigned long long zb = __ballot(lane < H && !isfinite(dinv));
+        FwdElim<T, H, 0, 16>::run(pa, iv, ln1, nrow, mx, dmin, dinv, b == 0 ? g.pad - r0 : 0);
+        // dmin is NaN after a non-finite pivot (Inf/NaN in the band), 0 after
+        // an exactly zero one; a multiplier above 1 would need an interchange
+        const unsigned long long zb = __ballot(lane < H && !(isfinite(dinv) && dinv != T(0)));
         const unsigned long long bb = __ballot(lane < nrow && !(mx <= T(1)));
         if (lane == 0 && s_bad == 0 && (zb || bb || !(dmin > T(0)))) {
-          s_bad = (zb || !(dmin > T(0))) ? 1 : 2;
+          s_bad = (dmin != dmin) ? 3 : ((zb || !(dmin > T(0))) ? 1 : 2);
           s_row = b * K + r0 + (zb ? __ffsll(zb) - 1 : (bb ? __ffsll(bb) - 1 : 0)) - g.pad;
         }
+        pmin_run = fmin(pmin_run, dmin);
         if (lane < H) {
 #pragma unroll
           for (int c = 0; c < H; ++c)
@@ -267,7 +272,10 @@ __global__ __launch_bounds__(LRS_NT) void factor_lds_kernel(FactorArgs a) {
       __syncthreads();
     }
     if (s_bad) {
-      if (tid == 0) latch_error(latch, s_bad == 1 ? LRSPIKE_ERR_ZERO_PIVOT : LRSPIKE_ERR_NOT_SUPPORTED, j, s_row);
+      if (tid == 0)
+        latch_error(latch,
+                    s_bad == 1 ? LRSPIKE_ERR_ZERO_PIVOT : (s_bad == 3 ? LRSPIKE_ERR_NONFINITE : LRSPIKE_ERR_NOT_SUPPORTED),
+                    j, s_row);
       return;
     }
     auto Li = [&](int r, int l) -> T {
@@ -347,6 +355,9 @@ __global__ __launch_bounds__(LRS_NT) void factor_lds_kernel(FactorArgs a) {
       __syncthreads();
     }
   }
+  const T am = wave_max(amax_run);
+  if ((tid & 63) == 0) state_max(latch, S_AMAX, (double)am);
+  if (tid == 0) state_min(latch, S_PIVMIN, (double)pmin_run);  // the register passes run on wave 0
 }
 
 // Spikes from the records, one workgroup per (partition, spike, chunk of MS

@@ -21,6 +21,8 @@
 // layout is the B operand layout, and tile-transposed the A operand of the
 // transposed product); LDS holds only the band slab of the next row block,
 // the packed L11^{-1}\U11 (later U11^{-1}) and L21 (later U12) blocks.
+#include <limits>
+
 #include "solve_wave.hip"
 
 namespace lrs {
@@ -50,25 +52,32 @@ __device__ __forceinline__ void wave_fence() {  // order LDS accesses of one wav
 // BW < K restricts the ride-along to the BW x BW diagonal blocks of L11^{-1}
 // (columns [BW floor(C / BW), C) at step C); the blocks below the diagonal are
 // then formed by block products.
+// padc: the first padc steps eliminate virtual identity rows (block 0 of a
+// ragged partition), whose unit pivots are left out of dmin.
 template <typename T, int K, int C, int BW = K>
 struct FwdElim {
-  static __device__ __forceinline__ void run(T (&pa)[K], T (&iv)[K], int lane, int nr, T& mx, T& dmin, T& dinv) {
+  static __device__ __forceinline__ void run(T (&pa)[K], T (&iv)[K], int lane, int nr, T& mx, T& dmin, T& dinv,
+                                             int padc) {
     if constexpr (C < K) {
       __builtin_amdgcn_sched_barrier(0);
       const T d = bcast(pa[C], C);
       const T inv = T(1) / d;  // uniform: one reciprocal per step
       if (lane == C) dinv = inv;
-      dmin = fmin(dmin, fabs(d));
+      // min |pivot| and max |multiplier|, both sticky on NaN (an Inf pivot
+      // counts as NaN), so that a non-finite panel fails the test below
+      const T ad = fabs(d), adc = ad <= std::numeric_limits<T>::max() ? ad : T(NAN);
+      if (C >= padc) dmin = (dmin != dmin || dmin <= adc) ? dmin : adc;
       const bool act = lane > C && lane < nr;
       const T l = act ? pa[C] * inv : T(0);
-      mx = fmax(mx, fabs(l));
+      const T al = fabs(l);
+      mx = (mx != mx || mx >= al) ? mx : al;
       if (act) pa[C] = l;
 #pragma unroll
       for (int c = C + 1; c < K; ++c) pa[c] = fma(-l, bcast(pa[c], C), pa[c]);
 #pragma unroll
       for (int c = (C / BW) * BW; c < C; ++c) iv[c] = fma(-l, bcast(iv[c], C), iv[c]);
       iv[C] -= l;
-      FwdElim<T, K, C + 1, BW>::run(pa, iv, lane, nr, mx, dmin, dinv);
+      FwdElim<T, K, C + 1, BW>::run(pa, iv, lane, nr, mx, dmin, dinv, padc);
     }
   }
 };
@@ -202,6 +211,8 @@ __global__ __launch_bounds__(64) void factor_wave_kernel(FactorArgs a) {
   int* ipv = wsT<int>(a.ws, L.ipiv) + (size_t)j * L.nbmax * K;
   int* flg = wsT<int>(a.ws, L.flag) + (size_t)j * L.nbmax;
   int* npv = wsT<int>(a.ws, L.npv);
+  // diagnostics: the smallest pivot (uniform) and the largest band entry seen (per lane)
+  T pmin_run = T(INFINITY), amax_run = T(0);
 
   // band slab of row block R: slab[(d + K) K + i] = A(R K + i, R K + i + d)
   // (partition-local, identity on the virtual rows, zero outside)
@@ -234,7 +245,10 @@ __global__ __launch_bounds__(64) void factor_wave_kernel(FactorArgs a) {
 #pragma unroll
       for (int u = 0; u < SG; ++u) {
         const int o = ln + 64 * (it0 + u);
-        if (o < (2 * k + 1) * K) slab[o + (K - k) * K] = v[u];
+        if (o < (2 * k + 1) * K) {
+          slab[o + (K - k) * K] = v[u];
+          amax_run = fmax(amax_run, fabs(v[u]));
+        }
       }
     }
   };
@@ -263,7 +277,10 @@ __global__ __launch_bounds__(64) void factor_wave_kernel(FactorArgs a) {
     for (int it = 0; it < NS; ++it) {
       const int dd = dd0 + DPI * it, d = dd - k, lc = lr + d;
       const T v = lr < 0 ? ((d == 0) ? T(1) : T(0)) : ((lr < g.nj && lc >= 0 && lc < g.nj) ? nx[it] : T(0));
-      if (dd < 2 * k + 1) dst[64 * it] = v;
+      if (dd < 2 * k + 1) {
+        dst[64 * it] = v;
+        amax_run = fmax(amax_run, fabs(v));
+      }
     }
   };
   auto sl = [&](int i, int d) -> T { return (d >= -K && d <= K) ? slab[(d + K) * K + i] : T(0); };
@@ -350,15 +367,16 @@ __global__ __launch_bounds__(64) void factor_wave_kernel(FactorArgs a) {
         }
       }
       if (b + 2 < nb) slab_fetch(b + 2, nx);
-      T mx = T(0), dmin = T(1e30), dinv = T(0);
+      T mx = T(0), dmin = T(INFINITY), dinv = T(0);
       int ln1 = lane;  // own opaque lane index (its masks are not kept for later use)
       asm volatile("" : "+v"(ln1));
-      FwdElim<T, K, 0, 16>::run(pa, iv, ln1, nr, mx, dmin, dinv);
+      FwdElim<T, K, 0, 16>::run(pa, iv, ln1, nr, mx, dmin, dinv, b == 0 ? g.pad : 0);
       const bool ok = !__any(!(mx <= T(1))) && (dmin > T(0));
       if (!ok) {
         if (lane == 0) npv[j] = 1;
         return;  // refactored with row interchanges by the general kernel
       }
+      pmin_run = fmin(pmin_run, dmin);
       // lib <- the 16 x 16 diagonal blocks of L11^{-1} strictly below the
       // diagonal (and, at K = 32, the block L_{21} of L11 below them, for the
       // products that follow); l21b <- L21
@@ -480,6 +498,14 @@ __global__ __launch_bounds__(64) void factor_wave_kernel(FactorArgs a) {
     } else {
       frag_store(rec + K * K, [&](int i, int c) { return (i <= c) ? lib[i * PT + c] : T(0); });
       if (lane < K) rec[2 * K * K + lane] = T(0);
+    }
+  }
+  {
+    const T am = wave_max(amax_run);
+    if ((threadIdx.x & 63) == 0) {
+      int* st = wsT<int>(a.ws, L.latch);
+      state_min(st, S_PIVMIN, (double)pmin_run);
+      state_max(st, S_AMAX, (double)am);
     }
   }
 }

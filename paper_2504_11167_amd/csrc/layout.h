@@ -14,6 +14,13 @@ struct Layout {
   // entries) is set; otherwise the uniform rule floor(n/p) + [j < n mod p]
   const int64_t* offs;
   int k, K, p, r, R2, nbmax, mmax, tsize;  // r: compressed rank (K when the user's r = k)
+  int refined;  // iterative refinement around the solve (residual, correction and norm buffers)
+  int variant;  // reduced system: 0 = the whole block-tridiagonal Z, 1 = its diagonal blocks only
+  // systems a plan holds (1, or the systems of a batched group) and, per
+  // partition, the system slot it belongs to (device; null = all in slot 0):
+  // refinement norms are kept per (system, column)
+  int nsys;
+  const int* psys;
   int NI;       // interfaces p - 1
   int levels;   // cyclic-reduction levels (ceil(log2(NI)))
   int lvl_off[32];  // first slot of each level in the F/E arrays
@@ -28,11 +35,34 @@ struct Layout {
   // F/E per (level, active row) [nfe][2][R2][R2], scratch X [NI][2][R2][R2]
   size_t zD, zLU, zpiv, zFE, zX;
   // solve vectors (double): y tips [p][2][K][mmax], compressed rhs [NI][R2][mmax],
-  // scratch n x mmax (adjoint D-stage), refinement copy of f and residual n x mmax, norms
+  // scratch n x mmax (adjoint D-stage), refinement copy of f and residual n x mmax,
+  // norms [nsys][mmax][2]
   size_t ytip, zg, scr, fcopy, res, norms;
   size_t npv;    // int32[p]: partition needs the interchanging factorization
-  size_t latch;  // int32[16]
+  size_t latch;  // device state block (STATE_BYTES): error latch, diagnostics, refinement control
   size_t total;
+};
+
+// Device state block at L.latch, int32 slots (doubles at even int indices):
+//   error latch: code, partition, partition-local row (int64)
+//   counters and refinement control
+//   diagnostics kept by atomic min / max on the bit patterns of non-negative
+//   doubles (ordered like the values), initialised to +inf (min) or 0 (max)
+constexpr int STATE_INTS = 64;
+constexpr size_t STATE_BYTES = STATE_INTS * 4;
+enum StateSlot {
+  S_CODE = 0, S_PART = 1, S_ROW = 2,  // S_ROW: int64 over slots 2, 3
+  S_SWAPPED = 8,                      // k-row blocks that interchanged rows
+  S_STOP = 9,                         // refinement: nonzero = no further correction runs
+  S_ITERS = 10,                       // refinement: corrections applied
+  S_RSTATE = 11,                      // refinement: 0 running, 1 converged, 2 failed
+  S_PIVMIN = 16,                      // double: min |pivot| of the partition LUs
+  S_AMAX = 18,                        // double: max |a_ij| over the band entries read
+  S_GAPMIN = 20,                      // double: min (sigma_r - sigma_{r+1}) / sigma_1 over the truncated spikes
+  S_ZMAX = 22,                        // double: max |entry| of the reduced system Z
+  S_ZGROW = 24,                       // double: max |entry| of its eliminated blocks (cyclic reduction)
+  S_CORR = 26,                        // double: last correction  max_c ||d_c|| / ||x_c||
+  S_CPREV = 28                        // double: the correction before it
 };
 
 inline size_t lrs_align(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -45,10 +75,18 @@ inline int kernel_K(int k) {
 
 // offs_host / offs_dev: explicit partition offsets (p + 1 entries, host and
 // device copies) or null for the uniform partition rule
-inline void make_layout(Layout& L, int64_t n, int k, int p, int r, int tsize, int mmax,
-                        const int64_t* offs_host = nullptr, const int64_t* offs_dev = nullptr) {
+// refined: the plan iterates the solve (residual and correction buffers);
+// variant: 0 = LR-SPIKE with the whole reduced system, 1 = its truncated form;
+// nsys / psys: systems held and the partition -> system slot map (batches)
+inline void make_layout(Layout& L, int64_t n, int k, int p, int r, int tsize, int mmax, int refined = 0,
+                        int variant = 0, const int64_t* offs_host = nullptr, const int64_t* offs_dev = nullptr,
+                        int nsys = 1, const int* psys = nullptr) {
   L.n = n;
   L.offs = offs_dev;
+  L.refined = refined;
+  L.variant = variant;
+  L.nsys = nsys;
+  L.psys = psys;
   L.k = k;
   L.K = kernel_K(k);
   L.p = p;
@@ -104,11 +142,11 @@ inline void make_layout(Layout& L, int64_t n, int k, int p, int r, int tsize, in
   L.ytip = take((size_t)p * 2 * K * mmax * 8);
   L.zg = take(NI * R2 * mmax * 8);
   L.scr = take((size_t)n * mmax * 8);
-  L.fcopy = take(tsize == 4 ? (size_t)n * mmax * 8 : 0);
-  L.res = take(tsize == 4 ? (size_t)n * mmax * 8 : 0);  // residual / correction (refinement)
-  L.norms = take((size_t)4 * mmax * 8 + 64);
+  L.fcopy = take(refined ? (size_t)n * mmax * 8 : 0);
+  L.res = take(refined ? (size_t)n * mmax * 8 : 0);  // residual / correction (refinement)
+  L.norms = take((size_t)2 * nsys * mmax * 8 + 64);
   L.npv = take((size_t)p * 4);
-  L.latch = take(16 * 4);
+  L.latch = take(STATE_BYTES);
   L.total = o;
 }
 

@@ -31,6 +31,7 @@ struct RedArgs {
   int level;      // cyclic-reduction level
   int m;          // solve columns
   int transpose;  // solve with Z^T
+  const int* gate;  // refinement: nonzero *gate = no-op (null = always run)
 };
 
 template <typename T>
@@ -155,15 +156,29 @@ __global__ __launch_bounds__(LRS_NT) void eigen_kernel(RedArgs a) {
   // order eigenvalues descending (stable: ties keep the lower index first):
   // lane i places itself at its rank
   if (tid < K) {
-    const double di = G[tid * LD + tid];
+    // a NaN eigenvalue (non-finite spike; latched later in the reduced
+    // system) ranks last, so that the ranks stay a permutation
+    auto eig = [&](int c) {
+      const double v = G[c * LD + c];
+      return v == v ? v : -INFINITY;
+    };
+    const double di = eig(tid);
     int rank = 0;
     for (int c = 0; c < K; ++c) {
-      const double dc = G[c * LD + c];
+      const double dc = eig(c);
       rank += (dc > di || (dc == di && c < tid)) ? 1 : 0;
     }
     order[rank] = tid;
   }
   __syncthreads();
+  // diagnostic: relative singular-value gap at the truncation,
+  // (sigma_r - sigma_{r+1}) / sigma_1 with sigma = sqrt(eigenvalue); a spike
+  // that is zero (no coupling block) has none
+  if (tid == 0 && r > 0 && r < K) {
+    auto sig = [&](int q) { return sqrt(fmax(G[order[q] * LD + order[q]], 0.0)); };
+    const double s1 = sig(0);
+    if (s1 > 0.0) state_min(rws<int>(a.ws, L.latch), S_GAPMIN, fmax((sig(r - 1) - sig(r)) / s1, 0.0));
+  }
   for (int o = tid; o < K * r; o += blockDim.x) {
     int i = o / r, q = o % r;
     Pi[i * r + q] = V[i * LD + order[q]];
@@ -215,6 +230,7 @@ __global__ void zassemble_kernel(RedArgs a) {
   double* FE = rws<double>(a.ws, L.zFE) + (size_t)(L.lvl_off[0] + i) * 2 * R2 * R2;
   double* F = FE;
   double* E = FE + R2 * R2;
+  double zmax = 0.0;
   for (int o = threadIdx.x; o < R2 * R2; o += blockDim.x) {
     int row = o / R2, col = o % R2;
     double d = 0.0, e = 0.0, f = 0.0;
@@ -239,7 +255,10 @@ __global__ void zassemble_kernel(RedArgs a) {
     D[o] = d;
     E[o] = e;
     F[o] = f;
+    zmax = fmax(zmax, fmax(fabs(d), fmax(fabs(e), fabs(f))));
   }
+  zmax = wave_max(zmax);
+  if ((threadIdx.x & 63) == 0) state_max(rws<int>(a.ws, L.latch), S_ZMAX, zmax);
 }
 
 // ------------------------------------------------------------------ block products
@@ -330,13 +349,16 @@ __device__ inline void gauss_jordan(double* W, int pw, int R, double* colc, doub
     if (tid < 64) {  // one wave finds the pivot row
       double bv = -1.0;
       int bi = R;
+      bool nonfinite = false;
       for (int i = c + lane; i < R; i += 64) {
         const double v = fabs(W[i * pw + c]);
+        nonfinite |= !(v <= 1.7976931348623157e308);
         if (v > bv) {
           bv = v;
           bi = i;
         }
       }
+      nonfinite = __any(nonfinite);
       for (int off = 32; off > 0; off >>= 1) {
         const double ov = __shfl_xor(bv, off, 64);
         const int oi = __shfl_xor(bi, off, 64);
@@ -347,7 +369,10 @@ __device__ inline void gauss_jordan(double* W, int pw, int R, double* colc, doub
       }
       if (lane == 0) {
         *s_piv = bi;
-        if (!(bv > 0.0)) latch_error(latch, 2, part, c);
+        if (nonfinite)
+          latch_error(latch, 4, part, c);
+        else if (!(bv > 0.0))
+          latch_error(latch, 2, part, c);
       }
     }
     __syncthreads();
@@ -408,10 +433,15 @@ __global__ __launch_bounds__(LRS_NT) void cr_odd_kernel(RedArgs a) {
   double* colc = W + R * pw;
   double* rowc = colc + R;
   const double* D = rws<double>(a.ws, L.zD) + (size_t)i * R * R;
+  double dmax = 0.0;  // largest entry of the block being inverted (a Schur complement above level 0)
   for (int o = threadIdx.x; o < R * 2 * R; o += blockDim.x) {
     const int row = o / (2 * R), col = o % (2 * R);
-    W[row * pw + col] = col < R ? D[row * R + col] : (col - R == row ? 1.0 : 0.0);
+    const double v = col < R ? D[row * R + col] : (col - R == row ? 1.0 : 0.0);
+    W[row * pw + col] = v;
+    dmax = fmax(dmax, fabs(v));
   }
+  dmax = wave_max(dmax);
+  if ((threadIdx.x & 63) == 0) state_max(rws<int>(a.ws, L.latch), S_ZGROW, dmax);
   __syncthreads();
   gauss_jordan(W, pw, R, colc, rowc, &s_piv, rws<int>(a.ws, L.latch), i);
   double* Dinv = rws<double>(a.ws, L.zLU) + (size_t)i * R * R;
@@ -514,6 +544,7 @@ __device__ inline void crs_product(const CrsLds& w, int R, int m, int mm, const 
 //   Z:    g_i -= M^F_i g_{i-s} + M^E_i g_{i+s}
 //   Z^T:  g_i -= (X^E_{i-s})^T g_{i-s} + (X^F_{i+s})^T g_{i+s}
 __global__ __launch_bounds__(LRS_NT) void crs_forward_kernel(RedArgs a) {
+  if (a.gate && *a.gate) return;
   const Layout& L = a.L;
   const int R = L.R2, s = 1 << a.level, c0 = blockIdx.y * CRS_MC, m = min(CRS_MC, a.m - c0), mm = L.mmax;
   const int i = 2 * blockIdx.x * s;
@@ -537,6 +568,7 @@ __global__ __launch_bounds__(LRS_NT) void crs_forward_kernel(RedArgs a) {
 //   Z:    g_i = Dinv_i g_i - X^F_i g_{i-s} - X^E_i g_{i+s}
 //   Z^T:  g_i = Dinv_i^T g_i - (M^E_{i-s})^T g_{i-s} - (M^F_{i+s})^T g_{i+s}
 __global__ __launch_bounds__(LRS_NT) void crs_backward_kernel(RedArgs a) {
+  if (a.gate && *a.gate) return;
   const Layout& L = a.L;
   const int R = L.R2, s = 1 << a.level, c0 = blockIdx.y * CRS_MC, m = min(CRS_MC, a.m - c0), mm = L.mmax;
   const bool top = a.level >= L.levels;
@@ -570,6 +602,7 @@ __global__ __launch_bounds__(LRS_NT) void crs_backward_kernel(RedArgs a) {
 //   (c_{j+1}) = Q_{j+1,t}^T h_{(j+1,t)} + Q_{j+1,b}^T h_{(j+1,b)}
 template <int K>
 __global__ void zrhs_kernel(RedArgs a, const double* bands) {
+  if (a.gate && *a.gate) return;
   extern __shared__ __align__(16) unsigned char lds_raw[];
   double* H = reinterpret_cast<double*>(lds_raw);  // up to 4 vectors K x m
   const Layout& L = a.L;

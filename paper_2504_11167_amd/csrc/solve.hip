@@ -21,7 +21,10 @@ struct SolveArgs {
   double* dst;        // output written (may equal src)
   int ld;             // row stride of src / dst
   int m;              // columns
+  const int* gate;    // refinement: nonzero *gate = the iteration has stopped, the kernel is a no-op (null = always run)
 };
+
+__device__ __forceinline__ bool gated(const int* gate) { return gate && *gate != 0; }
 
 template <int K>
 struct SwLds {
@@ -244,6 +247,7 @@ __device__ void backward_pass(const SolveArgs& a, const Geom& g, int j, int c0, 
 
 template <typename T, int K>
 __global__ __launch_bounds__(LRS_NT) void dstage_kernel(SolveArgs a) {
+  if (gated(a.gate)) return;
   extern __shared__ __align__(16) unsigned char lds_raw[];
   __shared__ int s_perm[2 * K];
   T* lds = reinterpret_cast<T*>(lds_raw);
@@ -256,6 +260,7 @@ __global__ __launch_bounds__(LRS_NT) void dstage_kernel(SolveArgs a) {
 // Recovery: corrections from the neighbours' interface tips, then both passes.
 template <typename T, int K>
 __global__ __launch_bounds__(LRS_NT) void retrieve_kernel(SolveArgs a) {
+  if (gated(a.gate)) return;
   using LD = SwLds<K>;
   constexpr int LDM = LD::LDM;
   extern __shared__ __align__(16) unsigned char lds_raw[];
@@ -416,6 +421,7 @@ __device__ void tbackward_pass(const SolveArgs& a, const Geom& g, int j, int c0,
 // Adjoint D-stage: nu_j = A_j^{-T} g_j into the scratch (full), tips into ytip.
 template <typename T, int K>
 __global__ __launch_bounds__(LRS_NT) void adj_dstage_kernel(SolveArgs a) {
+  if (gated(a.gate)) return;
   extern __shared__ __align__(16) unsigned char lds_raw[];
   __shared__ int s_perm[2 * K];
   T* lds = reinterpret_cast<T*>(lds_raw);
@@ -441,6 +447,7 @@ __global__ __launch_bounds__(LRS_NT) void adj_dstage_kernel(SolveArgs a) {
 // where u = Z^{-T} L^T h sits in the compressed vector.
 template <typename T, int K>
 __global__ __launch_bounds__(LRS_NT) void adj_retrieve_kernel(SolveArgs a) {
+  if (gated(a.gate)) return;
   using LD = SwLds<K>;
   constexpr int LDM = LD::LDM;
   extern __shared__ __align__(16) unsigned char lds_raw[];
@@ -502,7 +509,8 @@ __global__ __launch_bounds__(RES_ROWS) void residual_kernel(const double* __rest
                                                             const double* __restrict__ f,
                                                             const double* __restrict__ x,
                                                             double* __restrict__ out, int ld, int m,
-                                                            int transpose) {
+                                                            int transpose, const int* gate) {
+  if (gated(gate)) return;
   extern __shared__ double xs[];  // (RES_ROWS + 2k) x PX
   // odd pitch: the rows the lanes of a wave read lie in different LDS banks
   constexpr int PX = RES_MC + 1;

@@ -398,6 +398,7 @@ __device__ void bwd_wave(const SolveArgs& a, const Geom& g, int j, int c0) {
 
 template <typename T, int K, int MCT>
 __global__ __launch_bounds__(64) void dstage_wave_kernel(SolveArgs a) {
+  if (gated(a.gate)) return;
   extern __shared__ __align__(16) unsigned char lds_raw[];
   T* lds = reinterpret_cast<T*>(lds_raw);
   const int j = blockIdx.x, c0 = blockIdx.y * 16 * MCT;
@@ -407,6 +408,7 @@ __global__ __launch_bounds__(64) void dstage_wave_kernel(SolveArgs a) {
 
 template <typename T, int K, int MCT>
 __global__ __launch_bounds__(64) void retrieve_wave_kernel(SolveArgs a) {
+  if (gated(a.gate)) return;
   using W = WaveSweep<T, K, MCT>;
   constexpr int NC = W::NC;
   extern __shared__ __align__(16) unsigned char lds_raw[];

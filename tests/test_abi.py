@@ -43,6 +43,7 @@ def test_default_opts_and_strerror():
     ((100, 4, 2, 5, 0, 1), -4),
     ((100, 4, 2, -1, 0, 1), -4),
     ((100, 4, 2, 2, 7, 1), -5),
+    ((100, 4, 2, 2, 3, 1), -5),
     ((100, 4, 2, 2, 0, 0), -6),
 ])
 def test_workspace_size_argument_codes(args, code):
@@ -57,8 +58,10 @@ def test_workspace_size_grows_with_problem():
     a = lr.workspace_bytes(4096, 8, 4, 8)
     b = lr.workspace_bytes(8192, 8, 4, 8)
     c = lr.workspace_bytes(4096, 8, 4, 8, precision="fp32_refined")
+    d = lr.workspace_bytes(4096, 8, 4, 8, precision="fp64_refined")
     assert 0 < a < b
     assert c > 0
+    assert d > a  # the refined plans hold the residual and the copy of f
 
 
 def test_factor_rejects_bad_sizes_before_gpu():
