@@ -34,20 +34,39 @@ REFINE_TOL = 1e-12  # refined-vs-FP64 comparison: a decade below the 1e-11 accur
 def algorithmic_bytes(kernel, n, k, m, r, wf):
     """Bytes per launch the method itself must move (spikes streamed, never stored whole).
 
-    Per row: LU = read band 8(2k+1) + write LU wf(2k+1) + write the top-tip
-    operator G wf k; spike forward = read L wf k and G wf k, write the W forward
-    intermediate wf k when r < k; back-sweeps = read U wf(k+1) and the
-    intermediate wf k; solve = one sweep pair per stage over the factors
-    wf(2k+1), plus f read (D-stage) and f read + x written (recovery).
+    Per row: LU = read the band 8(2k+1) + write the LU factors wf(2k+1);
+    spike forward = read the L factor wf k, write the W forward intermediate
+    wf k when r < k; back-sweeps = read U wf(k+1) and the intermediate wf k;
+    solve = one sweep pair per stage over the factors wf(2k+1), plus f read
+    (D-stage) and f read + x written (recovery).  Words this design adds on
+    top (the top-tip operator G, wf k per row written by the LU and read by the
+    spike forward sweep) are not counted: see `design_overhead_bytes`.
     """
     per_row = {
-        "factor_pass1": 8 * (2 * k + 1) + wf * (2 * k + 1) + wf * k,
-        "spike_fwd": 2 * wf * k + (wf * k if r < k else 0),
+        "factor_pass1": 8 * (2 * k + 1) + wf * (2 * k + 1),
+        "spike_fwd": wf * k + (wf * k if r < k else 0),
         "factor_pass2": wf * (k + 1) + wf * k,
         "dstage_kernel": wf * (2 * k + 1) + 8 * m,
         "retrieve_kernel": wf * (2 * k + 1) + 16 * m,
     }.get(kernel)
     return None if per_row is None else per_row * n
+
+
+def design_overhead_bytes(kernel, n, k, wf):
+    """Bytes per launch this design moves beyond the method's own: the operator
+    G = U^{-T} E_t that gives the top tips without a backward sweep (written by
+    the LU kernel, read by the spike forward sweep)."""
+    return {"factor_pass1": wf * k * n, "spike_fwd": wf * k * n}.get(kernel, 0)
+
+
+def phase_bytes(n, k, m, wf):
+    """Algorithmic bytes of the two phases per the method's cost model (per row):
+    factor = band read 8(2k+1) + LU written wf(2k+1) + U re-read for the
+    back-sweeps wf(k+1) + the W forward intermediate written and read 2 k wf;
+    solve = two sweep pairs over the factors 2 (2k+1) wf + f read twice and x
+    written 24 m."""
+    return {"factor": n * (8 * (2 * k + 1) + wf * (2 * k + 1) + wf * (k + 1) + 2 * k * wf),
+            "solve": n * (2 * (2 * k + 1) * wf + 24 * m)}
 
 
 def source_digest():
@@ -285,8 +304,10 @@ def main():
         plan.solve(x, inplace=True)
         return plan
 
+    # warmup with per-launch timing on: fills the library's event pool, so the
+    # timed steps only record events
     for _ in range(args.warmup):
-        step(False)
+        step(True).profile_read()
     torch.cuda.synchronize()
     log("[bench] warmup done")
     stream = torch.cuda.current_stream()
@@ -310,9 +331,23 @@ def main():
     del plans
     log(f"[bench] {args.steps} steps: {ms_step:.3f} ms/step (wall {wall:.2f} s)")
 
-    # phase split and solve-only throughput on one factorization
-    plan = lr.Plan(bands, p, r, precision=args.precision, max_nrhs=m, workspace=ws)
+    # the same steps without per-launch events (shows what the timing costs)
+    u0, u1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    u0.record(stream)
+    for _ in range(args.steps):
+        step(False)
+    u1.record(stream)
     torch.cuda.synchronize()
+    ms_step_plain = u0.elapsed_time(u1) / args.steps
+
+    # phase split: factor alone, then solves alone on one factorization
+    f0, f1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    f0.record(stream)
+    for _ in range(args.steps):
+        plan = lr.Plan(bands, p, r, precision=args.precision, max_nrhs=m, workspace=ws)
+    f1.record(stream)
+    torch.cuda.synchronize()
+    ms_factor = f0.elapsed_time(f1) / args.steps
     s0, s1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     s0.record(stream)
     for _ in range(args.steps):
@@ -323,6 +358,19 @@ def main():
     ms_solve = s0.elapsed_time(s1) / args.steps
     info = plan.status()
 
+    # achievable bandwidth of a plain device copy (1 GiB each way), beside the nominal peak
+    src = torch.empty(1 << 27, dtype=torch.float64, device=dev)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    c0, c1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    c0.record(stream)
+    for _ in range(10):
+        dst.copy_(src)
+    c1.record(stream)
+    torch.cuda.synchronize()
+    copy_gbs = 2 * src.numel() * 8 * 10 / (c0.elapsed_time(c1) * 1e-3) / 1e9
+    del src, dst
+
     # dominant kernel's roofline
     wf = 8 if args.precision == "fp64" else 4
     dom = max((v for v in kern.items() if algorithmic_bytes(v[0], n, k, m, r, wf)), key=lambda kv: kv[1][0])
@@ -331,9 +379,17 @@ def main():
     abytes = algorithmic_bytes(name, n, k, m, r, wf)
     achieved = abytes / (avg_ms * 1e-3) / 1e9
     wl = f"n{n}_k{k}_p{p}_r{r}_m{m}_{args.precision}"
+    traffic = counter_traffic(name, wl)
     roof = {"bound": "hbm", "kernel": name, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": counter_traffic(name, wl),
-            "algorithmic_bytes_per_launch": abytes, "avg_launch_ms": round(avg_ms, 4)}
+            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+            "algorithmic_bytes_per_launch": abytes, "avg_launch_ms": round(avg_ms, 4),
+            "design_overhead_bytes_per_launch": design_overhead_bytes(name, n, k, wf),
+            "traffic_over_algorithmic": round(traffic / abytes, 3) if traffic else None,
+            "copy_kernel_gbs": round(copy_gbs, 1), "frac_of_copy": round(achieved / copy_gbs, 4)}
+    pb = phase_bytes(n, k, m, wf)
+    phases = {ph: {"ms": round(t, 4), "algorithmic_bytes": pb[ph], "achieved_gbs": round(pb[ph] / (t * 1e-3) / 1e9, 1),
+                   "frac": round(pb[ph] / (t * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+              for ph, t in (("factor", ms_factor), ("solve", ms_solve))}
 
     comp = None
     if not args.no_refined and args.precision == "fp64":
@@ -359,6 +415,8 @@ def main():
                    "n": n, "k": k, "p": p, "r": r, "nrhs": m, "precision": args.precision},
         "roofline": roof,
         "cpu_baseline": cpu,
+        "ms_per_step_without_launch_events": round(ms_step_plain, 4),
+        "phases": phases,
         "solve_only": {"ms": round(ms_solve, 4), "rows_rhs_per_s": n * m / (ms_solve * 1e-3)},
         "refined_vs_fp64": comp,
         "kernels_ms_per_step": {kk: round(v[0] / args.steps, 4) for kk, v in sorted(kern.items(), key=lambda kv: -kv[1][0])},

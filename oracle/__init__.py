@@ -11,7 +11,9 @@ A plain C implementation of what the banded LR-SPIKE method computes
                       and solve-based recovery (sections "SPIKE partitioning",
                       "SPIKE reduced system solvers", "SVD representation of the
                       spikes").  With ``transpose=True`` it is R3, the exact
-                      transpose of that operator.
+                      transpose of that operator.  ``variant="t"`` is
+                      LR-SPIKE-T: the reduced system cut to its independent
+                      2 x 2 interface blocks (truncated SPIKE).
 * ``band_solve_refined``  x* accurate to about one rounding whatever the
                       condition number (residual in long double).
 * ``reduced_dense``, ``partition_spikes``, ``thin_svd``, ``band_matvec``,
@@ -48,7 +50,7 @@ def _load():
         lib.orc_partition.argtypes = [i64, i32, _I64]
         lib.orc_partition.restype = None
         lib.orc_thin_svd.argtypes = [i64, i32, _D, _D, _D]
-        lib.orc_lrspike.argtypes = [i64, i32, _D, i32, i32, i32, _D, _D, i32, _D, i32]
+        lib.orc_lrspike.argtypes = [i64, i32, _D, i32, i32, i32, _D, _D, i32, _D, i32, i32]
         lib.orc_reduced_dense.argtypes = [i64, i32, _D, i32, i32, _D]
         lib.orc_partition_spikes.argtypes = [i64, i32, _D, i32, i32, _D, _D]
         lib.orc_band_grad.argtypes = [i64, i32, i32, _D, _D, _D]
@@ -120,13 +122,21 @@ def band_matvec(bands, x, transpose=False):
     return y[:, 0] if flat else y
 
 
-def lrspike(bands, f, p, r, transpose=False, return_sv=False, threads=0):
-    """R1 (or R3 with transpose=True): the literal LR-SPIKE solve at rank r."""
+_VARIANTS = {"full": 0, "t": 1}
+
+
+def lrspike(bands, f, p, r, transpose=False, return_sv=False, threads=0, variant="full"):
+    """R1 (or R3 with transpose=True): the literal LR-SPIKE solve at rank r.
+
+    variant="full" solves the whole truncated reduced system S~_red;
+    variant="t" is LR-SPIKE-T, which keeps only its 2 x 2 interface blocks
+    [[I, V~_{j,b}], [W~_{j+1,t}, I]] (the truncated-SPIKE system S~~_red)."""
     bands, n, k = _band_args(bands)
     f2, flat = _as2d(f)
     x = np.empty_like(f2)
     sv = np.zeros((p, 2, k))
-    rc = _load().orc_lrspike(n, k, _p(bands), p, r, f2.shape[1], _p(f2), _p(x), int(transpose), _p(sv), threads)
+    rc = _load().orc_lrspike(n, k, _p(bands), p, r, f2.shape[1], _p(f2), _p(x), int(transpose), _p(sv), threads,
+                             _VARIANTS[variant])
     _check(rc, "lrspike")
     x = x[:, 0] if flat else x
     return (x, sv) if return_sv else x

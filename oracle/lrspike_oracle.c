@@ -391,7 +391,7 @@ static void project_tip(int k, int r, const double *vr, double *tip) {
 
 /* Factorization stage.  Returns 0, >0 on a zero pivot, <0 on bad input. */
 static int plan_build(orc_plan *P, int64_t n, int k, const double *bands, int p,
-                      int r, int nthreads) {
+                      int r, int variant, int nthreads) {
   memset(P, 0, sizeof(*P));
   if (n < 1 || k < 1 || p < 1 || r < 0 || r > k) return -1;
   P->n = n;
@@ -474,7 +474,11 @@ static int plan_build(orc_plan *P, int64_t n, int k, const double *bands, int p,
   }
   /* Reduced system, order 2kp, unknowns ordered [x_{0,t}; x_{0,b}; x_{1,t}; ...],
    * identity on the diagonal, truncated V tips in the column block of
-   * x_{j+1,t} and truncated W tips in the column block of x_{j-1,b}. */
+   * x_{j+1,t} and truncated W tips in the column block of x_{j-1,b}.
+   * variant 1 (LR-SPIKE-T, the truncated-SPIKE form of eqs. truncated_redsys
+   * and red_sys_prec_mid_1): the blocks V~_{j,t} and W~_{j,b} that couple the
+   * interfaces are left out, so only the 2 x 2 blocks
+   * [[I, V~_{j,b}], [W~_{j+1,t}, I]] on x_{j,b}, x_{j+1,t} remain. */
   if (p > 1) {
     int64_t N = 2 * (int64_t)k * p;
     int hb = 3 * k - 1;
@@ -489,13 +493,13 @@ static int plan_build(orc_plan *P, int64_t n, int k, const double *bands, int p,
         for (int b = 0; b < k; ++b) {
           if (j < p - 1) {
             int64_t col = 2 * (int64_t)(j + 1) * k + b; /* x_{j+1,t} */
-            *gb_at(&P->S, rt + a, col) = P->Vt[kk * j + a * k + b];
+            if (variant == 0) *gb_at(&P->S, rt + a, col) = P->Vt[kk * j + a * k + b];
             *gb_at(&P->S, rb + a, col) = P->Vb[kk * j + a * k + b];
           }
           if (j > 0) {
             int64_t col = (2 * (int64_t)(j - 1) + 1) * k + b; /* x_{j-1,b} */
             *gb_at(&P->S, rt + a, col) = P->Wt[kk * j + a * k + b];
-            *gb_at(&P->S, rb + a, col) = P->Wb[kk * j + a * k + b];
+            if (variant == 0) *gb_at(&P->S, rb + a, col) = P->Wb[kk * j + a * k + b];
           }
         }
     }
@@ -617,14 +621,19 @@ static void plan_solve_t(orc_plan *P, int m, const double *g, double *lam) {
 /*
  * R1 (transpose = 0): x = M_r^{-1} f, the LR-SPIKE solution at rank r.
  * R3 (transpose = 1): x = M_r^{-T} f.
+ * variant 0: the whole truncated reduced system S~_red; variant 1: LR-SPIKE-T,
+ * its truncated-SPIKE form S~~_red (table solver-list), with the same
+ * solve-based recovery.
  * sv (nullable) receives the singular values of every spike, p x 2 x k
  * (V_j then W_j, descending; zeros for the absent V_{p-1} and W_0).
  */
 int orc_lrspike(int64_t n, int k, const double *bands, int p, int r, int m,
-                const double *f, double *x, int transpose, double *sv, int nthreads) {
+                const double *f, double *x, int transpose, double *sv, int nthreads,
+                int variant) {
   if (m < 1) return -6;
+  if (variant != 0 && variant != 1) return -12;
   orc_plan P;
-  int rc = plan_build(&P, n, k, bands, p, r, nthreads);
+  int rc = plan_build(&P, n, k, bands, p, r, variant, nthreads);
   if (rc) return rc;
   if (sv) memcpy(sv, P.sv, sizeof(double) * (size_t)p * 2 * k);
   if (transpose)
@@ -638,7 +647,7 @@ int orc_lrspike(int64_t n, int k, const double *bands, int p, int r, int m,
 /* The dense reduced system S~_red (order 2kp, row-major) at rank r. */
 int orc_reduced_dense(int64_t n, int k, const double *bands, int p, int r, double *S) {
   orc_plan P;
-  int rc = plan_build(&P, n, k, bands, p, r, 1);
+  int rc = plan_build(&P, n, k, bands, p, r, 0, 1);
   if (rc) return rc;
   int64_t N = 2 * (int64_t)k * p;
   memset(S, 0, sizeof(double) * (size_t)(N * N));

@@ -213,13 +213,31 @@ bool set_lds(const void* fn, size_t bytes) {
     if (hipGetLastError() != hipSuccess) return LRSPIKE_ERR_HIP; \
   } while (0)
 
+// Timing events are recycled through a process-wide pool, so that a profiled
+// launch only records two events (no event creation inside a timed region).
+std::vector<hipEvent_t>& event_pool() {
+  static std::vector<hipEvent_t> pool;
+  return pool;
+}
+hipEvent_t event_get() {
+  auto& pool = event_pool();
+  if (!pool.empty()) {
+    hipEvent_t e = pool.back();
+    pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  return hipEventCreate(&e) == hipSuccess ? e : nullptr;
+}
+void event_put(hipEvent_t e) { event_pool().push_back(e); }
+
 // Launch on the plan's stream; with profiling on, bracket it with an event pair.
 template <typename... KArgs, typename... Args>
 int launch(lrspike_plan P, const char* name, void (*kern)(KArgs...), dim3 grid, dim3 block, size_t lds,
            Args... args) {
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (P->profiling) {
-    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return LRSPIKE_ERR_HIP;
+    if (!(e0 = event_get()) || !(e1 = event_get())) return LRSPIKE_ERR_HIP;
     if (hipEventRecord(e0, P->stream) != hipSuccess) return LRSPIKE_ERR_HIP;
   }
   hipLaunchKernelGGL(kern, grid, block, lds, P->stream, args...);
@@ -515,8 +533,8 @@ void free_refine_host(lrspike_plan P) {
 
 void prof_clear(lrspike_plan P) {
   for (auto& e : P->prof) {
-    (void)hipEventDestroy(e.second.first);
-    (void)hipEventDestroy(e.second.second);
+    event_put(e.second.first);
+    event_put(e.second.second);
   }
   P->prof.clear();
 }

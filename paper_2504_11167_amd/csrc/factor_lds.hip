@@ -166,10 +166,13 @@ __global__ __launch_bounds__(LRS_NT) void factor_lds_kernel(FactorArgs a) {
         FwdElim<T, H, 0, 16>::run(pa, iv, ln1, nrow, mx, dmin, dinv, b == 0 ? g.pad - r0 : 0);
         // dmin is NaN after a non-finite pivot (Inf/NaN in the band), 0 after
         // an exactly zero one; a multiplier above 1 would need an interchange
+        // The first failing pivot decides the code: a zero one (reciprocal
+        // Inf) is ZERO_PIVOT even though the steps after it turn NaN.
         const unsigned long long zb = __ballot(lane < H && !(isfinite(dinv) && dinv != T(0)));
         const unsigned long long bb = __ballot(lane < nrow && !(mx <= T(1)));
+        const T dz = __shfl(dinv, zb ? __ffsll(zb) - 1 : 0);
         if (lane == 0 && s_bad == 0 && (zb || bb || !(dmin > T(0)))) {
-          s_bad = (dmin != dmin) ? 3 : ((zb || !(dmin > T(0))) ? 1 : 2);
+          s_bad = zb ? (isinf(dz) ? 1 : 3) : ((dmin != dmin) ? 3 : (!(dmin > T(0)) ? 1 : 2));
           s_row = b * K + r0 + (zb ? __ffsll(zb) - 1 : (bb ? __ffsll(bb) - 1 : 0)) - g.pad;
         }
         pmin_run = fmin(pmin_run, dmin);

@@ -166,6 +166,39 @@ def test_p12_backward_error():
     assert eta < 8 * (k + 1) * np.finfo(float).eps * 10
 
 
+def test_refined_reference_exact_on_integer_system():
+    """Small-integer band and integer x_true: f = A x_true is exact in double,
+    so a solve whose residual is accumulated beyond double precision recovers
+    x_true to the last bit, while plain elimination is off by about kappa u
+    (kappa_1 ~ 4e5 here).  A residual accumulated in double would leave the
+    refined result at the plain one's accuracy."""
+    rng = np.random.default_rng(1)
+    n, k = 600, 4
+    bands = rng.integers(-5, 6, size=(2 * k + 1, n)).astype(float)
+    for d in range(-k, k + 1):
+        if d < 0:
+            bands[d + k, :-d] = 0.0
+        elif d > 0:
+            bands[d + k, n - d:] = 0.0
+    bands[k] = np.round(0.3 * (np.abs(bands).sum(axis=0) - np.abs(bands[k])))
+    x_true = rng.integers(-8, 9, size=(n, 2)).astype(float)
+    f = dense(bands) @ x_true  # integers well below 2^53: exact
+    assert np.array_equal(f, oracle.band_matvec(bands, x_true))
+    x0 = oracle.band_solve(bands, f)
+    xr = oracle.band_solve_refined(bands, f, steps=3)
+    assert rel(x0, x_true) > 1e-14
+    assert rel(xr, x_true) <= 2 * np.finfo(float).eps
+
+
+def test_band_matvec_transpose_is_dense_transpose():
+    n, k = 50, 3
+    bands, _ = synth.make_problem(n, k, 1, seed=4, rule="theta", theta=0.5)
+    x = np.random.default_rng(3).standard_normal((n, 2))
+    A = dense(bands)
+    assert np.abs(oracle.band_matvec(bands, x) - A @ x).max() < 1e-13
+    assert np.abs(oracle.band_matvec(bands, x, transpose=True) - A.T @ x).max() < 1e-13
+
+
 def test_refined_reference_beats_plain_on_hard_matrix():
     """The long-double-residual reference reaches ~u forward error; check it by
     solving a problem whose exact answer is known (f = A x_true in exact arithmetic
@@ -323,8 +356,11 @@ def test_p7_rank_zero_is_two_block_jacobi_sweeps():
     assert rel(oracle.lrspike(bands, f, p, 0), ref) < 1e-13
 
 
-def _woodbury_dense(A, offs, k, r, f, transpose=False):
-    """M_r^{-1} f = D^{-1} f - D^{-1} K S~^{-1} E^T D^{-1} f built densely with numpy's SVD."""
+def _woodbury_dense(A, offs, k, r, f, transpose=False, truncated=False):
+    """M_r^{-1} f = D^{-1} f - D^{-1} K S~^{-1} E^T D^{-1} f built densely with numpy's SVD.
+    truncated=True: S~ with the blocks V~_{j,t} (rows x_{j,t}, columns x_{j+1,t})
+    and W~_{j,b} (rows x_{j,b}, columns x_{j-1,b}) zeroed, the truncated-SPIKE
+    system S~~_red of LR-SPIKE-T."""
     n = A.shape[0]
     p = len(offs) - 1
     D = _blocks(A, offs)
@@ -349,6 +385,12 @@ def _woodbury_dense(A, offs, k, r, f, transpose=False):
             Sp[s:e, (2 * j - 1) * k:2 * j * k] = W @ Psi @ Psi.T
     assert np.abs(A - D - K @ E.T).max() == 0.0  # the DS / Woodbury split of A
     S = np.eye(N) + E.T @ Sp
+    if truncated:
+        for j in range(p):
+            if j < p - 1:
+                S[2 * j * k:2 * j * k + k, 2 * (j + 1) * k:2 * (j + 1) * k + k] = 0.0
+            if j > 0:
+                S[(2 * j + 1) * k:(2 * j + 2) * k, (2 * j - 1) * k:2 * j * k] = 0.0
     Dinv = np.linalg.inv(D)
     M = Dinv - Dinv @ K @ np.linalg.solve(S, E.T @ Dinv)
     return (M.T if transpose else M) @ f, S
@@ -366,6 +408,79 @@ def test_p3_woodbury_dense_all_ranks(r):
     assert np.abs(S_or - S).max() < 1e-13
     reft, _ = _woodbury_dense(A, offs, k, r, f, transpose=True)
     assert rel(oracle.lrspike(bands, f, p, r, transpose=True), reft) < 1e-12
+
+
+# ---------------------------------------------------------------- LR-SPIKE-T
+
+
+@pytest.mark.parametrize("r", [0, 1, 2, 4])
+def test_t_variant_dense_truncated_woodbury(r):
+    """LR-SPIKE-T = D^{-1} - D^{-1} K S~~^{-1} E^T D^{-1} with S~~ the reduced
+    system without V~_{j,t} and W~_{j,b} (eqs. truncated_redsys,
+    red_sys_prec_mid_1), built densely with numpy; also its transpose."""
+    n, k, p = 96, 4, 4
+    bands, f = synth.make_problem(n, k, 2, seed=21, rule="weak")
+    A = dense(bands)
+    offs = oracle.partition(n, p)
+    ref, _ = _woodbury_dense(A, offs, k, r, f, truncated=True)
+    full, _ = _woodbury_dense(A, offs, k, r, f)
+    assert rel(oracle.lrspike(bands, f, p, r, variant="t"), ref) < 1e-12
+    if r > 0:  # (at r = 0 no spike is kept and the two coincide)
+        assert rel(ref, full) > 1e-6  # the dropped couplings matter on this matrix
+    reft, _ = _woodbury_dense(A, offs, k, r, f, transpose=True, truncated=True)
+    assert rel(oracle.lrspike(bands, f, p, r, transpose=True, variant="t"), reft) < 1e-12
+
+
+@pytest.mark.parametrize("r", [0, 2, 6])
+def test_t_variant_two_partitions_equals_full(r):
+    """With two partitions the only dropped blocks (V~_{0,t}, W~_{1,b}) sit in
+    rows no other unknown depends on: LR-SPIKE-T = LR-SPIKE (the 2 x 2 kernel of eq. 2x2)."""
+    bands, f = synth.make_problem(500, 6, 3, seed=22, rule="weak")
+    assert rel(oracle.lrspike(bands, f, 2, r, variant="t"), oracle.lrspike(bands, f, 2, r)) < 1e-13
+
+
+def test_t_variant_exact_when_off_diagonal_tips_vanish():
+    """Cut every partition into two halves that do not couple: then V_j lives in
+    the bottom half and W_j in the top half, V_{j,t} = W_{j,b} = 0, and the
+    truncated reduced system is the whole one (exact at r = k, equal to
+    LR-SPIKE at every r)."""
+    n, k, p = 180, 5, 6  # 30-row partitions: short enough for the tips to couple
+    bands, f = synth.make_problem(n, k, 2, seed=23, rule="weak")
+    offs = oracle.partition(n, p)
+    for j in range(p):
+        mid = (offs[j] + offs[j + 1]) // 2
+        for d in range(-k, k + 1):
+            for i in range(mid - k, mid + k):
+                if (i < mid <= i + d) or (i + d < mid <= i):
+                    bands[d + k, i] = 0.0
+    x_t = oracle.lrspike(bands, f, p, k, variant="t")
+    assert rel(x_t, oracle.band_solve(bands, f)) < 1e-13
+    for r in (1, 3):
+        assert rel(oracle.lrspike(bands, f, p, r, variant="t"), oracle.lrspike(bands, f, p, r)) < 1e-13
+    # without the cut the dropped blocks are not zero and the two differ
+    bands2, _ = synth.make_problem(n, k, 2, seed=23, rule="weak")
+    assert rel(oracle.lrspike(bands2, f, p, k, variant="t"), oracle.band_solve(bands2, f)) > 1e-10
+
+
+def test_t_variant_decay_on_strongly_dominant():
+    """Strict dominance 2k+1+|u| with n_j = 1024 rows: the spikes decay away from
+    their tip (the premise of truncated SPIKE), so V_{j,t} and W_{j,b} are below
+    rounding and LR-SPIKE-T equals LR-SPIKE."""
+    bands, f = synth.make_problem(4096, 8, 2, seed=24, rule="strict")
+    for r in (8, 4):
+        assert rel(oracle.lrspike(bands, f, 4, r, variant="t"), oracle.lrspike(bands, f, 4, r)) < 1e-14
+
+
+@pytest.mark.parametrize("r", [0, 3, 8])
+def test_t_variant_adjoint_dot_product(r):
+    n, k, p = 2000, 8, 6
+    bands, _ = synth.make_problem(n, k, 1, seed=25, rule="weak")
+    rng = np.random.default_rng(0)
+    f = rng.standard_normal((n, 3))
+    g = rng.standard_normal((n, 3))
+    x = oracle.lrspike(bands, f, p, r, variant="t")
+    lam = oracle.lrspike(bands, g, p, r, transpose=True, variant="t")
+    assert abs(np.sum(x * g) - np.sum(f * lam)) <= 1e-13 * np.linalg.norm(x) * np.linalg.norm(g)
 
 
 def test_p9_determinant_identity():
