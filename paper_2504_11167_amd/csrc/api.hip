@@ -317,6 +317,12 @@ int run_factor(lrspike_plan P) {
     const size_t bodd = (size_t)(R2 * (2 * R2 + 1) + 3 * R2) * 8, beven = (size_t)2 * R2 * (R2 + 1) * 8;
     if (!set_lds((const void*)cr_odd_kernel, bodd) || !set_lds((const void*)cr_even_kernel, beven))
       return LRSPIKE_ERR_NOT_SUPPORTED;
+    if (L.variant) {
+      // LR-SPIKE-T: the interface blocks are independent, each inverted on its own
+      ra.level = -1;
+      LRS_LAUNCH("cr_odd_kernel", cr_odd_kernel, dim3(L.NI), dim3(LRS_NT), bodd, ra);
+      return 0;
+    }
     for (int l = 0; l < L.levels; ++l) {
       int s = 1 << l;
       int nodd = (L.NI + s - 1) / (2 * s);  // rows (2q+1)s < NI
@@ -344,6 +350,11 @@ int run_reduced(lrspike_plan P, int m, int transpose, const int* gate) {
   const size_t bs = (size_t)(R2 * (R2 + 1) + R2 * (mc + 1) + R2 * mc) * 8;
   if (!set_lds((const void*)crs_forward_kernel, bs) || !set_lds((const void*)crs_backward_kernel, bs))
     return LRSPIKE_ERR_NOT_SUPPORTED;
+  if (L.variant) {  // LR-SPIKE-T: z_i = D_i^{-1} g_i (or D_i^{-T} g_i) for every interface at once
+    ra.level = -1;
+    LRS_LAUNCH("crs_backward_kernel", crs_backward_kernel, dim3(L.NI, nch), dim3(LRS_NT), bs, ra);
+    return 0;
+  }
   for (int l = 0; l < L.levels; ++l) {
     int s = 1 << l;
     ra.level = l;

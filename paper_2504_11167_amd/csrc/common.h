@@ -117,11 +117,17 @@ __device__ inline void latch_error(int* latch, int code, int part, int64_t row) 
 // Running min / max of non-negative doubles in the state block: the IEEE bit
 // patterns of non-negative doubles are ordered like their values, so 64-bit
 // integer atomics on the patterns keep the extreme (+inf is the min's start).
+// The stored extreme is read first and the atomic issued only when v would
+// change it, so that thousands of workgroups do not serialise on one address.
 __device__ inline void state_min(int* st, int slot, double v) {
-  atomicMin(reinterpret_cast<unsigned long long*>(st + slot), (unsigned long long)__double_as_longlong(v));
+  unsigned long long* a = reinterpret_cast<unsigned long long*>(st + slot);
+  const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+  if (b < __hip_atomic_load(a, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) atomicMin(a, b);
 }
 __device__ inline void state_max(int* st, int slot, double v) {
-  atomicMax(reinterpret_cast<unsigned long long*>(st + slot), (unsigned long long)__double_as_longlong(v));
+  unsigned long long* a = reinterpret_cast<unsigned long long*>(st + slot);
+  const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+  if (b > __hip_atomic_load(a, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) atomicMax(a, b);
 }
 
 // Wave-wide min / max (all 64 lanes; every lane gets the result).

@@ -84,7 +84,13 @@ __global__ __launch_bounds__(LRS_NT) void factor_lds_kernel(FactorArgs a) {
   int* ipv = wsT<int>(a.ws, L.ipiv) + (size_t)j * L.nbmax * K;
   int* flg = wsT<int>(a.ws, L.flag) + (size_t)j * L.nbmax;
   int* latch = wsT<int>(a.ws, L.latch);
-  T amax_run = T(0), pmin_run = T(INFINITY);  // diagnostics: largest band entry, smallest pivot
+  // diagnostics in LDS (registers are spent on the products): per thread the
+  // largest band entry it loaded, and the smallest pivot (wave 0)
+  __shared__ double s_amax[LRS_NT];
+  __shared__ double s_pmin;
+  __shared__ double s_dinv[K];  // reciprocal pivots of the block's two register passes
+  s_amax[tid] = 0.0;
+  if (tid == 0) s_pmin = INFINITY;
   // A_j(lr, lc) in partition-local rows/columns (identity on the padding rows)
   auto Aj = [&](int lr, int lc) -> T {
     if (lr < 0 || lc < 0) return (lr == lc) ? T(1) : T(0);
@@ -112,6 +118,7 @@ __global__ __launch_bounds__(LRS_NT) void factor_lds_kernel(FactorArgs a) {
                        d >= -k && d <= k;
       vals[t] = (T)a.bands[inb ? (int64_t)(d + k) * L.n + g.s + lr : 0];
     }
+    T am = T(0);
 #pragma unroll
     for (int t = 0; t < NI; ++t) {
       const int e = w + 4 * t - (K - 1), c = i + e, lc = C * K + c - g.pad, d = lc - lr;
@@ -119,8 +126,9 @@ __global__ __launch_bounds__(LRS_NT) void factor_lds_kernel(FactorArgs a) {
                        d >= -k && d <= k;
       const bool ident = (lr < 0 || lc < 0) && lr == lc;
       if (e <= K - 1 && c >= 0 && c < K) dst[i * PT + c] = inb ? vals[t] : (ident ? T(1) : T(0));
-      if (inb) amax_run = fmax(amax_run, fabs(vals[t]));
+      if (inb) am = fmax(am, fabs(vals[t]));
     }
+    s_amax[tid] = fmax(s_amax[tid], (double)am);
   };
   load_block(P, 0, 0);
   for (int o = tid; o < K * K; o += LRS_NT) Gp[(o / K) * PT + o % K] = T(0);
@@ -163,19 +171,20 @@ __global__ __launch_bounds__(LRS_NT) void factor_lds_kernel(FactorArgs a) {
         asm volatile("" : "+v"(ln1));
         // the L1^{-1} ride-along and the U1^{-1} pass cover the 16 x 16
         // diagonal blocks; their off-diagonal blocks come from block products
-        FwdElim<T, H, 0, 16>::run(pa, iv, ln1, nrow, mx, dmin, dinv, b == 0 ? g.pad - r0 : 0);
-        // dmin is NaN after a non-finite pivot (Inf/NaN in the band), 0 after
-        // an exactly zero one; a multiplier above 1 would need an interchange
-        // The first failing pivot decides the code: a zero one (reciprocal
-        // Inf) is ZERO_PIVOT even though the steps after it turn NaN.
+        FwdElim<T, H, 0, 16>::run(pa, iv, ln1, nrow, mx, dmin, dinv);
+        // a zero pivot leaves an infinite reciprocal in its lane, a non-finite
+        // one a NaN or zero reciprocal; the first failing pivot decides the
+        // code (ZERO_PIVOT for a zero one even though the steps after it turn
+        // NaN); a multiplier above 1 would need an interchange
+        // (the reciprocals go through LDS: no extra registers while the panel is live)
+        if (lane < H) s_dinv[r0 + lane] = (double)dinv;
+        wave_fence();
         const unsigned long long zb = __ballot(lane < H && !(isfinite(dinv) && dinv != T(0)));
         const unsigned long long bb = __ballot(lane < nrow && !(mx <= T(1)));
-        const T dz = __shfl(dinv, zb ? __ffsll(zb) - 1 : 0);
         if (lane == 0 && s_bad == 0 && (zb || bb || !(dmin > T(0)))) {
-          s_bad = zb ? (isinf(dz) ? 1 : 3) : ((dmin != dmin) ? 3 : (!(dmin > T(0)) ? 1 : 2));
+          s_bad = zb ? (isinf(s_dinv[r0 + __ffsll(zb) - 1]) ? 1 : 3) : (!(dmin > T(0)) ? 1 : 2);
           s_row = b * K + r0 + (zb ? __ffsll(zb) - 1 : (bb ? __ffsll(bb) - 1 : 0)) - g.pad;
         }
-        pmin_run = fmin(pmin_run, dmin);
         if (lane < H) {
 #pragma unroll
           for (int c = 0; c < H; ++c)
@@ -281,6 +290,10 @@ __global__ __launch_bounds__(LRS_NT) void factor_lds_kernel(FactorArgs a) {
                     j, s_row);
       return;
     }
+    if (tid < 64) {  // smallest pivot of the block's real rows (block 0 may start with virtual unit rows)
+      const double pinv = wave_max((tid < K && b * K + tid >= g.pad) ? fabs(s_dinv[tid]) : 0.0);
+      if (tid == 0 && pinv > 0.0) s_pmin = fmin(s_pmin, 1.0 / pinv);
+    }
     auto Li = [&](int r, int l) -> T {
       const T x = P[r * PT + l];
       return r > l ? x : (r == l ? T(1) : T(0));
@@ -358,9 +371,10 @@ __global__ __launch_bounds__(LRS_NT) void factor_lds_kernel(FactorArgs a) {
       __syncthreads();
     }
   }
-  const T am = wave_max(amax_run);
-  if ((tid & 63) == 0) state_max(latch, S_AMAX, (double)am);
-  if (tid == 0) state_min(latch, S_PIVMIN, (double)pmin_run);  // the register passes run on wave 0
+  __syncthreads();
+  const double am = wave_max(s_amax[tid]);
+  if ((tid & 63) == 0) state_max(latch, S_AMAX, am);
+  if (tid == 0) state_min(latch, S_PIVMIN, s_pmin);  // the register passes run on wave 0
 }
 
 // Spikes from the records, one workgroup per (partition, spike, chunk of MS

@@ -34,7 +34,8 @@ struct FWave {
   static constexpr int oSlab = 0;                    // (2K+1) x K, diagonal-major
   static constexpr int oLib = oSlab + (2 * K + 1) * K;  // K x PT
   static constexpr int oL21 = oLib + K * PT;         // K x PT
-  static constexpr int total = oL21 + K * PT;
+  static constexpr int oDiag = oL21 + K * PT;        // per lane: max |1 / pivot|, max |a_ij| (diagnostics)
+  static constexpr int total = oDiag + 128;
 };
 
 __device__ __forceinline__ void wave_fence() {  // order LDS accesses of one wave
@@ -52,32 +53,28 @@ __device__ __forceinline__ void wave_fence() {  // order LDS accesses of one wav
 // BW < K restricts the ride-along to the BW x BW diagonal blocks of L11^{-1}
 // (columns [BW floor(C / BW), C) at step C); the blocks below the diagonal are
 // then formed by block products.
-// padc: the first padc steps eliminate virtual identity rows (block 0 of a
-// ragged partition), whose unit pivots are left out of dmin.
+// mx and dmin collect max |multiplier| and min |pivot| (NaN operands are
+// ignored there: a non-finite pivot shows as a non-finite or zero reciprocal
+// dinv in its lane, which the callers test once per panel).
 template <typename T, int K, int C, int BW = K>
 struct FwdElim {
-  static __device__ __forceinline__ void run(T (&pa)[K], T (&iv)[K], int lane, int nr, T& mx, T& dmin, T& dinv,
-                                             int padc) {
+  static __device__ __forceinline__ void run(T (&pa)[K], T (&iv)[K], int lane, int nr, T& mx, T& dmin, T& dinv) {
     if constexpr (C < K) {
       __builtin_amdgcn_sched_barrier(0);
       const T d = bcast(pa[C], C);
       const T inv = T(1) / d;  // uniform: one reciprocal per step
       if (lane == C) dinv = inv;
-      // min |pivot| and max |multiplier|, both sticky on NaN (an Inf pivot
-      // counts as NaN), so that a non-finite panel fails the test below
-      const T ad = fabs(d), adc = ad <= std::numeric_limits<T>::max() ? ad : T(NAN);
-      if (C >= padc) dmin = (dmin != dmin || dmin <= adc) ? dmin : adc;
+      dmin = fmin(dmin, fabs(d));
       const bool act = lane > C && lane < nr;
       const T l = act ? pa[C] * inv : T(0);
-      const T al = fabs(l);
-      mx = (mx != mx || mx >= al) ? mx : al;
+      mx = fmax(mx, fabs(l));
       if (act) pa[C] = l;
 #pragma unroll
       for (int c = C + 1; c < K; ++c) pa[c] = fma(-l, bcast(pa[c], C), pa[c]);
 #pragma unroll
       for (int c = (C / BW) * BW; c < C; ++c) iv[c] = fma(-l, bcast(iv[c], C), iv[c]);
       iv[C] -= l;
-      FwdElim<T, K, C + 1, BW>::run(pa, iv, lane, nr, mx, dmin, dinv, padc);
+      FwdElim<T, K, C + 1, BW>::run(pa, iv, lane, nr, mx, dmin, dinv);
     }
   }
 };
@@ -211,8 +208,12 @@ __global__ __launch_bounds__(64) void factor_wave_kernel(FactorArgs a) {
   int* ipv = wsT<int>(a.ws, L.ipiv) + (size_t)j * L.nbmax * K;
   int* flg = wsT<int>(a.ws, L.flag) + (size_t)j * L.nbmax;
   int* npv = wsT<int>(a.ws, L.npv);
-  // diagnostics: the smallest pivot (uniform) and the largest band entry seen (per lane)
-  T pmin_run = T(INFINITY), amax_run = T(0);
+  // diagnostics, kept per lane in LDS (not in registers, which the panel
+  // and the products need): max |1 / pivot| over the lane's pivots and max
+  // |a_ij| over the band entries the lane stored
+  T* diag = lds + F::oDiag;
+  diag[lane] = T(0);
+  diag[64 + lane] = T(0);
 
   // band slab of row block R: slab[(d + K) K + i] = A(R K + i, R K + i + d)
   // (partition-local, identity on the virtual rows, zero outside)
@@ -242,14 +243,16 @@ __global__ __launch_bounds__(64) void factor_wave_kernel(FactorArgs a) {
         }
         v[u] = x;
       }
+      T am = diag[64 + ln];
 #pragma unroll
       for (int u = 0; u < SG; ++u) {
         const int o = ln + 64 * (it0 + u);
         if (o < (2 * k + 1) * K) {
           slab[o + (K - k) * K] = v[u];
-          amax_run = fmax(amax_run, fabs(v[u]));
+          am = fmax(am, fabs(v[u]));
         }
       }
+      diag[64 + ln] = am;
     }
   };
   // The same slab through registers: fetched early, stored late.  With
@@ -273,15 +276,17 @@ __global__ __launch_bounds__(64) void factor_wave_kernel(FactorArgs a) {
     asm volatile("" : "+v"(ln));
     const int i = ln % K, dd0 = ln / K, lr = R * K + i - g.pad;
     T* dst = slab + (K - k) * K + ln;
+    T am = diag[64 + ln];
 #pragma unroll
     for (int it = 0; it < NS; ++it) {
       const int dd = dd0 + DPI * it, d = dd - k, lc = lr + d;
       const T v = lr < 0 ? ((d == 0) ? T(1) : T(0)) : ((lr < g.nj && lc >= 0 && lc < g.nj) ? nx[it] : T(0));
       if (dd < 2 * k + 1) {
         dst[64 * it] = v;
-        amax_run = fmax(amax_run, fabs(v));
+        am = fmax(am, fabs(v));
       }
     }
+    diag[64 + ln] = am;
   };
   auto sl = [&](int i, int d) -> T { return (d >= -K && d <= K) ? slab[(d + K) * K + i] : T(0); };
   auto for_elems = [&](auto&& fn) {  // (t, ct, v, row, col) of the lane's accumulator elements
@@ -370,13 +375,16 @@ __global__ __launch_bounds__(64) void factor_wave_kernel(FactorArgs a) {
       T mx = T(0), dmin = T(INFINITY), dinv = T(0);
       int ln1 = lane;  // own opaque lane index (its masks are not kept for later use)
       asm volatile("" : "+v"(ln1));
-      FwdElim<T, K, 0, 16>::run(pa, iv, ln1, nr, mx, dmin, dinv, b == 0 ? g.pad : 0);
-      const bool ok = !__any(!(mx <= T(1))) && (dmin > T(0));
+      FwdElim<T, K, 0, 16>::run(pa, iv, ln1, nr, mx, dmin, dinv);
+      // a zero or non-finite pivot leaves an infinite, NaN or zero reciprocal
+      // in its lane: such a partition (and one that would interchange rows)
+      // goes to the interchanging kernel, which latches the precise error
+      const bool ok = !__any(!(mx <= T(1)) || (ln1 < K && !(isfinite(dinv) && dinv != T(0)))) && (dmin > T(0));
       if (!ok) {
         if (lane == 0) npv[j] = 1;
         return;  // refactored with row interchanges by the general kernel
       }
-      pmin_run = fmin(pmin_run, dmin);
+      if (ln1 < K && b * K + ln1 >= g.pad) diag[ln1] = fmax(diag[ln1], fabs(dinv));  // not the virtual rows
       // lib <- the 16 x 16 diagonal blocks of L11^{-1} strictly below the
       // diagonal (and, at K = 32, the block L_{21} of L11 below them, for the
       // products that follow); l21b <- L21
@@ -501,10 +509,11 @@ __global__ __launch_bounds__(64) void factor_wave_kernel(FactorArgs a) {
     }
   }
   {
-    const T am = wave_max(amax_run);
+    wave_sync();
+    const T pinv = wave_max(diag[lane]), am = wave_max(diag[64 + lane]);
     if ((threadIdx.x & 63) == 0) {
       int* st = wsT<int>(a.ws, L.latch);
-      state_min(st, S_PIVMIN, (double)pmin_run);
+      state_min(st, S_PIVMIN, pinv > T(0) ? 1.0 / (double)pinv : (double)INFINITY);
       state_max(st, S_AMAX, (double)am);
     }
   }

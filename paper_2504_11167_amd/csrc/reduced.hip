@@ -20,6 +20,15 @@
 // and the tips follow as x_{j,t/b} = y_{j,t/b} - P_{j,t/b} a_j - Q_{j,t/b} c_j.
 // Z is factored by block cyclic reduction (log2(p) levels, every level fully
 // parallel) in FP64 for every precision.
+//
+// LR-SPIKE-T (the truncated-SPIKE system S~~_red of eqs. truncated_redsys,
+// red_sys_prec_mid_1/2, red_sys_1, red_sys_mid, red_sys_3) drops V~_{j,t} and
+// W~_{j,b}: in the compressed form that removes E_j and F_j, so every
+// interface j is the independent system D_j z_j = g_j (solved here by the
+// inverse of D_j: the 2r x 2r counterpart of the block inversion the paper
+// writes with the Schur complement M_i), and the tips keep only their own
+// interface's term: x_{j,b} = y_{j,b} - P_{j,b} a_j, x_{j+1,t} = y_{j+1,t} -
+// Q_{j+1,t} c_{j+1}.
 #include "common.h"
 #include "layout.h"
 
@@ -28,7 +37,7 @@ namespace lrs {
 struct RedArgs {
   char* ws;
   Layout L;
-  int level;      // cyclic-reduction level
+  int level;      // cyclic-reduction level; -1 = LR-SPIKE-T: every interface block on its own
   int m;          // solve columns
   int transpose;  // solve with Z^T
   const int* gate;  // refinement: nonzero *gate = no-op (null = always run)
@@ -252,6 +261,7 @@ __global__ void zassemble_kernel(RedArgs a) {
       d = (row == col) ? 1.0 : 0.0;
       if (i >= 1) f = dot(Psi(i + 1), PT(i, 3));  // Psi_{i+1}^T Q_{i,b}
     }
+    if (L.variant) e = f = 0.0;  // LR-SPIKE-T: no coupling between interfaces
     D[o] = d;
     E[o] = e;
     F[o] = f;
@@ -426,9 +436,10 @@ __global__ __launch_bounds__(LRS_NT) void cr_odd_kernel(RedArgs a) {
   double* W = reinterpret_cast<double*>(lds_raw);
   __shared__ int s_piv;
   const Layout& L = a.L;
-  const int R = L.R2, s = 1 << a.level, pw = 2 * R + 1;
-  const bool top = a.level >= L.levels;
-  const int i = top ? 0 : (2 * blockIdx.x + 1) * s;
+  const bool tmode = a.level < 0;  // LR-SPIKE-T: invert every diagonal block, nothing else
+  const int R = L.R2, s = tmode ? 1 : 1 << a.level, pw = 2 * R + 1;
+  const bool top = tmode || a.level >= L.levels;
+  const int i = tmode ? blockIdx.x : (top ? 0 : (2 * blockIdx.x + 1) * s);
   if (i >= L.NI) return;
   double* colc = W + R * pw;
   double* rowc = colc + R;
@@ -570,9 +581,11 @@ __global__ __launch_bounds__(LRS_NT) void crs_forward_kernel(RedArgs a) {
 __global__ __launch_bounds__(LRS_NT) void crs_backward_kernel(RedArgs a) {
   if (a.gate && *a.gate) return;
   const Layout& L = a.L;
-  const int R = L.R2, s = 1 << a.level, c0 = blockIdx.y * CRS_MC, m = min(CRS_MC, a.m - c0), mm = L.mmax;
-  const bool top = a.level >= L.levels;
-  const int i = top ? 0 : (2 * blockIdx.x + 1) * s;
+  const bool tmode = a.level < 0;  // LR-SPIKE-T: g_i = Dinv_i g_i for every interface
+  const int R = L.R2, s = tmode ? 1 : 1 << a.level, c0 = blockIdx.y * CRS_MC, m = min(CRS_MC, a.m - c0),
+            mm = L.mmax;
+  const bool top = tmode || a.level >= L.levels;
+  const int i = tmode ? blockIdx.x : (top ? 0 : (2 * blockIdx.x + 1) * s);
   if (i >= L.NI) return;
   const CrsLds w = crs_lds(R, m);
   double* g = rws<double>(a.ws, L.zg) + c0;
@@ -647,10 +660,13 @@ __global__ void zrhs_kernel(RedArgs a, const double* bands) {
       out[row * m + c] = s;
     }
   };
-  hvec(i, true, H);
+  // LR-SPIKE-T keeps only P_{i,b} in (a_i) and Q_{i+1,t} in (c_{i+1}): the
+  // transpose of the tip corrections it applies
+  const bool tv = L.variant != 0;
+  if (!tv) hvec(i, true, H);
   hvec(i, false, H + K * m);
   hvec(i + 1, true, H + 2 * K * m);
-  hvec(i + 1, false, H + 3 * K * m);
+  if (!tv) hvec(i + 1, false, H + 3 * K * m);
   __syncthreads();
   auto PT = [&](int j, int w) { return ptip + ((size_t)j * 4 + w) * K * r; };
   for (int o = threadIdx.x; o < 2 * r * m; o += blockDim.x) {
@@ -659,13 +675,18 @@ __global__ void zrhs_kernel(RedArgs a, const double* bands) {
     if (row < r) {
       const double* Pt = PT(i, 0);
       const double* Pb = PT(i, 1);
-      for (int l = 0; l < K; ++l) s += Pt[l * r + row] * H[l * m + c] + Pb[l * r + row] * H[K * m + l * m + c];
+      for (int l = 0; l < K; ++l) {
+        if (!tv) s += Pt[l * r + row] * H[l * m + c];
+        s += Pb[l * r + row] * H[K * m + l * m + c];
+      }
     } else {
       const double* Qt = PT(i + 1, 2);
       const double* Qb = PT(i + 1, 3);
       int q = row - r;
-      for (int l = 0; l < K; ++l)
-        s += Qt[l * r + q] * H[2 * K * m + l * m + c] + Qb[l * r + q] * H[3 * K * m + l * m + c];
+      for (int l = 0; l < K; ++l) {
+        s += Qt[l * r + q] * H[2 * K * m + l * m + c];
+        if (!tv) s += Qb[l * r + q] * H[3 * K * m + l * m + c];
+      }
     }
     g[row * mm + c] = s;
   }

@@ -58,7 +58,8 @@ __device__ inline T rhs_at(const SolveArgs& a, const Geom& g, int q, int c, int 
 // Interface tips of the reduced solution: x_{i,t} (top = true) or x_{i,b} of
 // partition i, written as T into X (K x mc, pitch LDM):
 //   x_{i,t} = y_{i,t} - Q_{i,t} c_i - P_{i,t} a_i,   x_{i,b} likewise,
-// with a_i = z_i[0:r] (i <= p-2) and c_i = z_{i-1}[r:2r] (i >= 1).
+// with a_i = z_i[0:r] (i <= p-2) and c_i = z_{i-1}[r:2r] (i >= 1).  LR-SPIKE-T
+// drops the terms of the other interface (P_{i,t} a_i and Q_{i,b} c_i).
 template <typename T, int K>
 __device__ inline void interface_tip(const SolveArgs& a, int i, bool top, int c0, int mc, T* X) {
   constexpr int LDM = mc_of<K>() + 1;
@@ -73,11 +74,11 @@ __device__ inline void interface_tip(const SolveArgs& a, int i, bool top, int c0
     int row = o / mc, c = o % mc;
     double v = yt[row * L.mmax + c0 + c];
     if (r > 0) {
-      if (i <= L.p - 2) {
+      if (i <= L.p - 2 && !(L.variant && top)) {
         const double* av = zg + (size_t)i * L.R2 * L.mmax;  // a_i = first r entries of z_i
         for (int q = 0; q < r; ++q) v -= P[row * r + q] * av[q * L.mmax + c0 + c];
       }
-      if (i >= 1) {
+      if (i >= 1 && !(L.variant && !top)) {
         const double* cv = zg + ((size_t)(i - 1) * L.R2 + r) * L.mmax;  // c_i
         for (int q = 0; q < r; ++q) v -= Q[row * r + q] * cv[q * L.mmax + c0 + c];
       }

@@ -439,11 +439,11 @@ __global__ __launch_bounds__(64) void retrieve_wave_kernel(SolveArgs a) {
       int row = o / mc, c = o % mc;
       double v = yt[row * L.mmax + c0 + c];
       if (r > 0) {
-        if (i <= L.p - 2) {
+        if (i <= L.p - 2 && !(L.variant && top)) {  // (LR-SPIKE-T: own interface only)
           const double* av = zg + (size_t)i * L.R2 * L.mmax;
           for (int q = 0; q < r; ++q) v -= P[row * r + q] * av[q * L.mmax + c0 + c];
         }
-        if (i >= 1) {
+        if (i >= 1 && !(L.variant && !top)) {
           const double* cv = zg + ((size_t)(i - 1) * L.R2 + r) * L.mmax;
           for (int q = 0; q < r; ++q) v -= Q[row * r + q] * cv[q * L.mmax + c0 + c];
         }
