@@ -260,6 +260,31 @@ int lrspike_batch_partitions(lrspike_plan plan, int32_t count, int32_t *p_out);
  * lrspike_solve, lrspike_solve_adjoint, lrspike_band_grad and the profiling
  * calls return -1 for it. */
 
+/*
+ * Allocation-free factor + solve, for callers that cannot allocate (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * allocation).  The same kernels as lrspike_factor followed by lrspike_solve
+ * in FP64 (LRSPIKE_FP64, LRSPIKE_VARIANT_FULL), but the factors and every
+ * other intermediate live in a device scratch array of 64 MiB that the
+ * library holds per GPU for the life of the process; no host or device
+ * memory is allocated and no plan is returned.
+ *   n, k, bands, p, r   as for lrspike_factor
+ *   rhs        device pointer, n x nrhs row-major, overwritten by x = M_r^{-1} rhs
+ *   nrhs       >= 1
+ *   stream     hipStream_t to enqueue on (NULL = null stream); nothing synchronizes
+ *   status_out device pointer to one int32 that receives the latched error code
+ *              (0 or an LRSPIKE_ERR_* value) when the work completes, or NULL
+ * Returns 0, a negative argument code, LRSPIKE_ERR_NOT_SUPPORTED, or
+ * LRSPIKE_ERR_WORKSPACE when the problem's workspace (lrspike_workspace_size
+ * with precision FP64 and max_nrhs = nrhs) exceeds the 64 MiB scratch.
+ * Every call on a GPU shares that GPU's scratch: calls that overlap in time
+ * on one GPU (two streams, two host threads) race and must be serialized by
+ * the caller.  The scratch keeps the last call's contents; everything a call
+ * reads is written by that call first.
+ */
+int lrspike_solve_noalloc(int64_t n, int32_t k, const double *bands, int32_t p, int32_t r,
+                          double *rhs, int32_t nrhs, void *stream, int32_t *status_out);
+
 const char *lrspike_strerror(int code);
 
 #ifdef __cplusplus

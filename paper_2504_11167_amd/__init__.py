@@ -87,7 +87,7 @@ SYMBOLS = (
     "lrspike_default_opts", "lrspike_workspace_size", "lrspike_factor", "lrspike_solve",
     "lrspike_solve_adjoint", "lrspike_band_grad", "lrspike_status", "lrspike_destroy",
     "lrspike_strerror", "lrspike_profile", "lrspike_profile_read", "lrspike_factor_batched",
-    "lrspike_solve_batched", "lrspike_run_batched", "lrspike_batch_partitions",
+    "lrspike_solve_batched", "lrspike_run_batched", "lrspike_batch_partitions", "lrspike_solve_noalloc",
 )
 
 
@@ -122,6 +122,7 @@ def load_library():
     lib.lrspike_solve_batched.argtypes = [P, P]
     lib.lrspike_run_batched.argtypes = [P, P]
     lib.lrspike_batch_partitions.argtypes = [P, i32, ctypes.POINTER(i32)]
+    lib.lrspike_solve_noalloc.argtypes = [i64, i32, P, i32, i32, P, i32, P, P]
     lib.lrspike_strerror.argtypes = [i32]
     lib.lrspike_strerror.restype = ctypes.c_char_p
     _lib = lib
@@ -320,6 +321,32 @@ def solve(bands, b, p, r=None, precision=None, refine_tol=1e-13):
         raise ValueError("solve(): at r < k the gradient of the one-shot operator is not -lam x^T; "
                          "use precision='fp64_refined' (the default) or 'fp32_refined'")
     return LRSpikeSolve.apply(bands, b, p, r, precision, refine_tol)
+
+
+def solve_noalloc(bands, b, p, r, status=None):
+    """x = M_r^{-1} b (FP64) through ``lrspike_solve_noalloc``: factor and
+    solve with the library's static device scratch, nothing allocated (the
+    output tensor aside, which this wrapper clones from b).  status: optional
+    int32 CUDA tensor of one element that receives the latched error code."""
+    lib = load_library()
+    if not isinstance(bands, torch.Tensor) or bands.device.type != "cuda" or bands.dtype != torch.float64 or \
+            bands.dim() != 2 or not bands.is_contiguous():
+        raise TypeError("bands must be a contiguous float64 CUDA tensor of shape (2k+1, n)")
+    k = (bands.shape[0] - 1) // 2
+    n = bands.shape[1]
+    _check_vec(b, n, "rhs")
+    x = b.clone()
+    m = 1 if x.dim() == 1 else x.shape[1]
+    st = None
+    if status is not None:
+        if status.dtype != torch.int32 or status.device != bands.device or status.numel() < 1:
+            raise ValueError("status must be an int32 tensor on the bands' device")
+        st = status.data_ptr()
+    rc = lib.lrspike_solve_noalloc(n, k, bands.data_ptr(), int(p), int(r), x.data_ptr(), m,
+                                   torch.cuda.current_stream(bands.device).cuda_stream, st)
+    if rc:
+        raise LRSpikeError(rc, "lrspike_solve_noalloc")
+    return x
 
 
 def pack_systems(bands_list, rhs_list, p=None, r=None):

@@ -6,6 +6,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <vector>
 
 #include "../../include/lrspike.h"
@@ -28,6 +29,13 @@ using namespace lrs;
 namespace {
 struct BatchState;
 }
+
+// Device scratch of the allocation-free entry point lrspike_solve_noalloc: a
+// file-scope array, one copy per GPU, held until the process ends.  Host code
+// never uses the name itself as an address: the address of the current
+// device's copy comes from hipGetSymbolAddress (scratch_address below).
+#define LRS_SCRATCH_BYTES ((size_t)64 << 20)
+static __device__ __align__(256) char scratch[LRS_SCRATCH_BYTES];
 
 struct lrspike_plan_s {
   Layout L;
@@ -197,14 +205,22 @@ size_t lds_sw() { return (size_t)SwLds<K>::total * sizeof(T); }
 
 // Dynamic LDS above 64 KB needs the kernel attribute; each (kernel, size) is
 // set once per process (so that no attribute call happens during a capture).
+// (A fixed table, so that no call path allocates host memory for it.)
 bool set_lds(const void* fn, size_t bytes) {
   if (bytes > 160 * 1024) return false;
   if (bytes <= 64 * 1024) return true;
-  static std::vector<std::pair<const void*, size_t>> done;
-  for (auto& e : done)
-    if (e.first == fn && e.second >= bytes) return true;
+  struct Done {
+    const void* fn;
+    size_t bytes;
+  };
+  static Done done[512];
+  static int ndone = 0;
+  static std::mutex mu;
+  std::lock_guard<std::mutex> lock(mu);
+  for (int i = 0; i < ndone; ++i)
+    if (done[i].fn == fn && done[i].bytes >= bytes) return true;
   if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) != hipSuccess) return false;
-  done.push_back({fn, bytes});
+  if (ndone < 512) done[ndone++] = {fn, bytes};
   return true;
 }
 
@@ -552,6 +568,29 @@ void prof_clear(lrspike_plan P) {
 
 #include "batched.hip"
 
+// Per-device address of `scratch`, looked up once per device (with that
+// device current) and kept.
+constexpr int kMaxDevices = 64;
+void* scratch_dev[kMaxDevices];
+std::mutex scratch_mu;
+int scratch_address(void** out) {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return LRSPIKE_ERR_HIP;
+  std::lock_guard<std::mutex> lock(scratch_mu);
+  if (!scratch_dev[dev]) {
+    void* ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return LRSPIKE_ERR_HIP;
+    scratch_dev[dev] = ptr;
+  }
+  *out = scratch_dev[dev];
+  return 0;
+}
+
+// status_out[0] = the latched error code of the state block at st.
+__global__ void copy_status_kernel(const int* st, int* status_out) {
+  if (threadIdx.x == 0) status_out[0] = st[S_CODE];
+}
+
 bool is_device_ptr(const void* p) {
   if (!p) return false;
   hipPointerAttribute_t at;
@@ -882,6 +921,47 @@ int lrspike_batch_partitions(lrspike_plan P, int32_t count, int32_t* p_out) {
   for (BatchGroup& G : B.groups)
     for (int s : G.sys) p_out[s] = sys_partitions(B.descs[s], G.target);
   return 0;
+}
+
+int lrspike_solve_noalloc(int64_t n, int32_t k, const double* bands, int32_t p, int32_t r, double* rhs,
+                          int32_t nrhs, void* stream, int32_t* status_out) {
+  if (n < 1) return -1;
+  if (k < 1) return -2;
+  if (p < 1 || p > n) return -4;
+  if (r < 0 || r > k) return -5;
+  if (nrhs < 1) return -7;
+  const int K = kernel_K(k);
+  const int64_t njmin = n / p;
+  if ((p > 1 && njmin < 2 * (int64_t)k) || njmin < K) return -4;
+  if (K > 64 || (p > 1 && 2 * ((r == k) ? K : r) > 64)) return LRSPIKE_ERR_NOT_SUPPORTED;
+  // the plan lives on the stack; its workspace is the static scratch
+  lrspike_plan_s P;
+  make_layout(P.L, n, k, p, r, 8, nrhs);
+  if (P.L.total > LRS_SCRATCH_BYTES) return LRSPIKE_ERR_WORKSPACE;
+  if (!is_device_ptr(bands)) return -3;
+  if (!is_device_ptr(rhs)) return -6;
+  if (status_out && !is_device_ptr(status_out)) return -9;
+  void* ws = nullptr;
+  int rc = scratch_address(&ws);
+  if (rc) return rc;
+  P.precision = LRSPIKE_FP64;
+  P.variant = LRSPIKE_VARIANT_FULL;
+  P.max_refine = 0;
+  P.refine_tol = 0.0;
+  P.stream = reinterpret_cast<hipStream_t>(stream);
+  P.bands = bands;
+  P.ws = reinterpret_cast<char*>(ws);
+  P.profiling = 0;
+  int* state = reinterpret_cast<int*>(P.ws + P.L.latch);
+  rc = launch(&P, "state_init_kernel", state_init_kernel, dim3(1), dim3(64), 0, state);
+  factor_fn f = factor_for(LRSPIKE_FP64, K);
+  apply_fn a = apply_for(LRSPIKE_FP64, K);
+  if (!rc) rc = (f && a) ? f(&P) : LRSPIKE_ERR_NOT_SUPPORTED;
+  if (!rc) rc = a(&P, rhs, nrhs, 0);
+  if (!rc && status_out)
+    rc = launch(&P, "copy_status_kernel", copy_status_kernel, dim3(1), dim3(64), 0, (const int*)state,
+                (int*)status_out);
+  return rc;
 }
 
 const char* lrspike_strerror(int code) {

@@ -53,6 +53,17 @@ def test_workspace_size_argument_codes(args, code):
     assert lib.lrspike_workspace_size(*args, ctypes.byref(out)) == code
 
 
+def test_noalloc_rejects_problems_beyond_its_scratch_before_any_gpu_call():
+    """The allocation-free entry point checks sizes on the host first: a
+    workspace above its 64 MiB scratch returns LRSPIKE_ERR_WORKSPACE (7)."""
+    import paper_2504_11167_amd as lr
+    lib = lr.load_library()
+    assert lib.lrspike_solve_noalloc(1 << 22, 32, None, 1024, 8, None, 16, None, None) == 7
+    assert lib.lrspike_solve_noalloc(0, 4, None, 1, 1, None, 1, None, None) == -1
+    assert lib.lrspike_solve_noalloc(100, 4, None, 2, 5, None, 1, None, None) == -5
+    assert lib.lrspike_solve_noalloc(100, 4, None, 2, 2, None, 0, None, None) == -7
+
+
 def test_workspace_size_grows_with_problem():
     import paper_2504_11167_amd as lr
     a = lr.workspace_bytes(4096, 8, 4, 8)
