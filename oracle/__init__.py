@@ -16,6 +16,8 @@ A plain C implementation of what the banded LR-SPIKE method computes
                       2 x 2 interface blocks (truncated SPIKE).
 * ``band_solve_refined``  x* accurate to about one rounding whatever the
                       condition number (residual in long double).
+* ``bicgstab``        BiCGStab right-preconditioned by the LR-SPIKE operator,
+                      the outer Krylov solver of the paper's experiments.
 * ``reduced_dense``, ``partition_spikes``, ``thin_svd``, ``band_matvec``,
   ``band_grad`` and ``partition`` expose the intermediate objects the pins test.
 
@@ -53,6 +55,8 @@ def _load():
         lib.orc_lrspike.argtypes = [i64, i32, _D, i32, i32, i32, _D, _D, i32, _D, i32, i32]
         lib.orc_reduced_dense.argtypes = [i64, i32, _D, i32, i32, _D]
         lib.orc_partition_spikes.argtypes = [i64, i32, _D, i32, i32, _D, _D]
+        lib.orc_bicgstab.argtypes = [i64, i32, _D, i32, i32, i32, i32, _D, _D, ctypes.c_double, i32, i32,
+                                     ctypes.POINTER(ctypes.c_int), _D, i32]
         lib.orc_band_grad.argtypes = [i64, i32, i32, _D, _D, _D]
         lib.orc_band_grad.restype = None
         _lib = lib
@@ -140,6 +144,22 @@ def lrspike(bands, f, p, r, transpose=False, return_sv=False, threads=0, variant
     _check(rc, "lrspike")
     x = x[:, 0] if flat else x
     return (x, sv) if return_sv else x
+
+
+def bicgstab(bands, f, p, r, tol=1e-13, max_it=200, transpose=False, variant="full", threads=0):
+    """BiCGStab right-preconditioned by the LR-SPIKE operator M_r^{-1} (column by
+    column, x_0 = M^{-1} f).  Returns (x, iterations per column, final relative
+    residual per column)."""
+    bands, n, k = _band_args(bands)
+    f2, flat = _as2d(f)
+    m = f2.shape[1]
+    x = np.empty_like(f2)
+    its = (ctypes.c_int * m)()
+    res = np.zeros(m)
+    rc = _load().orc_bicgstab(n, k, _p(bands), p, r, _VARIANTS[variant], m, _p(f2), _p(x), tol, max_it,
+                              int(transpose), its, _p(res), threads)
+    _check(rc, "bicgstab")
+    return (x[:, 0] if flat else x), list(its), res
 
 
 def reduced_dense(bands, p, r):

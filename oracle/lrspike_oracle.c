@@ -644,6 +644,106 @@ int orc_lrspike(int64_t n, int k, const double *bands, int p, int r, int m,
   return 0;
 }
 
+/*
+ * BiCGStab preconditioned on the right by the LR-SPIKE operator M_r^{-1}
+ * (variant 0 LR-SPIKE, 1 LR-SPIKE-T), the outer Krylov solver the paper pairs
+ * with its preconditioners (table solver-list; the BiCGStab experiments with
+ * SuiteSparse matrices).  The textbook recurrence (van der Vorst), each column
+ * on its own, starting from x_0 = M^{-1} f:
+ *   r = f - A x, rh = r, p = v = 0, rho_old = alpha = omega = 1;
+ *   repeat: rho = (rh, r); beta = (rho / rho_old)(alpha / omega);
+ *           p = r + beta (p - omega v); ph = M^{-1} p; v = A ph;
+ *           alpha = rho / (rh, v); s = r - alpha v; sh = M^{-1} s; t = A sh;
+ *           omega = (t, s) / (t, t)  (0 when t = 0);
+ *           x += alpha ph + omega sh; r = s - omega t; rho_old = rho
+ *   until ||r||_2 <= tol ||f||_2 or max_it iterations.  transpose = 1 solves
+ *   A^T x = f with M_r^{-T}.  iters[c] receives the iterations of column c
+ *   and relres[c] its final ||r|| / ||f|| (the recursively updated residual).
+ */
+static double col_dot(int64_t n, int m, int c, const double *a, const double *b) {
+  double s = 0.0;
+  for (int64_t i = 0; i < n; ++i) s += a[i * m + c] * b[i * m + c];
+  return s;
+}
+
+int orc_bicgstab(int64_t n, int k, const double *bands, int p, int r, int variant, int m,
+                 const double *f, double *x, double tol, int max_it, int transpose,
+                 int *iters, double *relres, int nthreads) {
+  if (m < 1 || max_it < 0) return -7;
+  if (variant != 0 && variant != 1) return -6;
+  orc_plan P;
+  int rc = plan_build(&P, n, k, bands, p, r, variant, nthreads);
+  if (rc) return rc;
+  size_t nm = (size_t)(n * m);
+  double *rv = (double *)malloc(sizeof(double) * nm), *rh = (double *)malloc(sizeof(double) * nm);
+  double *pv = (double *)calloc(nm, sizeof(double)), *vv = (double *)calloc(nm, sizeof(double));
+  double *ph = (double *)malloc(sizeof(double) * nm), *sv = (double *)malloc(sizeof(double) * nm);
+  double *sh = (double *)malloc(sizeof(double) * nm), *tv = (double *)malloc(sizeof(double) * nm);
+  double *col = (double *)malloc(sizeof(double) * (size_t)n);
+  double *col2 = (double *)malloc(sizeof(double) * (size_t)n);
+  /* the preconditioner and the matrix are applied column by column */
+  void (*Msolve)(orc_plan *, int, const double *, double *) = transpose ? plan_solve_t : plan_solve;
+#define APPLY_M(src, dst, c)                                               \
+  do {                                                                     \
+    for (int64_t i_ = 0; i_ < n; ++i_) col[i_] = (src)[i_ * m + (c)];      \
+    Msolve(&P, 1, col, col2);                                              \
+    for (int64_t i_ = 0; i_ < n; ++i_) (dst)[i_ * m + (c)] = col2[i_];     \
+  } while (0)
+#define APPLY_A(src, dst, c)                                               \
+  do {                                                                     \
+    for (int64_t i_ = 0; i_ < n; ++i_) col[i_] = (src)[i_ * m + (c)];      \
+    orc_band_matvec(n, k, bands, 1, col, col2, transpose);                 \
+    for (int64_t i_ = 0; i_ < n; ++i_) (dst)[i_ * m + (c)] = col2[i_];     \
+  } while (0)
+  for (int c = 0; c < m; ++c) {
+    APPLY_M(f, x, c);
+    APPLY_A(x, rv, c);
+    for (int64_t i = 0; i < n; ++i) {
+      rv[i * m + c] = f[i * m + c] - rv[i * m + c];
+      rh[i * m + c] = rv[i * m + c];
+    }
+    double nf = sqrt(col_dot(n, m, c, f, f));
+    double rho_old = 1.0, alpha = 1.0, omega = 1.0;
+    int it = 0;
+    double nr = sqrt(col_dot(n, m, c, rv, rv));
+    while (it < max_it && !(nr <= tol * nf)) {
+      double rho = col_dot(n, m, c, rh, rv);
+      double beta = (rho / rho_old) * (alpha / omega);
+      for (int64_t i = 0; i < n; ++i) {
+        size_t o = (size_t)(i * m + c);
+        pv[o] = rv[o] + beta * (pv[o] - omega * vv[o]);
+      }
+      APPLY_M(pv, ph, c);
+      APPLY_A(ph, vv, c);
+      alpha = rho / col_dot(n, m, c, rh, vv);
+      for (int64_t i = 0; i < n; ++i) {
+        size_t o = (size_t)(i * m + c);
+        sv[o] = rv[o] - alpha * vv[o];
+      }
+      APPLY_M(sv, sh, c);
+      APPLY_A(sh, tv, c);
+      double tt = col_dot(n, m, c, tv, tv);
+      omega = tt > 0.0 ? col_dot(n, m, c, tv, sv) / tt : 0.0;
+      for (int64_t i = 0; i < n; ++i) {
+        size_t o = (size_t)(i * m + c);
+        x[o] += alpha * ph[o] + omega * sh[o];
+        rv[o] = sv[o] - omega * tv[o];
+      }
+      rho_old = rho;
+      ++it;
+      nr = sqrt(col_dot(n, m, c, rv, rv));
+      if (!(rho != 0.0 && omega != 0.0) && !(nr <= tol * nf)) break; /* breakdown */
+    }
+    if (iters) iters[c] = it;
+    if (relres) relres[c] = nf > 0.0 ? nr / nf : 0.0;
+  }
+#undef APPLY_M
+#undef APPLY_A
+  free(rv); free(rh); free(pv); free(vv); free(ph); free(sv); free(sh); free(tv); free(col); free(col2);
+  plan_free(&P);
+  return 0;
+}
+
 /* The dense reduced system S~_red (order 2kp, row-major) at rank r. */
 int orc_reduced_dense(int64_t n, int k, const double *bands, int p, int r, double *S) {
   orc_plan P;

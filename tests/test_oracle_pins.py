@@ -563,3 +563,58 @@ def test_argument_errors():
         oracle.lrspike(bands, f, 6, 4)  # n_j = 6 < 2k
     with pytest.raises(oracle.OracleError):
         oracle.lrspike(bands, f, 2, 5)  # r > k
+
+
+# ---------------------------------------------------------------- BiCGStab (outer Krylov solver)
+
+
+@pytest.mark.parametrize("variant,transpose", [("full", False), ("t", False), ("full", True)])
+@pytest.mark.parametrize("iters", [1, 3])
+def test_bicgstab_iterates_match_scipy(variant, transpose, iters):
+    """The oracle's preconditioned BiCGStab against scipy's independent
+    implementation of the same recurrence (right preconditioner, same x_0),
+    iterate by iterate, on a non-dominant matrix where the iterates are far
+    from converged."""
+    import scipy.sparse.linalg as sl
+    n, k, p, r = 1500, 5, 3, 2
+    bands, f = synth.make_problem(n, k, 1, seed=31, rule="theta", theta=0.4)
+    f = f[:, 0]
+    x_or, its, _ = oracle.bicgstab(bands, f, p, r, tol=0.0, max_it=iters, transpose=transpose, variant=variant)
+    assert its == [iters]
+    A = sl.LinearOperator((n, n), matvec=lambda v: oracle.band_matvec(bands, v.reshape(-1), transpose=transpose))
+    M = sl.LinearOperator((n, n), matvec=lambda v: oracle.lrspike(bands, v.reshape(-1), p, r, transpose=transpose,
+                                                                  variant=variant))
+    x0 = oracle.lrspike(bands, f, p, r, transpose=transpose, variant=variant)
+    x_sp, _ = sl.bicgstab(A, f, x0=x0.copy(), rtol=1e-300, atol=0.0, maxiter=iters, M=M)
+    assert rel(x_or, x_sp) < 1e-12
+    assert rel(x_or, oracle.band_solve(bands, f, transpose=transpose)) > 1e-9  # not converged yet
+
+
+def test_bicgstab_exact_preconditioner_converges_at_once():
+    """At r = k the preconditioner is A^{-1} (LR-SPIKE is exact): x_0 already
+    solves the system and at most one iteration is taken."""
+    bands, f = synth.make_problem(3000, 8, 2, seed=32, rule="weak")
+    x, its, res = oracle.bicgstab(bands, f, 4, 8, tol=1e-13)
+    assert max(its) <= 1 and max(res) <= 1e-13
+    assert rel(x, oracle.band_solve(bands, f)) < 1e-13
+
+
+def test_bicgstab_converges_where_refinement_does_not():
+    """Non-dominant matrix, strongly truncated spikes: I - M_r^{-1} A is not a
+    contraction (the plain refinement iteration x += M^{-1}(f - A x) grows),
+    yet BiCGStab reaches A^{-1} f, for both reduced-system variants."""
+    n, k, p, r = 4096, 8, 8, 2
+    bands, f = synth.make_problem(n, k, 2, seed=33, rule="theta", theta=0.15)
+    xs = oracle.band_solve_refined(bands, f, steps=3)
+    x = oracle.lrspike(bands, f, p, r)
+    errs = []
+    for _ in range(4):
+        x = x + oracle.lrspike(bands, f - oracle.band_matvec(bands, x), p, r)
+        errs.append(rel(x, xs))
+    assert errs[-1] > errs[0]  # refinement diverges here
+    for variant in ("full", "t"):
+        xb, its, res = oracle.bicgstab(bands, f, p, r, tol=1e-13, max_it=300, variant=variant)
+        assert max(res) <= 1e-13
+        assert rel(xb, xs) < 1e-9
+        true_res = np.linalg.norm(f - oracle.band_matvec(bands, xb), axis=0) / np.linalg.norm(f, axis=0)
+        assert true_res.max() < 1e-12
