@@ -47,9 +47,17 @@ enum {
   LRSPIKE_FP64 = 0,         /* factors, spikes and sweeps in FP64; one application of M_r^{-1} */
   LRSPIKE_FP32_REFINED = 1, /* FP32 factors/spikes/sweeps; FP64 reduced system,
                                residual and update in iterative refinement */
-  LRSPIKE_FP64_REFINED = 2  /* FP64 factors; M_r^{-1} as the preconditioner of an iterative
+  LRSPIKE_FP64_REFINED = 2, /* FP64 factors; M_r^{-1} as the preconditioner of an iterative
                                refinement with FP64 residual: x = A^{-1} rhs to refine_tol for
                                any r (and A^{-T} for the adjoint) */
+  LRSPIKE_FP64_BICGSTAB = 3, /* FP64 factors; M_r^{-1} as the right preconditioner of BiCGStab
+                               (the outer Krylov solver of table solver-list), FP64 vectors and
+                               inner products, per-column iterations: x = A^{-1} rhs until
+                               ||rhs - A x||_2 <= refine_tol ||rhs||_2 for every column, for
+                               systems where refinement does not contract (non-dominant A,
+                               small r); the adjoint runs the same iteration on A^T with M_r^{-T}.
+                               max_refine caps the iterations.  Not for batched plans */
+  LRSPIKE_FP32_BICGSTAB = 4  /* the same with FP32 factors behind M_r^{-1} */
 };
 
 /* Reduced interface system (the variant table of section "Selected LR-SPIKE

@@ -24,8 +24,9 @@ from . import build as _build
 __all__ = ["factor", "solve", "Plan", "BatchedPlan", "factor_batched", "pack_systems", "LRSpikeError",
            "library_path", "load_library"]
 
-FP64, FP32_REFINED, FP64_REFINED = 0, 1, 2
-_PRECISIONS = {"fp64": FP64, "fp32_refined": FP32_REFINED, "fp64_refined": FP64_REFINED}
+FP64, FP32_REFINED, FP64_REFINED, FP64_BICGSTAB, FP32_BICGSTAB = 0, 1, 2, 3, 4
+_PRECISIONS = {"fp64": FP64, "fp32_refined": FP32_REFINED, "fp64_refined": FP64_REFINED,
+               "fp64_bicgstab": FP64_BICGSTAB, "fp32_bicgstab": FP32_BICGSTAB}
 VARIANT_FULL, VARIANT_T = 0, 1
 _VARIANTS = {"full": VARIANT_FULL, "t": VARIANT_T}
 _ERRORS = {
@@ -271,7 +272,9 @@ class Plan:
 
 def factor(bands, p, r, precision="fp64", max_nrhs=32, **kw):
     """Factor A (bands: (2k+1, n) float64 CUDA tensor) into p partitions at rank r.
-    precision: "fp64", "fp32_refined" or "fp64_refined"; variant: "full" (LR-SPIKE) or "t" (LR-SPIKE-T)."""
+    precision: "fp64" (one application of M_r^{-1}), "fp32_refined" / "fp64_refined" (iterative
+    refinement preconditioned by M_r^{-1}) or "fp64_bicgstab" / "fp32_bicgstab" (BiCGStab
+    right-preconditioned by M_r^{-1}); variant: "full" (LR-SPIKE) or "t" (LR-SPIKE-T)."""
     return Plan(bands, p, r, precision=precision, max_nrhs=max_nrhs, **kw)
 
 

@@ -23,6 +23,7 @@ struct RedArgs;
 #include "solve.hip"
 #include "factor_wave.hip"
 #include "factor_lds.hip"
+#include "krylov.hip"
 
 using namespace lrs;
 
@@ -488,6 +489,72 @@ int run_refined(lrspike_plan P, double* rhs, int m, int transpose) {
   return 0;
 }
 
+// BiCGStab preconditioned by the plan's M_r^{-1} (M_r^{-T} for the adjoint,
+// which then runs on A^T): x_0 = M^{-1} b, then the iteration of krylov.hip,
+// every kernel gated by the device stopping rule; like run_refined, eager
+// solves enqueue one iteration ahead of the stop flag they read back, and a
+// captured solve records all max_refine iterations.
+template <typename T, int K>
+int run_bicgstab(lrspike_plan P, double* rhs, int m, int transpose) {
+  const Layout& L = P->L;
+  hipStream_t st = P->stream;
+  const int64_t nm = L.n * (int64_t)m;
+  double* b = reinterpret_cast<double*>(P->ws + L.fcopy);
+  double* r = reinterpret_cast<double*>(P->ws + L.res);
+  double* vec = reinterpret_cast<double*>(P->ws + L.bvec);
+  double *rh = vec, *pv = vec + nm, *vv = vec + 2 * nm, *ph = vec + 3 * nm, *sv = vec + 4 * nm, *sh = vec + 5 * nm,
+         *tv = vec + 6 * nm;
+  int* state = reinterpret_cast<int*>(P->ws + L.latch);
+  const int* gate = state + S_STOP;
+  BicgArgs ba{L.n, m, m, L.bblk, reinterpret_cast<double*>(P->ws + L.bsc), reinterpret_cast<double*>(P->ws + L.bpart),
+              gate, L.mmax};
+  hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(st, &cap) != hipSuccess) return LRSPIKE_ERR_HIP;
+  const bool capturing = cap != hipStreamCaptureStatusNone;
+  if (hipMemcpyAsync(b, rhs, nm * 8, hipMemcpyDeviceToDevice, st) != hipSuccess) return LRSPIKE_ERR_HIP;
+  LRS_LAUNCH("refine_reset_kernel", refine_reset_kernel, dim3(1), dim3(256), 0, state,
+             reinterpret_cast<double*>(P->ws + L.norms), L.nsys * L.mmax);
+  int rc = run_apply<T, K>(P, rhs, m, transpose);
+  if (rc) return rc;
+  const size_t bres = (size_t)(RES_ROWS + 2 * L.k) * (RES_MC + 1) * 8;
+  if (!set_lds((const void*)residual_kernel, bres)) return LRSPIKE_ERR_NOT_SUPPORTED;
+  const size_t bmv = (size_t)(BICG_TPB + 2 * L.k) * (BICG_MC + 1) * 8;
+  if (!set_lds((const void*)bicg_matvec_kernel, bmv)) return LRSPIKE_ERR_NOT_SUPPORTED;
+  LRS_LAUNCH("residual_kernel", residual_kernel, dim3((unsigned)((L.n + RES_ROWS - 1) / RES_ROWS)), dim3(RES_ROWS),
+             bres, P->bands, L.n, L.k, (const double*)b, (const double*)rhs, r, m, m, transpose, gate);
+  const dim3 gv(L.bblk), tb(BICG_TPB), gc(m);
+  LRS_LAUNCH("bicg_start_kernel", bicg_start_kernel, gv, tb, 0, ba, (const double*)b, (const double*)r, rh, pv, vv);
+  LRS_LAUNCH("bicg_reduce_kernel", bicg_reduce_kernel, gc, tb, 0, ba, 2, (int)BS_RR, (int)BS_BB, 0);
+  LRS_LAUNCH("bicg_init_kernel", bicg_init_kernel, dim3(1), dim3(BICG_TPB), 0, ba, state, P->refine_tol);
+  for (int it = 0; it < P->max_refine; ++it) {
+    LRS_LAUNCH("bicg_p_kernel", bicg_p_kernel, gv, tb, 0, ba, (const double*)r, pv, (const double*)vv, ph);
+    if ((rc = run_apply<T, K>(P, ph, m, transpose, gate))) return rc;
+    LRS_LAUNCH("bicg_matvec_kernel", bicg_matvec_kernel, gv, tb, bmv, ba, P->bands, L.k, (const double*)ph, vv,
+               (const double*)rh, 1, transpose);
+    LRS_LAUNCH("bicg_reduce_kernel", bicg_reduce_kernel, gc, tb, 0, ba, 1, (int)BS_RV, 0, 0);
+    LRS_LAUNCH("bicg_s_kernel", bicg_s_kernel, gv, tb, 0, ba, (const double*)r, (const double*)vv, sv, sh);
+    if ((rc = run_apply<T, K>(P, sh, m, transpose, gate))) return rc;
+    LRS_LAUNCH("bicg_matvec_kernel", bicg_matvec_kernel, gv, tb, bmv, ba, P->bands, L.k, (const double*)sh, tv,
+               (const double*)sv, 2, transpose);
+    LRS_LAUNCH("bicg_reduce_kernel", bicg_reduce_kernel, gc, tb, 0, ba, 2, (int)BS_TS, (int)BS_TT, 0);
+    LRS_LAUNCH("bicg_x_kernel", bicg_x_kernel, gv, tb, 0, ba, rhs, r, (const double*)rh, (const double*)ph,
+               (const double*)sv, (const double*)sh, (const double*)tv);
+    LRS_LAUNCH("bicg_reduce_kernel", bicg_reduce_kernel, gc, tb, 0, ba, 2, (int)BS_RHO_NEXT, (int)BS_RR, 0);
+    LRS_LAUNCH("bicg_ctl_kernel", bicg_ctl_kernel, dim3(1), dim3(BICG_TPB), 0, ba, state, P->refine_tol, it,
+               P->max_refine);
+    if (capturing) continue;
+    int* slot = P->hstate + 4 * (it & 1);
+    if (hipMemcpyAsync(slot, state + S_STOP, 4, hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipEventRecord(P->hev[it & 1], st) != hipSuccess)
+      return LRSPIKE_ERR_HIP;
+    if (it >= 1) {
+      if (hipEventSynchronize(P->hev[(it - 1) & 1]) != hipSuccess) return LRSPIKE_ERR_HIP;
+      if (P->hstate[4 * ((it - 1) & 1)] != 0) break;  // stopped: this iteration was a no-op
+    }
+  }
+  return 0;
+}
+
 typedef int (*factor_fn)(lrspike_plan);
 typedef int (*apply_fn)(lrspike_plan, double*, int, int);
 
@@ -511,30 +578,37 @@ factor_fn pick_factor(int K) {
   return nullptr;
 }
 
-template <typename T, bool REF>
+// OUTER: 0 one application, 1 iterative refinement, 2 BiCGStab
+template <typename T, int OUTER>
 apply_fn pick_apply(int K) {
+#define LRS_APPLY(KK) \
+  case KK: return OUTER == 0 ? run_plain<T, KK> : (OUTER == 1 ? run_refined<T, KK> : run_bicgstab<T, KK>);
   switch (K) {
-    case 1: return REF ? run_refined<T, 1> : run_plain<T, 1>;
-    case 2: return REF ? run_refined<T, 2> : run_plain<T, 2>;
-    case 4: return REF ? run_refined<T, 4> : run_plain<T, 4>;
-    case 8: return REF ? run_refined<T, 8> : run_plain<T, 8>;
-    case 16: return REF ? run_refined<T, 16> : run_plain<T, 16>;
-    case 32: return REF ? run_refined<T, 32> : run_plain<T, 32>;
-    case 64: return REF ? run_refined<T, 64> : run_plain<T, 64>;
+    LRS_APPLY(1)
+    LRS_APPLY(2)
+    LRS_APPLY(4)
+    LRS_APPLY(8)
+    LRS_APPLY(16)
+    LRS_APPLY(32)
+    LRS_APPLY(64)
   }
+#undef LRS_APPLY
   return nullptr;
 }
 
-bool prec_valid(int prec) {
-  return prec == LRSPIKE_FP64 || prec == LRSPIKE_FP32_REFINED || prec == LRSPIKE_FP64_REFINED;
+bool prec_valid(int prec) { return prec >= LRSPIKE_FP64 && prec <= LRSPIKE_FP32_BICGSTAB; }
+int prec_tsize(int prec) { return (prec == LRSPIKE_FP32_REFINED || prec == LRSPIKE_FP32_BICGSTAB) ? 4 : 8; }
+// 0 one application of M, 1 iterative refinement, 2 BiCGStab
+int prec_refined(int prec) {
+  if (prec == LRSPIKE_FP64) return 0;
+  return (prec == LRSPIKE_FP64_BICGSTAB || prec == LRSPIKE_FP32_BICGSTAB) ? 2 : 1;
 }
-int prec_tsize(int prec) { return prec == LRSPIKE_FP32_REFINED ? 4 : 8; }
-int prec_refined(int prec) { return prec != LRSPIKE_FP64; }
 factor_fn factor_for(int prec, int K) { return prec_tsize(prec) == 8 ? pick_factor<double>(K) : pick_factor<float>(K); }
 apply_fn apply_for(int prec, int K) {
-  if (prec == LRSPIKE_FP64) return pick_apply<double, false>(K);
-  if (prec == LRSPIKE_FP64_REFINED) return pick_apply<double, true>(K);
-  return pick_apply<float, true>(K);
+  const int outer = prec_refined(prec);
+  if (prec_tsize(prec) == 8)
+    return outer == 0 ? pick_apply<double, 0>(K) : (outer == 1 ? pick_apply<double, 1>(K) : pick_apply<double, 2>(K));
+  return outer == 1 ? pick_apply<float, 1>(K) : pick_apply<float, 2>(K);
 }
 
 // Pinned host slots and events of the eager refinement loop (refined plans).
@@ -645,6 +719,7 @@ int lrspike_factor(int64_t n, int32_t k, const double* bands, int32_t p, int32_t
   if (!prec_valid(opts->precision)) return -6;
   if (opts->variant != LRSPIKE_VARIANT_FULL && opts->variant != LRSPIKE_VARIANT_T) return -6;
   if (opts->max_nrhs < 1) return -6;
+  if (prec_refined(opts->precision) == 2 && opts->max_nrhs > BICG_TPB) return -6;  // one thread per column
   if (K > 64) return LRSPIKE_ERR_NOT_SUPPORTED;
   // reduced-system blocks of order 2r are inverted in one workgroup's LDS
   if (p > 1 && 2 * ((r == k) ? K : r) > 64) return LRSPIKE_ERR_NOT_SUPPORTED;
@@ -825,7 +900,7 @@ int lrspike_factor_batched(int32_t count, const lrspike_batch_desc* descs, const
   if (!is_device_ptr(bands_base)) return -3;
   if (!opts) return -4;
   if (!plan_out) return -5;
-  if (!prec_valid(opts->precision)) return -4;
+  if (!prec_valid(opts->precision) || prec_refined(opts->precision) == 2) return -4;  // no BiCGStab for batches
   for (int s = 0; s < count; ++s) {
     const lrspike_batch_desc& d = descs[s];
     if (d.n < 1 || d.k < 1 || d.r < 0 || d.r > d.k || d.nrhs < 1 || d.p < 0 || d.p > d.n || d.band_offset < 0 ||

@@ -38,6 +38,11 @@ struct Layout {
   // scratch n x mmax (adjoint D-stage), refinement copy of f and residual n x mmax,
   // norms [nsys][mmax][2]
   size_t ytip, zg, scr, fcopy, res, norms;
+  // BiCGStab (refined == 2): vectors rh, p, v, ph, s, sh, t (n x mmax each),
+  // per-column scalars [mmax][BICG_SCALARS] and per-workgroup partial inner
+  // products [bblk][mmax][3] (bblk workgroups cover the rows)
+  size_t bvec, bsc, bpart;
+  int bblk;
   size_t npv;    // int32[p]: partition needs the interchanging factorization
   size_t latch;  // device state block (STATE_BYTES): error latch, diagnostics, refinement control
   size_t total;
@@ -49,6 +54,7 @@ struct Layout {
 //   diagnostics kept by atomic min / max on the bit patterns of non-negative
 //   doubles (ordered like the values), initialised to +inf (min) or 0 (max)
 constexpr int STATE_INTS = 64;
+constexpr int BICG_SCALARS = 12;  // per-column scalars of the BiCGStab iteration
 constexpr size_t STATE_BYTES = STATE_INTS * 4;
 enum StateSlot {
   S_CODE = 0, S_PART = 1, S_ROW = 2,  // S_ROW: int64 over slots 2, 3
@@ -75,7 +81,8 @@ inline int kernel_K(int k) {
 
 // offs_host / offs_dev: explicit partition offsets (p + 1 entries, host and
 // device copies) or null for the uniform partition rule
-// refined: the plan iterates the solve (residual and correction buffers);
+// refined: the plan iterates the solve: 1 = iterative refinement (residual and
+// correction buffers), 2 = BiCGStab (also its vectors, scalars and partials);
 // variant: 0 = LR-SPIKE with the whole reduced system, 1 = its truncated form;
 // nsys / psys: systems held and the partition -> system slot map (batches)
 inline void make_layout(Layout& L, int64_t n, int k, int p, int r, int tsize, int mmax, int refined = 0,
@@ -145,6 +152,13 @@ inline void make_layout(Layout& L, int64_t n, int k, int p, int r, int tsize, in
   L.fcopy = take(refined ? (size_t)n * mmax * 8 : 0);
   L.res = take(refined ? (size_t)n * mmax * 8 : 0);  // residual / correction (refinement)
   L.norms = take((size_t)2 * nsys * mmax * 8 + 64);
+  {
+    const int64_t blocks = (n + 2047) / 2048;
+    L.bblk = (int)(blocks < 4096 ? blocks : 4096);
+  }
+  L.bvec = take(refined == 2 ? (size_t)7 * n * mmax * 8 : 0);
+  L.bsc = take(refined == 2 ? (size_t)mmax * BICG_SCALARS * 8 : 0);
+  L.bpart = take(refined == 2 ? (size_t)L.bblk * mmax * 3 * 8 : 0);
   L.npv = take((size_t)p * 4);
   L.latch = take(STATE_BYTES);
   L.total = o;
