@@ -43,7 +43,7 @@ def test_default_opts_and_strerror():
     ((100, 4, 2, 5, 0, 1), -4),
     ((100, 4, 2, -1, 0, 1), -4),
     ((100, 4, 2, 2, 7, 1), -5),
-    ((100, 4, 2, 2, 3, 1), -5),
+    ((100, 4, 2, 2, 5, 1), -5),
     ((100, 4, 2, 2, 0, 0), -6),
 ])
 def test_workspace_size_argument_codes(args, code):
