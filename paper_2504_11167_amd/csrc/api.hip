@@ -398,24 +398,19 @@ int run_apply(lrspike_plan P, double* rhs, int m, int transpose, const int* gate
   dim3 grid(L.p, (m + mc_of<K>() - 1) / mc_of<K>());
   size_t bs = lds_sw<T, K>();
   int rc;
-  if (!transpose && K >= 16 && K <= 32 && P->wave) {
-    // matrix-core sweeps: one wave per partition and column chunk
+  // (the matrix-core sweeps address a partition's rows with 32-bit byte offsets)
+  const bool rows31 = (int64_t)L.nbmax * L.K * m * 8 < ((int64_t)1 << 31);
+  if (!transpose && K >= 16 && K <= 32 && P->wave && rows31) {
+    // matrix-core sweeps: one wave per partition and chunk of 16 columns (one
+    // accumulator tile wide, which leaves the registers for the prefetch ring)
     if constexpr (K >= 16 && K <= 32) {
-      const bool one = m <= 16;
-      dim3 gw(L.p, one ? 1 : (m + 31) / 32);
-      const size_t bw = one ? (size_t)WaveSweep<T, K, 1>::total * sizeof(T) + 2 * K * sizeof(int)
-                            : (size_t)WaveSweep<T, K, 2>::total * sizeof(T) + 2 * K * sizeof(int);
+      dim3 gw(L.p, (m + 15) / 16);
+      const size_t bw = (size_t)WaveSweep<T, K, 1>::total * sizeof(T) + 2 * K * sizeof(int);
       if (L.p > 1) {
-        if (one)
-          LRS_LAUNCH("dstage_kernel", dstage_wave_kernel<T, K, 1>, gw, dim3(64), bw, sa);
-        else
-          LRS_LAUNCH("dstage_kernel", dstage_wave_kernel<T, K, 2>, gw, dim3(64), bw, sa);
+        LRS_LAUNCH("dstage_kernel", dstage_wave_kernel<T, K, 1>, gw, dim3(64), bw, sa);
         if ((rc = run_reduced<K>(P, m, 0, gate))) return rc;
       }
-      if (one)
-        LRS_LAUNCH("retrieve_kernel", retrieve_wave_kernel<T, K, 1>, gw, dim3(64), bw, sa);
-      else
-        LRS_LAUNCH("retrieve_kernel", retrieve_wave_kernel<T, K, 2>, gw, dim3(64), bw, sa);
+      LRS_LAUNCH("retrieve_kernel", retrieve_wave_kernel<T, K, 1>, gw, dim3(64), bw, sa);
     }
   } else if (!transpose) {
     if (!set_lds((const void*)dstage_kernel<T, K>, bs) || !set_lds((const void*)retrieve_kernel<T, K>, bs))

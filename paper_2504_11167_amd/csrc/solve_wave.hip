@@ -71,6 +71,33 @@ __device__ __forceinline__ void load_strip(typename WaveSweep<T, K, MCT>::V (&st
       }
 }
 
+// strip -= the interface corrections of its rows (rows in the first K and the
+// last K real rows of the partition); callers skip blocks without such rows
+template <typename T, int K, int MCT>
+__device__ __forceinline__ void sub_corr(typename WaveSweep<T, K, MCT>::V (&st)[K / 16][MCT], const Geom& g, int R,
+                                         const T* Ct, const T* Cb) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int t = 0; t < K / 16; ++t)
+#pragma unroll
+    for (int ct = 0; ct < MCT; ++ct)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int row = 16 * t + acc_row<T>(lane, v), col = 16 * ct + (lane & 15);
+        const int lr = R * K + row - g.pad;
+        if (lr >= 0 && lr < g.nj) {
+          if (Ct && lr < K) st[t][ct][v] -= Ct[lr * (16 * MCT) + col];
+          if (Cb && lr >= g.nj - K) st[t][ct][v] -= Cb[(lr - (g.nj - K)) * (16 * MCT) + col];
+        }
+      }
+}
+
+// does block R hold rows that take an interface correction?
+__device__ __forceinline__ bool corr_block(const Geom& g, int K, int R) {
+  const int lo = R * K - g.pad, hi = lo + K - 1;
+  return lo < K || hi >= g.nj - K;
+}
+
 template <typename T, int K, int MCT>
 __device__ __forceinline__ void store_strip(const typename WaveSweep<T, K, MCT>::V (&st)[K / 16][MCT],
                                             double* dst, int64_t ld, const Geom& g, int R, int c0,
@@ -212,58 +239,138 @@ __device__ __forceinline__ void zero_strip(typename WaveSweep<T, K, MCT>::V (&st
     for (int ct = 0; ct < MCT; ++ct) st[t][ct] = typename WaveSweep<T, K, MCT>::V{0, 0, 0, 0};
 }
 
+// Prefetch distance of the sweeps in blocks: the records and right-hand-side
+// rows of block b + PD are requested while block b is processed.  With one
+// wave per partition the chain of one block does not cover the memory
+// latency; the short blocks at K = 16 take the deeper ring (at most 63 loads
+// may be outstanding per wave; a K = 16 block issues about a dozen).
+template <int K, int MCT>
+constexpr int sweep_pd() { return (K <= 16 && MCT == 1) ? 4 : 2; }
+
+// Calls f(std::integral_constant<int, u>) for u = 0 .. N-1.
+template <int N, int U = 0, typename F>
+__device__ __forceinline__ void static_for(F&& f) {
+  if constexpr (U < N) {
+    f(std::integral_constant<int, U>{});
+    static_for<N, U + 1>(f);
+  }
+}
+
+// Right-hand-side rows of one partition through a buffer descriptor whose
+// range is the partition's rows: an element outside the partition or the
+// column range gets an offset past the range, so its load returns 0 and its
+// store is dropped by the hardware.  No element needs a branch, every load is
+// issued unconditionally, and the wait counts stay exact across the
+// unrolled block loop.  (The host keeps rows x ld x 8 below 2^31.)
+typedef unsigned int lrs_u32x2 __attribute__((ext_vector_type(2)));
+struct RowBuf {
+  __amdgpu_buffer_rsrc_t rs;
+  int ld, nj, pad, mcol;  // mcol: columns of this chunk (c < mcol valid)
+};
+__device__ __forceinline__ RowBuf row_buf(const double* base, const Geom& g, int64_t ld, int c0, int m) {
+  RowBuf rb;
+  rb.rs = __builtin_amdgcn_make_buffer_rsrc((void*)(base + g.s * ld + c0), 0, (int)((int64_t)g.nj * ld * 8),
+                                            0x00020000);
+  rb.ld = (int)ld;
+  rb.nj = g.nj;
+  rb.pad = g.pad;
+  rb.mcol = m - c0;
+  return rb;
+}
+__device__ __forceinline__ int row_off(const RowBuf& rb, int lr, int col) {
+  return (lr >= 0 && lr < rb.nj && col < rb.mcol) ? (lr * rb.ld + col) * 8 : 0x7FFFFFF8;
+}
+template <typename T, int K, int MCT>
+__device__ __forceinline__ void buf_load_strip(typename WaveSweep<T, K, MCT>::V (&st)[K / 16][MCT], const RowBuf& rb,
+                                               int R) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int t = 0; t < K / 16; ++t)
+#pragma unroll
+    for (int ct = 0; ct < MCT; ++ct)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int row = 16 * t + acc_row<T>(lane, v), col = 16 * ct + (lane & 15);
+        const lrs_u32x2 raw = __builtin_amdgcn_raw_buffer_load_b64(rb.rs, row_off(rb, R * K + row - rb.pad, col), 0, 0);
+        st[t][ct][v] = (T)__builtin_bit_cast(double, raw);
+      }
+}
+template <typename T, int K, int MCT>
+__device__ __forceinline__ void buf_store_strip(const typename WaveSweep<T, K, MCT>::V (&st)[K / 16][MCT],
+                                                const RowBuf& rb, int R) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int t = 0; t < K / 16; ++t)
+#pragma unroll
+    for (int ct = 0; ct < MCT; ++ct)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int row = 16 * t + acc_row<T>(lane, v), col = 16 * ct + (lane & 15);
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(lrs_u32x2, (double)st[t][ct][v]), rb.rs,
+                                              row_off(rb, R * K + row - rb.pad, col), 0, 0);
+      }
+}
+
 // Forward pass L^{-1} P^T over the partition (rhs minus optional corrections).
 // DSTAGE: accumulate y_t = G^T z and write y_b, y_t to the tip buffer;
-// otherwise z is written to a.dst.
-template <typename T, int K, int MCT, bool DSTAGE>
-__device__ void fwd_wave(const SolveArgs& a, const Geom& g, int j, int c0, T* lds, const T* Ct,
-                         const T* Cb) {
+// otherwise z is written to a.dst.  The per-block data live in rings of
+// NS = PD + 1 register slots, block b in slot b mod NS; the block loop is
+// unrolled NS times so that every slot index is a compile-time constant, and
+// every prefetch is issued unconditionally (a block past the end re-reads the
+// last one).  SWP: the partition was factored with interchanges (block
+// flags, permutations and side-slot factors are read); without it no flag is
+// read at all.
+template <typename T, int K, int MCT, bool DSTAGE, bool SWP>
+__device__ void fwd_wave_impl(const SolveArgs& a, const Geom& g, int j, int c0, T* lds, const T* Ct, const T* Cb) {
   using W = WaveSweep<T, K, MCT>;
   using V = typename W::V;
-  constexpr int NF = W::RT * W::KS;
+  constexpr int NF = W::RT * W::KS, PD = sweep_pd<K, MCT>(), NS = PD + 1;
   const Layout& L = a.L;
-  const int lane = threadIdx.x & 63;
+  const int lane = threadIdx.x & 63, nb = g.nb;
   const T* fac = wsp<T>(a.ws, L.fac) + (size_t)j * L.nbmax * L.rec;
   const T* swx = wsp<T>(a.ws, L.swx) + (size_t)j * L.nbmax * 3 * K * K;
   const T* gm = wsp<T>(a.ws, L.gmat) + (size_t)j * L.nbmax * K * K;
   const int* ipv = wsp<int>(a.ws, L.ipiv) + (size_t)j * L.nbmax * K;
   const int* flg = wsp<int>(a.ws, L.flag) + (size_t)j * L.nbmax;
   int* perm = reinterpret_cast<int*>(lds + W::total);
-  V w0[W::RT][MCT], w1[W::RT][MCT], z[W::RT][MCT], acc[W::RT][MCT], nx[W::RT][MCT];
+  const RowBuf src = row_buf(a.src, g, a.ld, c0, a.m);
+  const RowBuf dst = row_buf(a.dst, g, a.ld, c0, a.m);
+  V z[W::RT][MCT], acc[W::RT][MCT], rows[NS][W::RT][MCT];  // rows[b mod NS]: r_b, updated in place
+  T lpq[NS][NF], gtq[NS][NF];
   zero_strip<T, K, MCT>(acc);
-  load_strip<T, K, MCT>(w0, a.src, a.ld, g, 0, c0, a.m, Ct, Cb);
-  if (g.nb > 1)
-    load_strip<T, K, MCT>(w1, a.src, a.ld, g, 1, c0, a.m, Ct, Cb);
-  else
-    zero_strip<T, K, MCT>(w1);
-  // factor fragments, flags and right-hand-side rows are fetched two blocks
-  // ahead (one wave per SIMD: one block of work does not cover the memory
-  // latency)
-  T lp[NF], gt[NF], lpn[NF], gtn[NF], lp2[NF], gt2[NF];
-  load_frags<T, K>(lp, fac);
-  if (DSTAGE) load_frags<T, K>(gt, gm);
-  int fl = flg[0], fln = 0, fl2 = 0;
-  if (g.nb > 1) {
-    load_frags<T, K>(lpn, fac + (size_t)L.rec);
-    if (DSTAGE) load_frags<T, K>(gtn, gm + (size_t)K * K);
-    fln = flg[1];
-  }
-  for (int b = 0; b < g.nb; ++b) {
-    const bool last = (b == g.nb - 1);
-    if (b + 2 < g.nb) {
-      load_frags<T, K>(lp2, fac + (size_t)(b + 2) * L.rec);
-      if (DSTAGE) load_frags<T, K>(gt2, gm + (size_t)(b + 2) * K * K);
-      fl2 = flg[b + 2];
+  auto fetch_rec = [&](int q, T (&lp)[NF], T (&gt)[NF]) __attribute__((always_inline)) {
+    const int qc = min(q, nb - 1);
+    load_frags<T, K>(lp, fac + (size_t)qc * L.rec);
+    if (DSTAGE) load_frags<T, K>(gt, gm + (size_t)qc * K * K);
+  };
+  // block 0 with its interface corrections, then the first PD records and rows
+  buf_load_strip<T, K, MCT>(rows[0], src, 0);
+  if (Ct || Cb) sub_corr<T, K, MCT>(rows[0], g, 0, Ct, Cb);
+  static_for<PD>([&](auto U) __attribute__((always_inline)) {
+    constexpr int u = decltype(U)::value;
+    fetch_rec(u, lpq[u], gtq[u]);
+    buf_load_strip<T, K, MCT>(rows[u + 1], src, u + 1);
+  });
+  auto body = [&](auto U, int b) __attribute__((always_inline)) {
+    constexpr int u = decltype(U)::value;  // slot of block b
+    constexpr int u1 = (u + 1) % NS;       // rows of block b + 1
+    constexpr int uf = (u + PD) % NS;      // slot that receives the records of block b + PD
+    const bool last = (b == nb - 1);
+    fetch_rec(b + PD, lpq[uf], gtq[uf]);
+    T (&lp)[NF] = lpq[u];
+    V (&w0)[W::RT][MCT] = rows[u];
+    V (&w1)[W::RT][MCT] = rows[u1];
+    if ((Ct || Cb) && !last && corr_block(g, K, b + 1)) sub_corr<T, K, MCT>(w1, g, b + 1, Ct, Cb);
+    int fl = 0;
+    if constexpr (SWP) {
+      fl = flg[b];
+      if (fl & 1) permute_strips<T, K, MCT>(w0, w1, !last, ipv + (size_t)b * K, lds + W::oStage, perm);
     }
-    if (b + 2 < g.nb)
-      load_strip<T, K, MCT>(nx, a.src, a.ld, g, b + 2, c0, a.m, Ct, Cb);
-    else
-      zero_strip<T, K, MCT>(nx);
-    if (fl & 1) permute_strips<T, K, MCT>(w0, w1, !last, ipv + (size_t)b * K, lds + W::oStage, perm);
     zero_strip<T, K, MCT>(z);
     blk_mul<T, K, MCT, 0>(lp, nullptr, T(1), w0, z);  // z_b = L11^{-1} r_b
+    buf_load_strip<T, K, MCT>(rows[u], src, b + 1 + PD);  // slot (b + 1 + PD) mod NS = u, free once z_b is formed
     if (!last) {
-      if (fl & 1) {
+      if (SWP && (fl & 1)) {
         T l21[NF];
         load_frags<T, K>(l21, swx + (size_t)b * 3 * K * K);
         blk_mul<T, K, MCT, 9>(l21, nullptr, T(-1), z, w1);
@@ -271,97 +378,94 @@ __device__ void fwd_wave(const SolveArgs& a, const Geom& g, int j, int c0, T* ld
         blk_mul<T, K, MCT, 1>(lp, nullptr, T(-1), z, w1);  // r_{b+1} -= L21 z_b
       }
     }
-    if (DSTAGE) {
-      blk_mul<T, K, MCT, 9>(gt, nullptr, T(1), z, acc);  // y_t += G^T z_b
-      if (last) {
-        // y_b = U11^{-1} z_last
-        T up[NF];
-        load_frags<T, K>(up, fac + (size_t)b * L.rec + K * K);
-        V yb[W::RT][MCT];
-        zero_strip<T, K, MCT>(yb);
-        blk_mul<T, K, MCT, 2>(up, nullptr, T(1), z, yb);
-        double* yt = wsp<double>(a.ws, L.ytip) + (size_t)j * 2 * K * L.mmax;
-#pragma unroll
-        for (int t = 0; t < W::RT; ++t)
-#pragma unroll
-          for (int ct = 0; ct < MCT; ++ct)
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-              const int row = 16 * t + acc_row<T>(lane, v), col = 16 * ct + (lane & 15);
-              if (c0 + col < a.m) {
-                yt[(size_t)row * L.mmax + c0 + col] = (double)acc[t][ct][v];
-                yt[(size_t)(K + row) * L.mmax + c0 + col] = (double)yb[t][ct][v];
-              }
-            }
-      }
-    } else {
-      store_strip<T, K, MCT>(z, a.dst, a.ld, g, b, c0, a.m);
-    }
+    if (DSTAGE)
+      blk_mul<T, K, MCT, 9>(gtq[u], nullptr, T(1), z, acc);  // y_t += G^T z_b
+    else
+      buf_store_strip<T, K, MCT>(z, dst, b);
+  };
+  int b0 = 0;
+  for (; b0 + NS <= nb; b0 += NS)
+    static_for<NS>([&](auto U) __attribute__((always_inline)) { body(U, b0 + decltype(U)::value); });
+  static_for<NS>([&](auto U) __attribute__((always_inline)) {
+    if (b0 + decltype(U)::value < nb) body(U, b0 + decltype(U)::value);
+  });
+  if (DSTAGE) {
+    // y_b = U11^{-1} z_last; y_t and y_b to the tip buffer
+    T up[NF];
+    load_frags<T, K>(up, fac + (size_t)(nb - 1) * L.rec + K * K);
+    V yb[W::RT][MCT];
+    zero_strip<T, K, MCT>(yb);
+    blk_mul<T, K, MCT, 2>(up, nullptr, T(1), z, yb);
+    double* yt = wsp<double>(a.ws, L.ytip) + (size_t)j * 2 * K * L.mmax;
 #pragma unroll
     for (int t = 0; t < W::RT; ++t)
 #pragma unroll
-      for (int ct = 0; ct < MCT; ++ct) {
-        w0[t][ct] = w1[t][ct];
-        w1[t][ct] = nx[t][ct];
-      }
+      for (int ct = 0; ct < MCT; ++ct)
 #pragma unroll
-    for (int f = 0; f < NF; ++f) {
-      lp[f] = lpn[f];
-      lpn[f] = lp2[f];
-      if (DSTAGE) {
-        gt[f] = gtn[f];
-        gtn[f] = gt2[f];
-      }
-    }
-    fl = fln;
-    fln = fl2;
+        for (int v = 0; v < 4; ++v) {
+          const int row = 16 * t + acc_row<T>(lane, v), col = 16 * ct + (lane & 15);
+          if (c0 + col < a.m) {
+            yt[(size_t)row * L.mmax + c0 + col] = (double)acc[t][ct][v];
+            yt[(size_t)(K + row) * L.mmax + c0 + col] = (double)yb[t][ct][v];
+          }
+        }
   }
 }
 
-// Backward pass x_b = U11^{-1}(z_b - U12 x_{b+1} - U13 x_{b+2}) over a.dst.
-template <typename T, int K, int MCT>
-__device__ void bwd_wave(const SolveArgs& a, const Geom& g, int j, int c0) {
+template <typename T, int K, int MCT, bool DSTAGE>
+__device__ void fwd_wave(const SolveArgs& a, const Geom& g, int j, int c0, T* lds, const T* Ct, const T* Cb) {
+  if (wsp<int>(a.ws, a.L.npv)[j] != 0)
+    fwd_wave_impl<T, K, MCT, DSTAGE, true>(a, g, j, c0, lds, Ct, Cb);
+  else
+    fwd_wave_impl<T, K, MCT, DSTAGE, false>(a, g, j, c0, lds, Ct, Cb);
+}
+
+// Backward pass x_b = U11^{-1}(z_b - U12 x_{b+1} - U13 x_{b+2}) over a.dst,
+// blocks from the last to the first; the q-th block visited (b = nb - 1 - q)
+// lives in ring slot q mod NS (same ring as the forward pass).
+template <typename T, int K, int MCT, bool SWP>
+__device__ void bwd_wave_impl(const SolveArgs& a, const Geom& g, int j, int c0) {
   using W = WaveSweep<T, K, MCT>;
   using V = typename W::V;
-  constexpr int NF = W::RT * W::KS;
+  constexpr int NF = W::RT * W::KS, PD = sweep_pd<K, MCT>(), NS = PD + 1;
   const Layout& L = a.L;
+  const int nb = g.nb;
   const T* fac = wsp<T>(a.ws, L.fac) + (size_t)j * L.nbmax * L.rec;
   const T* swx = wsp<T>(a.ws, L.swx) + (size_t)j * L.nbmax * 3 * K * K;
   const int* flg = wsp<int>(a.ws, L.flag) + (size_t)j * L.nbmax;
-  V x1[W::RT][MCT], x2[W::RT][MCT], zb[W::RT][MCT], zn[W::RT][MCT], xb[W::RT][MCT];
+  const RowBuf xb_buf = row_buf(a.dst, g, a.ld, c0, a.m);
+  V x1[W::RT][MCT], x2[W::RT][MCT], xb[W::RT][MCT], zq[NS][W::RT][MCT];
+  T upq[NS][NF], udq[NS][W::RT][4];
   zero_strip<T, K, MCT>(x1);
   zero_strip<T, K, MCT>(x2);
-  // records, flags and z rows are fetched two blocks ahead
-  T up[NF], upn[NF], up2[NF], ud[W::RT][4], udn[W::RT][4], ud2[W::RT][4];
-  V zn2[W::RT][MCT];
-  int b = g.nb - 1;
-  load_frags<T, K>(up, fac + (size_t)b * L.rec + K * K);
-  load_udrows<T, K>(ud, fac + (size_t)b * L.rec + 2 * K * K);
-  int fl = flg[b], fln = 0, fl2 = 0;
-  load_strip<T, K, MCT>(zb, a.dst, a.ld, g, b, c0, a.m, nullptr, nullptr);
-  if (b > 0) {
-    load_frags<T, K>(upn, fac + (size_t)(b - 1) * L.rec + K * K);
-    load_udrows<T, K>(udn, fac + (size_t)(b - 1) * L.rec + 2 * K * K);
-    fln = flg[b - 1];
-    load_strip<T, K, MCT>(zn, a.dst, a.ld, g, b - 1, c0, a.m, nullptr, nullptr);
-  }
-  for (; b >= 0; --b) {
-    const bool last = (b == g.nb - 1);
-    if (b > 1) {
-      load_frags<T, K>(up2, fac + (size_t)(b - 2) * L.rec + K * K);
-      load_udrows<T, K>(ud2, fac + (size_t)(b - 2) * L.rec + 2 * K * K);
-      fl2 = flg[b - 2];
-      load_strip<T, K, MCT>(zn2, a.dst, a.ld, g, b - 2, c0, a.m, nullptr, nullptr);
-    }
+  auto fetch = [&](int q, T (&up)[NF], T (&ud)[W::RT][4], V (&zs)[W::RT][MCT]) __attribute__((always_inline)) {
+    const int b = max(nb - 1 - q, 0);
+    load_frags<T, K>(up, fac + (size_t)b * L.rec + K * K);
+    load_udrows<T, K>(ud, fac + (size_t)b * L.rec + 2 * K * K);
+    buf_load_strip<T, K, MCT>(zs, xb_buf, nb - 1 - q);  // rows before the partition read as 0
+  };
+  static_for<PD>([&](auto U) __attribute__((always_inline)) {
+    constexpr int u = decltype(U)::value;
+    fetch(u, upq[u], udq[u], zq[u]);
+  });
+  auto body = [&](auto U, int q) __attribute__((always_inline)) {
+    constexpr int u = decltype(U)::value, uf = (u + PD) % NS;
+    const int b = nb - 1 - q;
+    const bool last = (q == 0);
+    fetch(q + PD, upq[uf], udq[uf], zq[uf]);
+    T (&up)[NF] = upq[u];
+    V (&zb)[W::RT][MCT] = zq[u];
     if (!last) {
-      if (fl & 2) {
+      int fl = 0;
+      if constexpr (SWP) fl = flg[b];
+      if (SWP && (fl & 2)) {
         T u12[NF];
         load_frags<T, K>(u12, swx + (size_t)b * 3 * K * K + K * K);
         blk_mul<T, K, MCT, 9>(u12, nullptr, T(-1), x1, zb);
       } else {
-        u12_mul<T, K, MCT>(up, ud, x1, zb);  // z_b -= U12 x_{b+1}
+        u12_mul<T, K, MCT>(up, udq[u], x1, zb);  // z_b -= U12 x_{b+1}
       }
-      if (fl & 1) {
+      if (SWP && (fl & 1)) {
         T u13[NF];
         load_frags<T, K>(u13, swx + (size_t)b * 3 * K * K + 2 * K * K);
         blk_mul<T, K, MCT, 9>(u13, nullptr, T(-1), x2, zb);
@@ -369,31 +473,29 @@ __device__ void bwd_wave(const SolveArgs& a, const Geom& g, int j, int c0) {
     }
     zero_strip<T, K, MCT>(xb);
     blk_mul<T, K, MCT, 2>(up, nullptr, T(1), zb, xb);  // x_b = U11^{-1} (...)
-    store_strip<T, K, MCT>(xb, a.dst, a.ld, g, b, c0, a.m);
+    buf_store_strip<T, K, MCT>(xb, xb_buf, b);
 #pragma unroll
     for (int t = 0; t < W::RT; ++t)
 #pragma unroll
       for (int ct = 0; ct < MCT; ++ct) {
         x2[t][ct] = x1[t][ct];
         x1[t][ct] = xb[t][ct];
-        zb[t][ct] = zn[t][ct];
-        zn[t][ct] = zn2[t][ct];
       }
-#pragma unroll
-    for (int f = 0; f < NF; ++f) {
-      up[f] = upn[f];
-      upn[f] = up2[f];
-    }
-#pragma unroll
-    for (int t = 0; t < W::RT; ++t)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        ud[t][v] = udn[t][v];
-        udn[t][v] = ud2[t][v];
-      }
-    fl = fln;
-    fln = fl2;
-  }
+  };
+  int q0 = 0;
+  for (; q0 + NS <= nb; q0 += NS)
+    static_for<NS>([&](auto U) __attribute__((always_inline)) { body(U, q0 + decltype(U)::value); });
+  static_for<NS>([&](auto U) __attribute__((always_inline)) {
+    if (q0 + decltype(U)::value < nb) body(U, q0 + decltype(U)::value);
+  });
+}
+
+template <typename T, int K, int MCT>
+__device__ void bwd_wave(const SolveArgs& a, const Geom& g, int j, int c0) {
+  if (wsp<int>(a.ws, a.L.npv)[j] != 0)
+    bwd_wave_impl<T, K, MCT, true>(a, g, j, c0);
+  else
+    bwd_wave_impl<T, K, MCT, false>(a, g, j, c0);
 }
 
 template <typename T, int K, int MCT>
@@ -497,6 +599,9 @@ __global__ __launch_bounds__(64) void pass2_wave_kernel(FactorArgs a) {
   const T* swx = wsT<T>(a.ws, L.swx) + (size_t)j * L.nbmax * 3 * K * K;
   const T* ym = wsT<T>(a.ws, L.ymat) + (size_t)j * L.nbmax * 2 * K * K;
   const int* flg = wsT<int>(a.ws, L.flag) + (size_t)j * L.nbmax;
+  // flags only for partitions factored with interchanges (zero elsewhere; a
+  // flag load consumed at once would stall every block)
+  const bool swp = wsT<int>(a.ws, L.npv)[j] != 0;
   const int coff = spike == 0 ? 0 : K;  // Y columns [W | V]
   // V's right-hand side lives in the last k rows: its forward result is zero
   // above the last two blocks (interchanges act within a block pair) and is
@@ -530,13 +635,13 @@ __global__ __launch_bounds__(64) void pass2_wave_kernel(FactorArgs a) {
   int b = g.nb - 1;
   load_frags<T, K>(up, fac + (size_t)b * L.rec + K * K);
   load_udrows<T, K>(ud, fac + (size_t)b * L.rec + 2 * K * K);
-  int fl = flg[b];
+  int fl = swp ? flg[b] : 0;
   load_y(b, zb);
   int fln = 0, fl2 = 0;
   if (b > 0) {
     load_frags<T, K>(upn, fac + (size_t)(b - 1) * L.rec + K * K);
     load_udrows<T, K>(udn, fac + (size_t)(b - 1) * L.rec + 2 * K * K);
-    fln = flg[b - 1];
+    fln = swp ? flg[b - 1] : 0;
     load_y(b - 1, zn);
   }
   for (; b >= 0; --b) {
@@ -544,7 +649,7 @@ __global__ __launch_bounds__(64) void pass2_wave_kernel(FactorArgs a) {
     if (b > 1) {
       load_frags<T, K>(up2, fac + (size_t)(b - 2) * L.rec + K * K);
       load_udrows<T, K>(ud2, fac + (size_t)(b - 2) * L.rec + 2 * K * K);
-      fl2 = flg[b - 2];
+      fl2 = swp ? flg[b - 2] : 0;
       load_y(b - 2, zn2);
     }
     if (!last) {
