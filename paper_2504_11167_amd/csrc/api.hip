@@ -420,6 +420,26 @@ int run_apply(lrspike_plan P, double* rhs, int m, int transpose, const int* gate
       if ((rc = run_reduced<K>(P, m, 0, gate))) return rc;
     }
     LRS_LAUNCH("retrieve_kernel", retrieve_kernel<T, K>, grid, dim3(LRS_NT), bs, sa);
+  } else if (K >= 16 && K <= 32 && P->wave && rows31) {
+    // adjoint on the matrix cores for the partitions factored without
+    // interchanges; the workgroup kernels take the others
+    if constexpr (K >= 16 && K <= 32) {
+      if (!set_lds((const void*)adj_dstage_kernel<T, K>, bs) || !set_lds((const void*)adj_retrieve_kernel<T, K>, bs))
+        return LRSPIKE_ERR_NOT_SUPPORTED;
+      dim3 gw(L.p, (m + 15) / 16);
+      const size_t bw = (size_t)WaveSweep<T, K, 1>::total * sizeof(T);
+      SolveArgs sf = sa;
+      sf.only_flagged = 1;
+      if (L.p > 1) {
+        SolveArgs sd = sa, sdf = sf;
+        sd.dst = sdf.dst = reinterpret_cast<double*>(P->ws + L.scr);
+        LRS_LAUNCH("adj_dstage_kernel", adj_dstage_wave_kernel<T, K>, gw, dim3(64), 0, sd);
+        LRS_LAUNCH("adj_dstage_pivoting", adj_dstage_kernel<T, K>, grid, dim3(LRS_NT), bs, sdf);
+        if ((rc = run_reduced<K>(P, m, 1, gate))) return rc;
+      }
+      LRS_LAUNCH("adj_retrieve_kernel", adj_retrieve_wave_kernel<T, K>, gw, dim3(64), bw, sa);
+      LRS_LAUNCH("adj_retrieve_pivoting", adj_retrieve_kernel<T, K>, grid, dim3(LRS_NT), bs, sf);
+    }
   } else {
     if (!set_lds((const void*)adj_dstage_kernel<T, K>, bs) || !set_lds((const void*)adj_retrieve_kernel<T, K>, bs))
       return LRSPIKE_ERR_NOT_SUPPORTED;

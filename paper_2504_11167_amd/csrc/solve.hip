@@ -22,6 +22,7 @@ struct SolveArgs {
   int ld;             // row stride of src / dst
   int m;              // columns
   const int* gate;    // refinement: nonzero *gate = the iteration has stopped, the kernel is a no-op (null = always run)
+  int only_flagged;   // workgroup adjoint kernels: only the partitions factored with interchanges
 };
 
 __device__ __forceinline__ bool gated(const int* gate) { return gate && *gate != 0; }
@@ -423,6 +424,7 @@ __device__ void tbackward_pass(const SolveArgs& a, const Geom& g, int j, int c0,
 template <typename T, int K>
 __global__ __launch_bounds__(LRS_NT) void adj_dstage_kernel(SolveArgs a) {
   if (gated(a.gate)) return;
+  if (a.only_flagged && wsp<int>(a.ws, a.L.npv)[blockIdx.x] == 0) return;
   extern __shared__ __align__(16) unsigned char lds_raw[];
   __shared__ int s_perm[2 * K];
   T* lds = reinterpret_cast<T*>(lds_raw);
@@ -449,6 +451,7 @@ __global__ __launch_bounds__(LRS_NT) void adj_dstage_kernel(SolveArgs a) {
 template <typename T, int K>
 __global__ __launch_bounds__(LRS_NT) void adj_retrieve_kernel(SolveArgs a) {
   if (gated(a.gate)) return;
+  if (a.only_flagged && wsp<int>(a.ws, a.L.npv)[blockIdx.x] == 0) return;
   using LD = SwLds<K>;
   constexpr int LDM = LD::LDM;
   extern __shared__ __align__(16) unsigned char lds_raw[];

@@ -44,6 +44,10 @@ __device__ __forceinline__ T fmask(T v, int t, int step, int lane, T dg) {
   if constexpr (kind == 1) return i <= kk ? v : T(0);
   if constexpr (kind == 2) return i <= kk ? v : T(0);
   if constexpr (kind == 3) return i > kk ? v : dg;
+  // transposed operands, v = M(kk, i) gathered by load_tfrags:
+  if constexpr (kind == 4) return i < kk ? v : (i == kk ? T(1) : T(0));  // (L11^{-1})^T, unit upper
+  if constexpr (kind == 5) return i >= kk ? v : T(0);                    // L21^T, (U11^{-1})^T: lower
+  if constexpr (kind == 7) return kk > i ? v : T(0);                     // U12^T without its diagonal
   return v;
 }
 
@@ -182,7 +186,9 @@ __device__ __forceinline__ void blk_mul(const T (&frag)[(K / 16) * (K / 4)], con
   for (int t = 0; t < K / 16; ++t)
 #pragma unroll
     for (int step = 0; step < K / 4; ++step) {
-      if (((kind == 0 || kind == 3) && (step >> 2) > t) || ((kind == 1 || kind == 2) && (step >> 2) < t)) continue;
+      if (((kind == 0 || kind == 3 || kind == 5) && (step >> 2) > t) ||
+          ((kind == 1 || kind == 2 || kind == 4 || kind == 7) && (step >> 2) < t))
+        continue;
       const T av = sign * fmask<T, kind>(frag[t * (K / 4) + step], t, step, lane,
                                          kind == 3 ? dg[t * (K / 4) + step] : T(0));
 #pragma unroll
@@ -195,6 +201,19 @@ __device__ __forceinline__ void load_frags(T (&dst)[(K / 16) * (K / 4)], const T
   const int lane = threadIdx.x & 63;
 #pragma unroll
   for (int f = 0; f < (K / 16) * (K / 4); ++f) dst[f] = src[(f << 6) + lane];
+}
+
+// Fragments of M^T as the A operand: lane holds M(kk, i) for (i, kk) =
+// (16 t + lane mod 16, frag_k(step, lane / 16)), gathered inside the K x K
+// record block (a few cache lines); blk_mul's transposed kinds mask them.
+template <typename T, int K>
+__device__ __forceinline__ void load_tfrags(T (&dst)[(K / 16) * (K / 4)], const T* blk) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int t = 0; t < K / 16; ++t)
+#pragma unroll
+    for (int step = 0; step < K / 4; ++step)
+      dst[t * (K / 4) + step] = blk[fidx<T, K>(frag_k<T>(step, lane >> 4), 16 * t + (lane & 15))];
 }
 
 // Diagonal of U12 (UD vector of the record) at the strip rows a lane holds.
@@ -580,6 +599,201 @@ __global__ __launch_bounds__(64) void retrieve_wave_kernel(SolveArgs a) {
   bwd_wave<T, K, MCT>(a, g, j, c0);
 }
 
+
+// ------------------------------------------------------------------ adjoint
+// Transposed sweeps for partitions factored without interchanges (A_j = L U,
+// A_j^{-T} = L^{-T} U^{-T}), with the prefetch ring of the forward sweeps.
+// Transposed forward (U^T, top to bottom): W_b = U11^{-T} R_b, then
+// R_{b+1} -= U12^T W_b; W is written to a.dst.  One gather of the UP record
+// serves (U11^{-1})^T (its lower part) and U12^T (its strict upper part; the
+// diagonal UD is applied elementwise).
+template <typename T, int K, int MCT>
+__device__ void tfwd_wave(const SolveArgs& a, const Geom& g, int j, int c0, const T* Ct, const T* Cb) {
+  using W = WaveSweep<T, K, MCT>;
+  using V = typename W::V;
+  constexpr int NF = W::RT * W::KS, PD = sweep_pd<K, MCT>(), NS = PD + 1;
+  const Layout& L = a.L;
+  const int nb = g.nb;
+  const T* fac = wsp<T>(a.ws, L.fac) + (size_t)j * L.nbmax * L.rec;
+  const RowBuf src = row_buf(a.src, g, a.ld, c0, a.m);
+  const RowBuf dst = row_buf(a.dst, g, a.ld, c0, a.m);
+  V wb[W::RT][MCT], rows[NS][W::RT][MCT];
+  T upq[NS][NF], udq[NS][W::RT][4];
+  auto fetch_rec = [&](int q, T (&up)[NF], T (&ud)[W::RT][4]) __attribute__((always_inline)) {
+    const int qc = min(q, nb - 1);
+    load_tfrags<T, K>(up, fac + (size_t)qc * L.rec + K * K);
+    load_udrows<T, K>(ud, fac + (size_t)qc * L.rec + 2 * K * K);
+  };
+  buf_load_strip<T, K, MCT>(rows[0], src, 0);
+  if (Ct || Cb) sub_corr<T, K, MCT>(rows[0], g, 0, Ct, Cb);
+  static_for<PD>([&](auto U) __attribute__((always_inline)) {
+    constexpr int u = decltype(U)::value;
+    fetch_rec(u, upq[u], udq[u]);
+    buf_load_strip<T, K, MCT>(rows[u + 1], src, u + 1);
+  });
+  auto body = [&](auto U, int b) __attribute__((always_inline)) {
+    constexpr int u = decltype(U)::value, u1 = (u + 1) % NS, uf = (u + PD) % NS;
+    const bool last = (b == nb - 1);
+    fetch_rec(b + PD, upq[uf], udq[uf]);
+    V (&w0)[W::RT][MCT] = rows[u];
+    V (&w1)[W::RT][MCT] = rows[u1];
+    if ((Ct || Cb) && !last && corr_block(g, K, b + 1)) sub_corr<T, K, MCT>(w1, g, b + 1, Ct, Cb);
+    zero_strip<T, K, MCT>(wb);
+    blk_mul<T, K, MCT, 5>(upq[u], nullptr, T(1), w0, wb);  // W_b = U11^{-T} R_b
+    buf_load_strip<T, K, MCT>(rows[u], src, b + 1 + PD);
+    if (!last) {
+      blk_mul<T, K, MCT, 7>(upq[u], nullptr, T(-1), wb, w1);  // R_{b+1} -= U12^T W_b (off the diagonal)
+#pragma unroll
+      for (int t = 0; t < W::RT; ++t)
+#pragma unroll
+        for (int ct = 0; ct < MCT; ++ct)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) w1[t][ct][v] -= udq[u][t][v] * wb[t][ct][v];
+    }
+    buf_store_strip<T, K, MCT>(wb, dst, b);
+  };
+  int b0 = 0;
+  for (; b0 + NS <= nb; b0 += NS)
+    static_for<NS>([&](auto U) __attribute__((always_inline)) { body(U, b0 + decltype(U)::value); });
+  static_for<NS>([&](auto U) __attribute__((always_inline)) {
+    if (b0 + decltype(U)::value < nb) body(U, b0 + decltype(U)::value);
+  });
+}
+
+// Transposed backward (L^T, bottom to top) over a.dst: u_b = L11^{-T}(W_b -
+// L21^T u_{b+1}); one gather of the LP record serves L21^T (its lower part)
+// and (L11^{-1})^T (its strict upper part, unit diagonal).  TIPS: u is not
+// stored; the rows of its first and last K real rows go to the tip buffer
+// (the adjoint D-stage).  Otherwise u overwrites a.dst.
+template <typename T, int K, int MCT, bool TIPS>
+__device__ void tbwd_wave(const SolveArgs& a, const Geom& g, int j, int c0) {
+  using W = WaveSweep<T, K, MCT>;
+  using V = typename W::V;
+  constexpr int NF = W::RT * W::KS, PD = sweep_pd<K, MCT>(), NS = PD + 1;
+  const Layout& L = a.L;
+  const int nb = g.nb, lane = threadIdx.x & 63;
+  const T* fac = wsp<T>(a.ws, L.fac) + (size_t)j * L.nbmax * L.rec;
+  const RowBuf buf = row_buf(a.dst, g, a.ld, c0, a.m);
+  double* yt = wsp<double>(a.ws, L.ytip) + (size_t)j * 2 * K * L.mmax;
+  V x1[W::RT][MCT], ub[W::RT][MCT], zq[NS][W::RT][MCT];
+  T lpq[NS][NF];
+  zero_strip<T, K, MCT>(x1);
+  auto fetch = [&](int q, T (&lp)[NF], V (&zs)[W::RT][MCT]) __attribute__((always_inline)) {
+    const int b = max(nb - 1 - q, 0);
+    load_tfrags<T, K>(lp, fac + (size_t)b * L.rec);
+    buf_load_strip<T, K, MCT>(zs, buf, nb - 1 - q);
+  };
+  static_for<PD>([&](auto U) __attribute__((always_inline)) {
+    constexpr int u = decltype(U)::value;
+    fetch(u, lpq[u], zq[u]);
+  });
+  auto body = [&](auto U, int q) __attribute__((always_inline)) {
+    constexpr int u = decltype(U)::value, uf = (u + PD) % NS;
+    const int b = nb - 1 - q;
+    fetch(q + PD, lpq[uf], zq[uf]);
+    V (&zb)[W::RT][MCT] = zq[u];
+    if (q != 0) blk_mul<T, K, MCT, 5>(lpq[u], nullptr, T(-1), x1, zb);  // W_b - L21^T u_{b+1}
+    zero_strip<T, K, MCT>(ub);
+    blk_mul<T, K, MCT, 4>(lpq[u], nullptr, T(1), zb, ub);  // u_b = L11^{-T} (...)
+    if constexpr (TIPS) {
+      if (corr_block(g, K, b)) {
+#pragma unroll
+        for (int t = 0; t < W::RT; ++t)
+#pragma unroll
+          for (int ct = 0; ct < MCT; ++ct)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+              const int row = 16 * t + acc_row<T>(lane, v), col = 16 * ct + (lane & 15);
+              const int lr = b * K + row - g.pad;
+              if (lr >= 0 && c0 + col < a.m) {
+                if (lr < K) yt[(size_t)lr * L.mmax + c0 + col] = (double)ub[t][ct][v];
+                if (lr >= g.nj - K) yt[(size_t)(K + lr - (g.nj - K)) * L.mmax + c0 + col] = (double)ub[t][ct][v];
+              }
+            }
+      }
+    } else {
+      buf_store_strip<T, K, MCT>(ub, buf, b);
+    }
+#pragma unroll
+    for (int t = 0; t < W::RT; ++t)
+#pragma unroll
+      for (int ct = 0; ct < MCT; ++ct) x1[t][ct] = ub[t][ct];
+  };
+  int q0 = 0;
+  for (; q0 + NS <= nb; q0 += NS)
+    static_for<NS>([&](auto U) __attribute__((always_inline)) { body(U, q0 + decltype(U)::value); });
+  static_for<NS>([&](auto U) __attribute__((always_inline)) {
+    if (q0 + decltype(U)::value < nb) body(U, q0 + decltype(U)::value);
+  });
+}
+
+// Adjoint D-stage on the matrix cores: nu_j = A_j^{-T} g_j (U^T sweep with
+// W into a.dst, then L^T sweep), tips nu_t, nu_b to the tip buffer.
+// Partitions factored with interchanges are left to adj_dstage_kernel.
+template <typename T, int K>
+__global__ __launch_bounds__(64) void adj_dstage_wave_kernel(SolveArgs a) {
+  if (gated(a.gate)) return;
+  const int j = blockIdx.x, c0 = blockIdx.y * 16;
+  if (wsp<int>(a.ws, a.L.npv)[j]) return;
+  const Geom g = part_geom(a.L, j, K);
+  tfwd_wave<T, K, 1>(a, g, j, c0, nullptr, nullptr);
+  tbwd_wave<T, K, 1, true>(a, g, j, c0);
+}
+
+// Adjoint recovery on the matrix cores: lambda_j = A_j^{-T}(g_j - [w_{j,t};
+// 0; w_{j,b}]) in place, with
+//   w_{j,t} = B_{j-1}^T nu_{j-1,b} - Pi_{j-1} u_a(j-1)      (j >= 1)
+//   w_{j,b} = C_{j+1}^T nu_{j+1,t} - Psi_{j+1} u_c(j+1)      (j <= p-2)
+// (u = Z^{-T} L^T h in the compressed vector); LR-SPIKE-T needs no change here.
+template <typename T, int K>
+__global__ __launch_bounds__(64) void adj_retrieve_wave_kernel(SolveArgs a) {
+  if (gated(a.gate)) return;
+  using W = WaveSweep<T, K, 1>;
+  constexpr int NC = W::NC;
+  extern __shared__ __align__(16) unsigned char lds_raw[];
+  T* lds = reinterpret_cast<T*>(lds_raw);
+  const Layout& L = a.L;
+  const int j = blockIdx.x, c0 = blockIdx.y * NC;
+  if (wsp<int>(a.ws, L.npv)[j]) return;
+  const int mc = min(NC, a.m - c0);
+  const Geom g = part_geom(L, j, K);
+  const int lane = threadIdx.x & 63, k = L.k, r = L.r;
+  T* Ct = lds + W::oCt;
+  T* Cb = lds + W::oCb;
+  const double* ytip = wsp<double>(a.ws, L.ytip);
+  const double* proj = wsp<double>(a.ws, L.proj);
+  const double* zg = wsp<double>(a.ws, L.zg);
+  if (j > 0) {
+    const double* nub = ytip + ((size_t)(j - 1) * 2 + 1) * K * L.mmax;
+    const double* Pi = proj + (size_t)(j - 1) * 2 * K * r;
+    const double* ua = zg + (size_t)(j - 1) * L.R2 * L.mmax;
+    for (int o = lane; o < K * mc; o += 64) {
+      const int i = o / mc, c = o % mc;
+      double s = 0.0;
+      for (int l = 0; l < K; ++l) s += band_at(a.bands, L.n, k, g.s - K + l, g.s + i) * nub[l * L.mmax + c0 + c];
+      for (int q = 0; q < r; ++q) s -= Pi[i * r + q] * ua[q * L.mmax + c0 + c];
+      Ct[i * NC + c] = (T)s;
+    }
+  }
+  if (j < L.p - 1) {
+    const double* nut = ytip + ((size_t)(j + 1) * 2 + 0) * K * L.mmax;
+    const double* Psi = proj + ((size_t)(j + 1) * 2 + 1) * K * r;
+    const double* uc = zg + ((size_t)j * L.R2 + r) * L.mmax;
+    const int64_t s1 = g.s + g.nj;
+    for (int o = lane; o < K * mc; o += 64) {
+      const int i = o / mc, c = o % mc;
+      double s = 0.0;
+      for (int l = 0; l < K; ++l) s += band_at(a.bands, L.n, k, s1 + l, s1 - K + i) * nut[l * L.mmax + c0 + c];
+      for (int q = 0; q < r; ++q) s -= Psi[i * r + q] * uc[q * L.mmax + c0 + c];
+      Cb[i * NC + c] = (T)s;
+    }
+  }
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+  tfwd_wave<T, K, 1>(a, g, j, c0, j > 0 ? Ct : nullptr, j < L.p - 1 ? Cb : nullptr);
+  tbwd_wave<T, K, 1, false>(a, g, j, c0);
+}
 
 // Factorization pass 2 for K >= 16 (r < k): back substitution of one spike
 // (blockIdx.y = 0: W, 1: V) over the stored forward intermediate Y,
