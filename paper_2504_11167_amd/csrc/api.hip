@@ -901,6 +901,9 @@ int lrspike_destroy(lrspike_plan P) {
       for (BatchGroup& G : P->batch->groups) free_group(G);
       if (P->batch->graph) (void)hipGraphExecDestroy(P->batch->graph);
       if (P->batch->capture) (void)hipStreamDestroy(P->batch->capture);
+      for (hipStream_t s : P->batch->gstreams) (void)hipStreamDestroy(s);
+      for (hipEvent_t e : P->batch->joins) (void)hipEventDestroy(e);
+      if (P->batch->fork) (void)hipEventDestroy(P->batch->fork);
       delete P->batch;
     }
   }
@@ -985,9 +988,7 @@ int lrspike_run_batched(lrspike_plan P, double* rhs_base) {
   if (hipStreamSynchronize(st) != hipSuccess) return LRSPIKE_ERR_HIP;
   hipGraph_t g = nullptr;
   if (hipStreamBeginCapture(B.capture, hipStreamCaptureModeThreadLocal) != hipSuccess) return LRSPIKE_ERR_HIP;
-  set_group_streams(B, B.capture);
-  rc = run_batched_eager(P, rhs_base, true, true);
-  set_group_streams(B, st);
+  rc = run_batched_on(P, B.capture, rhs_base, true, true);
   const hipError_t ce = hipStreamEndCapture(B.capture, &g);
   if (rc || ce != hipSuccess) {
     if (g) (void)hipGraphDestroy(g);

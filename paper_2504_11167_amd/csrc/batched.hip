@@ -50,11 +50,14 @@ struct BatchState {
   hipGraphExec_t graph = nullptr;
   double* graph_rhs = nullptr;
   hipStream_t capture = nullptr;  // private stream the graph is captured on (the caller's may be the null stream)
+  // groups run side by side: one stream per group (default priority), forked
+  // from and joined back into the caller's (or the capture) stream by events,
+  // so that a captured step is a graph with one branch per group
+  std::vector<hipStream_t> gstreams;
+  std::vector<hipEvent_t> joins;
+  hipEvent_t fork = nullptr;
 };
 
-static void set_group_streams(BatchState& B, hipStream_t st) {
-  for (BatchGroup& G : B.groups) G.plan->stream = st;
-}
 
 // gband[(d+k) N + row0 + i] = A_s[i, i+d] (zero where i + d leaves system s)
 __global__ void pack_band_kernel(const BatchSys* __restrict__ sys, const BatchChunk* __restrict__ chunks,
@@ -249,14 +252,49 @@ static int autotune(BatchState& B, const lrspike_opts* opts) {
   return rc;
 }
 
-static int run_batched_eager(lrspike_plan P, double* rhs_base, bool factor, bool solve) {
-  BatchState& B = *P->batch;
-  int rc = 0;
-  if (factor)
-    for (BatchGroup& G : B.groups)
-      if ((rc = factor_group(B, G))) return rc;
-  if (solve)
-    for (BatchGroup& G : B.groups)
-      if ((rc = solve_group(B, G, rhs_base))) return rc;
+// Streams and events of the side-by-side groups (created once per plan).
+static int batch_streams(BatchState& B) {
+  if (!B.fork && hipEventCreateWithFlags(&B.fork, hipEventDisableTiming) != hipSuccess) {
+    B.fork = nullptr;
+    return LRSPIKE_ERR_HIP;
+  }
+  while (B.gstreams.size() < B.groups.size()) {
+    hipStream_t s = nullptr;
+    hipEvent_t e = nullptr;
+    if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) return LRSPIKE_ERR_HIP;
+    B.gstreams.push_back(s);
+    if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) return LRSPIKE_ERR_HIP;
+    B.joins.push_back(e);
+  }
   return 0;
+}
+
+// Factor and/or solve every group: each group on its own stream, forked from
+// `base` and joined back into it, the group with the most band entries first.
+static int run_batched_on(lrspike_plan P, hipStream_t base, double* rhs_base, bool factor, bool solve) {
+  BatchState& B = *P->batch;
+  int rc = batch_streams(B);
+  if (rc) return rc;
+  if (hipEventRecord(B.fork, base) != hipSuccess) return LRSPIKE_ERR_HIP;
+  std::vector<int> order(B.groups.size());
+  for (size_t g = 0; g < order.size(); ++g) order[g] = (int)g;
+  std::sort(order.begin(), order.end(), [&](int a, int b) {
+    return B.groups[a].N * (2 * B.groups[a].k + 1) > B.groups[b].N * (2 * B.groups[b].k + 1);
+  });
+  for (int g : order) {
+    BatchGroup& G = B.groups[g];
+    hipStream_t s = B.gstreams[g];
+    if (hipStreamWaitEvent(s, B.fork, 0) != hipSuccess) return LRSPIKE_ERR_HIP;
+    G.plan->stream = s;
+    if (factor && (rc = factor_group(B, G))) return rc;
+    if (solve && (rc = solve_group(B, G, rhs_base))) return rc;
+    if (hipEventRecord(B.joins[g], s) != hipSuccess) return LRSPIKE_ERR_HIP;
+  }
+  for (size_t g = 0; g < B.groups.size(); ++g)
+    if (hipStreamWaitEvent(base, B.joins[g], 0) != hipSuccess) return LRSPIKE_ERR_HIP;
+  return 0;
+}
+
+static int run_batched_eager(lrspike_plan P, double* rhs_base, bool factor, bool solve) {
+  return run_batched_on(P, P->stream, rhs_base, factor, solve);
 }

@@ -204,17 +204,6 @@ def test_refined_nondominant_low_rank_reports_failure(gpu):
     assert e.value.info["last_correction"] > 1e-6
 
 
-@pytest.mark.slow
-def test_full_size_large_workload(gpu):
-    """The benchmark configuration itself (n = 2^22, k = 32, p = 1024, r = 8,
-    16 right-hand sides, FP64), element by element against the oracle."""
-    n, k, p, r, m = 1 << 22, 32, 1024, 8, 16
-    bands, f = synth.make_problem(n, k, m, seed=0, rule="weak")
-    x, info = run(gpu, bands, f, p, r)
-    ref = oracle.lrspike(bands, f, p, r)
-    assert rel(x, ref) <= 1e-12
-
-
 def _batch(count, seed, ks=(4, 16, 32), nmax=3000, mmax=6):
     """count systems of the batched workload's kind: k drawn from ks, n up to nmax, 1..mmax right-hand sides."""
     rng = np.random.default_rng(seed)
