@@ -46,7 +46,7 @@ def _load():
         lib = ctypes.CDLL(path)
         i64, i32 = ctypes.c_int64, ctypes.c_int
         lib.orc_band_solve.argtypes = [i64, i32, _D, i32, _D, _D, i32]
-        lib.orc_band_solve_refined.argtypes = [i64, i32, _D, i32, _D, _D, i32]
+        lib.orc_band_solve_refined.argtypes = [i64, i32, _D, i32, _D, _D, i32, i32]
         lib.orc_band_matvec.argtypes = [i64, i32, _D, i32, _D, _D, i32]
         lib.orc_band_matvec.restype = None
         lib.orc_partition.argtypes = [i64, i32, _I64]
@@ -108,12 +108,13 @@ def band_solve(bands, f, transpose=False):
     return x[:, 0] if flat else x
 
 
-def band_solve_refined(bands, f, steps=2):
-    """x* with `steps` long-double-residual corrections (accurate to ~u for any kappa)."""
+def band_solve_refined(bands, f, steps=2, transpose=False):
+    """x* (or A^{-T} f) with `steps` long-double-residual corrections (accurate to ~u for any kappa)."""
     bands, n, k = _band_args(bands)
     f2, flat = _as2d(f)
     x = np.empty_like(f2)
-    _check(_load().orc_band_solve_refined(n, k, _p(bands), f2.shape[1], _p(f2), _p(x), steps), "band_solve_refined")
+    _check(_load().orc_band_solve_refined(n, k, _p(bands), f2.shape[1], _p(f2), _p(x), steps, int(transpose)),
+           "band_solve_refined")
     return x[:, 0] if flat else x
 
 

@@ -209,10 +209,11 @@ void orc_band_matvec(int64_t n, int k, const double *bands, int m, const double 
 /*
  * x* in FP64 made accurate to about one rounding independently of the
  * condition number: R0 followed by `steps` corrections whose residual
- * f - A x is accumulated in long double.
+ * f - A x is accumulated in long double.  transpose = 1: the same for
+ * A^T x = f (residual f - A^T x, corrections by the transposed solve).
  */
 int orc_band_solve_refined(int64_t n, int k, const double *bands, int m,
-                           const double *f, double *x, int steps) {
+                           const double *f, double *x, int steps, int transpose) {
   gband M;
   if (gb_from_input(&M, n, k, bands, 0, n)) return -100;
   int64_t info = gb_factor(&M);
@@ -221,17 +222,25 @@ int orc_band_solve_refined(int64_t n, int k, const double *bands, int m,
     return (int)imin64(info, 2147483647);
   }
   memcpy(x, f, sizeof(double) * (size_t)(n * m));
-  gb_solve(&M, m, x);
+  if (transpose)
+    gb_solve_t(&M, m, x);
+  else
+    gb_solve(&M, m, x);
   double *r = (double *)malloc(sizeof(double) * (size_t)(n * m));
   for (int s = 0; s < steps; ++s) {
     for (int64_t i = 0; i < n; ++i)
       for (int c = 0; c < m; ++c) {
         long double acc = (long double)f[i * m + c];
-        for (int64_t j = imax64(0, i - k); j <= imin64(n - 1, i + k); ++j)
-          acc -= (long double)band_entry(n, k, bands, i, j) * (long double)x[j * m + c];
+        for (int64_t j = imax64(0, i - k); j <= imin64(n - 1, i + k); ++j) {
+          const double a = transpose ? band_entry(n, k, bands, j, i) : band_entry(n, k, bands, i, j);
+          acc -= (long double)a * (long double)x[j * m + c];
+        }
         r[i * m + c] = (double)acc;
       }
-    gb_solve(&M, m, r);
+    if (transpose)
+      gb_solve_t(&M, m, r);
+    else
+      gb_solve(&M, m, r);
     for (int64_t i = 0; i < n * m; ++i) x[i] += r[i];
   }
   free(r);

@@ -188,6 +188,12 @@ def test_refined_reference_exact_on_integer_system():
     xr = oracle.band_solve_refined(bands, f, steps=3)
     assert rel(x0, x_true) > 1e-14
     assert rel(xr, x_true) <= 2 * np.finfo(float).eps
+    # the transposed system: g = A^T x_true, exact in double as well
+    g = dense(bands).T @ x_true
+    xt0 = oracle.band_solve(bands, g, transpose=True)
+    xtr = oracle.band_solve_refined(bands, g, steps=3, transpose=True)
+    assert rel(xt0, x_true) > 1e-14
+    assert rel(xtr, x_true) <= 2 * np.finfo(float).eps
 
 
 def test_band_matvec_transpose_is_dense_transpose():
