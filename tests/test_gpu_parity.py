@@ -86,9 +86,11 @@ def test_pivoting_nondominant(gpu, k, theta):
     # two backward-stable FP64 solves differ by ~kappa u; allow the GPU 10x the oracle's own error
     tol = max(1e-12, 10 * rel(x0, ref))
     assert rel(x, ref) <= tol
+    # the adjoint by the same rule, against the transposed extended-precision reference
     xa, _ = run(gpu, bands, f, p, k, adjoint=True)
-    refa = oracle.band_solve(bands, f, transpose=True)
-    assert rel(xa, refa) <= max(1e-12, 1e3 * rel(x0, ref))
+    refa = oracle.band_solve_refined(bands, f, steps=2, transpose=True)
+    x0a = oracle.band_solve(bands, f, transpose=True)
+    assert rel(xa, refa) <= max(1e-12, 10 * rel(x0a, refa))
 
 
 @pytest.mark.parametrize("n,k,p,r,m,rule", [
@@ -167,7 +169,8 @@ def test_mixed_interchange_partitions(gpu):
         x, info = run(gpu, bands, f, p, r)
         assert info["swapped_blocks"] > 0
         ref = oracle.lrspike(bands, f, p, r)
-        assert rel(x, ref) <= 1e-11
+        print(f"mixed interchange r={r}: rel {rel(x, ref):.2e}", flush=True)
+        assert rel(x, ref) <= 1e-12
 
 
 def _c2_problem(m):
