@@ -57,25 +57,40 @@ __device__ __forceinline__ void wave_fence() {  // order LDS accesses of one wav
 // ignored there: a non-finite pivot shows as a non-finite or zero reciprocal
 // dinv in its lane, which the callers test once per panel).
 template <typename T, int K, int C, int BW = K>
-struct FwdElim {
-  static __device__ __forceinline__ void run(T (&pa)[K], T (&iv)[K], int lane, int nr, T& mx, T& dmin, T& dinv) {
+struct FwdElimLA {
+  // d, inv: this step's pivot and its reciprocal, formed during the previous
+  // step as soon as the pivot's own entry was final (look-ahead: the division
+  // overlaps the rest of that step's updates instead of heading this one)
+  static __device__ __forceinline__ void run(T (&pa)[K], T (&iv)[K], int lane, int nr, T& mx, T& dmin, T& dinv,
+                                             T d, T inv) {
     if constexpr (C < K) {
       __builtin_amdgcn_sched_barrier(0);
-      const T d = bcast(pa[C], C);
-      const T inv = T(1) / d;  // uniform: one reciprocal per step
       if (lane == C) dinv = inv;
       dmin = fmin(dmin, fabs(d));
       const bool act = lane > C && lane < nr;
       const T l = act ? pa[C] * inv : T(0);
       mx = fmax(mx, fabs(l));
       if (act) pa[C] = l;
+      T dn = T(1), invn = T(1);
+      if constexpr (C + 1 < K) {
+        pa[C + 1] = fma(-l, bcast(pa[C + 1], C), pa[C + 1]);
+        dn = bcast(pa[C + 1], C + 1);
+        invn = T(1) / dn;
+      }
 #pragma unroll
-      for (int c = C + 1; c < K; ++c) pa[c] = fma(-l, bcast(pa[c], C), pa[c]);
+      for (int c = C + 2; c < K; ++c) pa[c] = fma(-l, bcast(pa[c], C), pa[c]);
 #pragma unroll
       for (int c = (C / BW) * BW; c < C; ++c) iv[c] = fma(-l, bcast(iv[c], C), iv[c]);
       iv[C] -= l;
-      FwdElim<T, K, C + 1, BW>::run(pa, iv, lane, nr, mx, dmin, dinv);
+      FwdElimLA<T, K, C + 1, BW>::run(pa, iv, lane, nr, mx, dmin, dinv, dn, invn);
     }
+  }
+};
+template <typename T, int K, int C, int BW = K>
+struct FwdElim {
+  static __device__ __forceinline__ void run(T (&pa)[K], T (&iv)[K], int lane, int nr, T& mx, T& dmin, T& dinv) {
+    const T d0 = bcast(pa[0], 0);
+    FwdElimLA<T, K, 0, BW>::run(pa, iv, lane, nr, mx, dmin, dinv, d0, T(1) / d0);
   }
 };
 
@@ -582,71 +597,85 @@ __global__ __launch_bounds__(64) void spike_wave_kernel(FactorArgs a) {
     rhs_w(1, w1);
   else
     zero_strip<T, K, MCT>(w1);
-  T lp[NF], gt[NF], lpn[NF], gtn[NF];
-  load_frags<T, K>(lp, fac);
-  load_frags<T, K>(gt, gm);
-  for (int b = 0; b < g.nb; ++b) {
-    const bool last = (b == g.nb - 1);
-    asm volatile("" : "+v"(lane));  // no lane-derived values kept across blocks
-    if (!last) {
-      load_frags<T, K>(lpn, fac + (size_t)(b + 1) * L.rec);
-      load_frags<T, K>(gtn, gm + (size_t)(b + 1) * K * K);
-    }
+  // L and G^T fragments in a prefetch ring (as in the solve sweeps): block q
+  // in slot q mod NS, every prefetch unconditional, the block loop unrolled
+  // over the slots; the last block, which also forms V, comes after the loop
+  constexpr int PD = sweep_pd<K, MCT>(), NS = PD + 1;
+  const int nb = g.nb;
+  T lpq[NS][NF], gtq[NS][NF];
+  auto fetch = [&](int q, T (&lp)[NF], T (&gt)[NF]) __attribute__((always_inline)) {
+    const int qc = min(q, nb - 1);
+    load_frags<T, K>(lp, fac + (size_t)qc * L.rec);
+    load_frags<T, K>(gt, gm + (size_t)qc * K * K);
+  };
+  static_for<PD>([&](auto U) __attribute__((always_inline)) {
+    constexpr int u = decltype(U)::value;
+    fetch(u, lpq[u], gtq[u]);
+  });
+  // blocks 0 .. nb-2: the right-hand side [C_j; 0] lives in blocks 0 and 1 only
+  auto body = [&](auto U, int b) __attribute__((always_inline)) {
+    constexpr int u = decltype(U)::value, uf = (u + PD) % NS;
+    fetch(b + PD, lpq[uf], gtq[uf]);
     zero_strip<T, K, MCT>(z);
-    blk_mul<T, K, MCT, 0>(lp, nullptr, T(1), w0, z);
-    if (!last) blk_mul<T, K, MCT, 1>(lp, nullptr, T(-1), z, w1);
-    blk_mul<T, K, MCT, 9>(gt, nullptr, T(1), z, acc);
+    blk_mul<T, K, MCT, 0>(lpq[u], nullptr, T(1), w0, z);
+    blk_mul<T, K, MCT, 1>(lpq[u], nullptr, T(-1), z, w1);
+    blk_mul<T, K, MCT, 9>(gtq[u], nullptr, T(1), z, acc);
     if (ym) {
       put_y(b, 0, z);
-      if (b == g.nb - 2) {  // V's forward result above the last block (zero here; read by the back-sweep)
+      if (b == nb - 2) {  // V's forward result above the last block (zero here; read by the back-sweep)
         V zz[W::RT][MCT];
         zero_strip<T, K, MCT>(zz);
         put_y(b, K, zz);
       }
     }
-    if (last) {
-      T up[NF];
-      load_frags<T, K>(up, fac + (size_t)b * L.rec + K * K);
-      V wb[W::RT][MCT], bv[W::RT][MCT], zv[W::RT][MCT], vb[W::RT][MCT], vt[W::RT][MCT];
-      zero_strip<T, K, MCT>(wb);
-      blk_mul<T, K, MCT, 2>(up, nullptr, T(1), z, wb);
-      // V spike in the last block
-#pragma unroll
-      for (int t = 0; t < W::RT; ++t)
-#pragma unroll
-        for (int ct = 0; ct < MCT; ++ct)
-#pragma unroll
-          for (int v = 0; v < 4; ++v) {
-            const int row = 16 * t + acc_row<T>(lane, v), col = 16 * ct + (lane & 15);
-            const int lr = b * K + row - g.pad;
-            bv[t][ct][v] = (j < L.p - 1 && lr >= 0) ? (T)band_at(a.bands, L.n, k, g.s + lr, g.s + g.nj + col) : T(0);
-          }
-      zero_strip<T, K, MCT>(zv);
-      blk_mul<T, K, MCT, 0>(lp, nullptr, T(1), bv, zv);
-      zero_strip<T, K, MCT>(vb);
-      blk_mul<T, K, MCT, 2>(up, nullptr, T(1), zv, vb);
-      zero_strip<T, K, MCT>(vt);
-      blk_mul<T, K, MCT, 9>(gt, nullptr, T(1), zv, vt);
-      if (ym) put_y(b, K, zv);
-      put(0, vt);
-      put(1, vb);
-      put(2, acc);
-      put(3, wb);
-    }
 #pragma unroll
     for (int t = 0; t < W::RT; ++t)
 #pragma unroll
       for (int ct = 0; ct < MCT; ++ct) w0[t][ct] = w1[t][ct];
-    if (b + 2 < g.nb)
-      rhs_w(b + 2, w1);  // only the first two blocks carry [C_j; 0]
-    else
-      zero_strip<T, K, MCT>(w1);
-    if (!last)
+    zero_strip<T, K, MCT>(w1);
+  };
+  int b0 = 0;
+  for (; b0 + NS <= nb - 1; b0 += NS)
+    static_for<NS>([&](auto U) __attribute__((always_inline)) { body(U, b0 + decltype(U)::value); });
+  static_for<NS>([&](auto U) __attribute__((always_inline)) {
+    if (b0 + decltype(U)::value < nb - 1) body(U, b0 + decltype(U)::value);
+  });
+  // last block: W's bottom tip and top tip, and the V spike (its right-hand
+  // side [0; B_j] lives in this block only)
+  {
+    const int b = nb - 1;
+    T lp[NF], gt[NF], up[NF];
+    load_frags<T, K>(lp, fac + (size_t)b * L.rec);
+    load_frags<T, K>(gt, gm + (size_t)b * K * K);
+    load_frags<T, K>(up, fac + (size_t)b * L.rec + K * K);
+    zero_strip<T, K, MCT>(z);
+    blk_mul<T, K, MCT, 0>(lp, nullptr, T(1), w0, z);
+    blk_mul<T, K, MCT, 9>(gt, nullptr, T(1), z, acc);
+    if (ym) put_y(b, 0, z);
+    V wb[W::RT][MCT], bv[W::RT][MCT], zv[W::RT][MCT], vb[W::RT][MCT], vt[W::RT][MCT];
+    zero_strip<T, K, MCT>(wb);
+    blk_mul<T, K, MCT, 2>(up, nullptr, T(1), z, wb);
 #pragma unroll
-      for (int f = 0; f < NF; ++f) {
-        lp[f] = lpn[f];
-        gt[f] = gtn[f];
-      }
+    for (int t = 0; t < W::RT; ++t)
+#pragma unroll
+      for (int ct = 0; ct < MCT; ++ct)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int row = 16 * t + acc_row<T>(lane, v), col = 16 * ct + (lane & 15);
+          const int lr = b * K + row - g.pad;
+          bv[t][ct][v] = (j < L.p - 1 && lr >= 0) ? (T)band_at(a.bands, L.n, k, g.s + lr, g.s + g.nj + col) : T(0);
+        }
+    zero_strip<T, K, MCT>(zv);
+    blk_mul<T, K, MCT, 0>(lp, nullptr, T(1), bv, zv);
+    zero_strip<T, K, MCT>(vb);
+    blk_mul<T, K, MCT, 2>(up, nullptr, T(1), zv, vb);
+    zero_strip<T, K, MCT>(vt);
+    blk_mul<T, K, MCT, 9>(gt, nullptr, T(1), zv, vt);
+    if (ym) put_y(b, K, zv);
+    put(0, vt);
+    put(1, vb);
+    put(2, acc);
+    put(3, wb);
   }
 }
 

@@ -795,86 +795,71 @@ __global__ __launch_bounds__(64) void adj_retrieve_wave_kernel(SolveArgs a) {
   tbwd_wave<T, K, 1, false>(a, g, j, c0);
 }
 
-// Factorization pass 2 for K >= 16 (r < k): back substitution of one spike
-// (blockIdx.y = 0: W, 1: V) over the stored forward intermediate Y,
-//   z_b = U11^{-1} (Y_b - U12 z_{b+1} - U13 z_{b+2}),
-// accumulating the Gram matrix z^T z on the matrix cores: the accumulator
-// tiles of z are at once the B operand and (tile-transposed) the A operand.
-template <typename T, int K>
-__global__ __launch_bounds__(64) void pass2_wave_kernel(FactorArgs a) {
+// Pass-2 back substitution of one spike (kernel below).  The q-th block
+// visited (b = nb - 1 - q) lives in ring slot q mod NS, as in the solve's
+// backward pass: records, U12 diagonals and Y strips are prefetched PD blocks
+// ahead with unconditional (clamped) loads.
+template <typename T, int K, bool SWP>
+__device__ void pass2_wave_impl(const FactorArgs& a, const Geom& g, int j, int spike) {
   constexpr int MCT = K / 16;
   using W = WaveSweep<T, K, MCT>;
   using V = typename W::V;
-  constexpr int NF = W::RT * W::KS;
+  constexpr int NF = W::RT * W::KS, PD = sweep_pd<K, MCT>(), NS = PD + 1;
   const Layout& L = a.L;
-  const int j = blockIdx.x, spike = blockIdx.y, lane = threadIdx.x & 63;
-  const Geom g = part_geom(L, j, K);
+  const int lane = threadIdx.x & 63, nb = g.nb;
   const T* fac = wsT<T>(a.ws, L.fac) + (size_t)j * L.nbmax * L.rec;
   const T* swx = wsT<T>(a.ws, L.swx) + (size_t)j * L.nbmax * 3 * K * K;
   const T* ym = wsT<T>(a.ws, L.ymat) + (size_t)j * L.nbmax * 2 * K * K;
   const int* flg = wsT<int>(a.ws, L.flag) + (size_t)j * L.nbmax;
-  // flags only for partitions factored with interchanges (zero elsewhere; a
-  // flag load consumed at once would stall every block)
-  const bool swp = wsT<int>(a.ws, L.npv)[j] != 0;
   const int coff = spike == 0 ? 0 : K;  // Y columns [W | V]
   // V's right-hand side lives in the last k rows: its forward result is zero
   // above the last two blocks (interchanges act within a block pair) and is
-  // neither stored nor read there
-  auto load_y = [&](int b, V (&st)[W::RT][MCT]) {
-    if (spike == 1 && b < g.nb - 2) {
-      zero_strip<T, K, MCT>(st);
-      return;
-    }
-#pragma unroll
-    for (int t = 0; t < W::RT; ++t)
-#pragma unroll
-      for (int ct = 0; ct < MCT; ++ct)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const int row = 16 * t + acc_row<T>(lane, v), col = 16 * ct + (lane & 15);
-          st[t][ct][v] = ym[(size_t)b * 2 * K * K + row * 2 * K + coff + col];
-        }
-  };
-  V x1[W::RT][MCT], x2[W::RT][MCT], zb[W::RT][MCT], zn[W::RT][MCT], xb[W::RT][MCT], gr[W::RT][W::RT];
+  // not stored there; those blocks read the strip of block nb - 2 (cached)
+  // and take zero instead
+  const int ymin = spike == 0 ? 0 : max(nb - 2, 0);
+  V x1[W::RT][MCT], x2[W::RT][MCT], xb[W::RT][MCT], zq[NS][W::RT][MCT], gr[W::RT][W::RT];
+  T upq[NS][NF], udq[NS][W::RT][4];
   zero_strip<T, K, MCT>(x1);
   zero_strip<T, K, MCT>(x2);
 #pragma unroll
   for (int ti = 0; ti < W::RT; ++ti)
 #pragma unroll
     for (int tj = 0; tj < W::RT; ++tj) gr[ti][tj] = V{0, 0, 0, 0};
-  // records and Y strips are fetched two blocks ahead (one wave per SIMD:
-  // one block of work does not cover the memory latency)
-  T up[NF], upn[NF], up2[NF], ud[W::RT][4], udn[W::RT][4], ud2[W::RT][4];
-  V zn2[W::RT][MCT];
-  int b = g.nb - 1;
-  load_frags<T, K>(up, fac + (size_t)b * L.rec + K * K);
-  load_udrows<T, K>(ud, fac + (size_t)b * L.rec + 2 * K * K);
-  int fl = swp ? flg[b] : 0;
-  load_y(b, zb);
-  int fln = 0, fl2 = 0;
-  if (b > 0) {
-    load_frags<T, K>(upn, fac + (size_t)(b - 1) * L.rec + K * K);
-    load_udrows<T, K>(udn, fac + (size_t)(b - 1) * L.rec + 2 * K * K);
-    fln = swp ? flg[b - 1] : 0;
-    load_y(b - 1, zn);
-  }
-  for (; b >= 0; --b) {
-    const bool last = (b == g.nb - 1);
-    if (b > 1) {
-      load_frags<T, K>(up2, fac + (size_t)(b - 2) * L.rec + K * K);
-      load_udrows<T, K>(ud2, fac + (size_t)(b - 2) * L.rec + 2 * K * K);
-      fl2 = swp ? flg[b - 2] : 0;
-      load_y(b - 2, zn2);
-    }
-    if (!last) {
-      if (fl & 2) {
+  auto fetch = [&](int q, T (&up)[NF], T (&ud)[W::RT][4], V (&zs)[W::RT][MCT]) __attribute__((always_inline)) {
+    const int b = max(nb - 1 - q, 0), by = max(b, ymin);
+    load_frags<T, K>(up, fac + (size_t)b * L.rec + K * K);
+    load_udrows<T, K>(ud, fac + (size_t)b * L.rec + 2 * K * K);
+    const T* yb = ym + (size_t)by * 2 * K * K + coff;
+#pragma unroll
+    for (int t = 0; t < W::RT; ++t)
+#pragma unroll
+      for (int ct = 0; ct < MCT; ++ct)
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+          zs[t][ct][v] = yb[(16 * t + acc_row<T>(lane, v)) * 2 * K + 16 * ct + (lane & 15)];
+  };
+  static_for<PD>([&](auto U) __attribute__((always_inline)) {
+    constexpr int u = decltype(U)::value;
+    fetch(u, upq[u], udq[u], zq[u]);
+  });
+  auto body = [&](auto U, int q) __attribute__((always_inline)) {
+    constexpr int u = decltype(U)::value, uf = (u + PD) % NS;
+    const int b = nb - 1 - q;
+    fetch(q + PD, upq[uf], udq[uf], zq[uf]);
+    T (&up)[NF] = upq[u];
+    V (&zb)[W::RT][MCT] = zq[u];
+    if (b < ymin) zero_strip<T, K, MCT>(zb);
+    if (q > 0) {
+      int fl = 0;
+      if constexpr (SWP) fl = flg[b];
+      if (SWP && (fl & 2)) {
         T u12[NF];
         load_frags<T, K>(u12, swx + (size_t)b * 3 * K * K + K * K);
         blk_mul<T, K, MCT, 9>(u12, nullptr, T(-1), x1, zb);
       } else {
-        u12_mul<T, K, MCT>(up, ud, x1, zb);
+        u12_mul<T, K, MCT>(up, udq[u], x1, zb);
       }
-      if (fl & 1) {
+      if (SWP && (fl & 1)) {
         T u13[NF];
         load_frags<T, K>(u13, swx + (size_t)b * 3 * K * K + 2 * K * K);
         blk_mul<T, K, MCT, 9>(u13, nullptr, T(-1), x2, zb);
@@ -896,24 +881,14 @@ __global__ __launch_bounds__(64) void pass2_wave_kernel(FactorArgs a) {
       for (int ct = 0; ct < MCT; ++ct) {
         x2[t][ct] = x1[t][ct];
         x1[t][ct] = xb[t][ct];
-        zb[t][ct] = zn[t][ct];
-        zn[t][ct] = zn2[t][ct];
       }
-#pragma unroll
-    for (int f = 0; f < NF; ++f) {
-      up[f] = upn[f];
-      upn[f] = up2[f];
-    }
-#pragma unroll
-    for (int t = 0; t < W::RT; ++t)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        ud[t][v] = udn[t][v];
-        udn[t][v] = ud2[t][v];
-      }
-    fl = fln;
-    fln = fl2;
-  }
+  };
+  int q0 = 0;
+  for (; q0 + NS <= nb; q0 += NS)
+    static_for<NS>([&](auto U) __attribute__((always_inline)) { body(U, q0 + decltype(U)::value); });
+  static_for<NS>([&](auto U) __attribute__((always_inline)) {
+    if (q0 + decltype(U)::value < nb) body(U, q0 + decltype(U)::value);
+  });
   // gram layout [GV | GW], K x K row-major each
   double* gram = wsT<double>(a.ws, L.gram) + ((size_t)j * 2 + (spike == 0 ? 1 : 0)) * K * K;
 #pragma unroll
@@ -927,6 +902,23 @@ __global__ __launch_bounds__(64) void pass2_wave_kernel(FactorArgs a) {
         gram[row * K + col] = (double)gr[ti][tj][v];
         if (tj > ti) gram[col * K + row] = (double)gr[ti][tj][v];
       }
+}
+
+// Factorization pass 2 for K >= 16 (r < k): back substitution of one spike
+// (blockIdx.y = 0: W, 1: V) over the stored forward intermediate Y,
+//   z_b = U11^{-1} (Y_b - U12 z_{b+1} - U13 z_{b+2}),
+// accumulating the Gram matrix z^T z on the matrix cores: the accumulator
+// tiles of z are at once the B operand and (tile-transposed) the A operand.
+// The interchange flags are read only for partitions factored with
+// interchanges (a compile-time variant: elsewhere they are all zero).
+template <typename T, int K>
+__global__ __launch_bounds__(64) void pass2_wave_kernel(FactorArgs a) {
+  const int j = blockIdx.x, spike = blockIdx.y;
+  const Geom g = part_geom(a.L, j, K);
+  if (wsT<int>(a.ws, a.L.npv)[j] != 0)
+    pass2_wave_impl<T, K, true>(a, g, j, spike);
+  else
+    pass2_wave_impl<T, K, false>(a, g, j, spike);
 }
 
 }  // namespace lrs
