@@ -286,6 +286,80 @@ def bench_batched(args):
     print(json.dumps(out))
 
 
+def bench_gradient(args):
+    """The differentiation workload: n = 2^20, k = 16, p = 256, r = 8, one
+    right-hand side, FP64.  One step = factor + x = A^{-1} b + the adjoint
+    lam = A^{-T} (x - x*) + grad_band = -lam x^T on the band, i.e. one
+    forward and backward of the loss 0.5 ||x - x*||^2.  At r < k the plan is
+    FP64-refined (M_r^{-1} preconditions the FP64 refinement forward and
+    backward, so the gradients are those of A^{-1} b); the one-shot operator
+    M_r^{-1} (plain FP64 plan, solve + adjoint + band product) is timed beside."""
+    import torch
+    import paper_2504_11167_amd as lr
+    import synth
+
+    n, k, p, r, m = 1 << 20, 16, 256, 8, 1
+    log = (lambda *a: None) if args.quiet else (lambda *a: print(*a, file=sys.stderr, flush=True))
+    bands_h, f_h = synth.make_problem(n, k, 2, seed=0, rule="weak")
+    dev = torch.device("cuda:0")
+    bands = torch.from_numpy(bands_h).to(dev)
+    b = torch.from_numpy(f_h[:, :1].copy()).to(dev)
+    xstar = torch.from_numpy(f_h[:, 1:2].copy()).to(dev)
+    del bands_h, f_h
+    stream = torch.cuda.current_stream()
+    res = {}
+    for prec in ("fp64_refined", "fp64"):
+        ws = torch.empty(lr.workspace_bytes(n, k, p, r, prec, m), dtype=torch.uint8, device=dev)
+        x = torch.empty_like(b)
+        lam = torch.empty_like(b)
+
+        def step():
+            x.copy_(b)
+            plan = lr.Plan(bands, p, r, precision=prec, max_nrhs=m, workspace=ws, refine_tol=1e-13)
+            plan.solve(x, inplace=True)
+            torch.sub(x, xstar, out=lam)
+            plan.solve_adjoint(lam, inplace=True)
+            plan.band_grad(lam, x)
+            return plan
+
+        for _ in range(args.warmup):
+            step().status()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(args.steps):
+            plan = step()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        info = plan.status()
+        ms = e0.elapsed_time(e1) / args.steps
+        res[prec] = {"ms_per_step": round(ms, 4), "refine_iters": info["refine_iters"]}
+        log(f"[bench] gradient workload {prec}: {ms:.3f} ms/step")
+        del ws, plan
+    ms_step = res["fp64_refined"]["ms_per_step"]
+    out = {
+        "metric": METRIC,
+        "value": n * m / (ms_step * 1e-3),
+        "unit": "rows*rhs/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"gradient: lrspike n={n} k={k} p={p} r={r} nrhs={m} weak-dominance, "
+                               f"factor + solve + adjoint + band gradient, fp64_refined",
+                   "n": n, "k": k, "p": p, "r": r, "nrhs": m},
+        "roofline": None,
+        "cpu_baseline": None,
+        "precisions": res,
+    }
+    print(json.dumps(out))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -295,8 +369,9 @@ def main():
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32_refined"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-refined", action="store_true", help="skip the refined-FP32 vs FP64 comparison")
-    ap.add_argument("--workload", default="large", choices=["large", "batched"],
-                    help="large: one n = 2^22 system (default); batched: the many-systems workload")
+    ap.add_argument("--workload", default="large", choices=["large", "batched", "gradient"],
+                    help="large: one n = 2^22 system (default); batched: the many-systems workload; "
+                         "gradient: the n = 2^20 differentiation workload")
     ap.add_argument("--systems", type=int, default=4096, help="batched workload: number of systems")
     ap.add_argument("--quiet", action="store_true")
     args = ap.parse_args()
@@ -307,6 +382,8 @@ def main():
 
     if args.workload == "batched":
         return bench_batched(args)
+    if args.workload == "gradient":
+        return bench_gradient(args)
 
     import numpy as np
     import torch
