@@ -18,6 +18,10 @@ A plain C implementation of what the banded LR-SPIKE method computes
                       condition number (residual in long double).
 * ``bicgstab``        BiCGStab right-preconditioned by the LR-SPIKE operator,
                       the outer Krylov solver of the paper's experiments.
+* ``lrspike_rsvd``    R1 / R3 with the spikes truncated through the randomized
+                      SVD (Halko-Martinsson-Tropp proto-algorithm, caller-drawn
+                      Gaussian test matrices); ``rsvd_project`` is its range
+                      finder Q Q^T a.
 * ``reduced_dense``, ``partition_spikes``, ``thin_svd``, ``band_matvec``,
   ``band_grad`` and ``partition`` expose the intermediate objects the pins test.
 
@@ -53,6 +57,8 @@ def _load():
         lib.orc_partition.restype = None
         lib.orc_thin_svd.argtypes = [i64, i32, _D, _D, _D]
         lib.orc_lrspike.argtypes = [i64, i32, _D, i32, i32, i32, _D, _D, i32, _D, i32, i32]
+        lib.orc_lrspike_rsvd.argtypes = [i64, i32, _D, i32, i32, i32, _D, _D, i32, _D, i32, i32, i32, i32, _D]
+        lib.orc_rsvd_project.argtypes = [i64, i32, _D, i32, i32, _D, _D]
         lib.orc_reduced_dense.argtypes = [i64, i32, _D, i32, i32, _D]
         lib.orc_partition_spikes.argtypes = [i64, i32, _D, i32, i32, _D, _D]
         lib.orc_bicgstab.argtypes = [i64, i32, _D, i32, i32, i32, i32, _D, _D, ctypes.c_double, i32, i32,
@@ -145,6 +151,40 @@ def lrspike(bands, f, p, r, transpose=False, return_sv=False, threads=0, variant
     _check(rc, "lrspike")
     x = x[:, 0] if flat else x
     return (x, sv) if return_sv else x
+
+
+def lrspike_rsvd(bands, f, p, r, omega, q=0, transpose=False, return_sv=False, threads=0, variant="full"):
+    """R1 / R3 with every spike truncated through the randomized SVD (the
+    proto-algorithm of Halko, Martinsson and Tropp): omega holds the Gaussian
+    test matrices, shape (p, 2, k, ell) (V_j then W_j of each partition), q
+    the power steps.  Needs r < k."""
+    bands, n, k = _band_args(bands)
+    f2, flat = _as2d(f)
+    om = _f64(omega)
+    if om.ndim != 4 or om.shape[:3] != (p, 2, k):
+        raise ValueError("omega must have shape (p, 2, k, ell)")
+    ell = om.shape[3]
+    x = np.empty_like(f2)
+    sv = np.zeros((p, 2, k))
+    rc = _load().orc_lrspike_rsvd(n, k, _p(bands), p, r, f2.shape[1], _p(f2), _p(x), int(transpose), _p(sv),
+                                  threads, _VARIANTS[variant], ell, q, _p(om))
+    _check(rc, "lrspike_rsvd")
+    x = x[:, 0] if flat else x
+    return (x, sv) if return_sv else x
+
+
+def rsvd_project(a, omega, q=0):
+    """Q Q^T a for Q an orthonormal basis of range((a a^T)^q a omega): the
+    randomized range finder of the spike truncation."""
+    a = _f64(a)
+    om = _f64(omega)
+    rows, cols = a.shape
+    ell = om.shape[1]
+    if om.shape[0] != cols:
+        raise ValueError("omega must have a.shape[1] rows")
+    out = np.empty_like(a)
+    _check(_load().orc_rsvd_project(rows, cols, _p(a), ell, q, _p(om), _p(out)), "rsvd_project")
+    return out
 
 
 def bicgstab(bands, f, p, r, tol=1e-13, max_it=200, transpose=False, variant="full", threads=0):

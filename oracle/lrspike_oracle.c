@@ -349,6 +349,103 @@ int orc_thin_svd(int64_t rows, int cols, const double *a, double *sigma, double 
 }
 
 /* ------------------------------------------------------------------------ */
+/* Randomized SVD of a spike (section "SVD representation of the spikes":    */
+/* the proto-algorithm of Halko, Martinsson and Tropp with a few passes over  */
+/* the matrix and oversampling).  For the tall rows x cols matrix a and the  */
+/* Gaussian test matrix omega (cols x ell, row-major, drawn by the caller):  */
+/*   Y = (a a^T)^q a omega          (q power steps, 2 + 2q passes over a)    */
+/*   Q = orthonormal basis of range(Y)  (Householder QR of Y)                */
+/*   B = Q^T a,   a ~ Q B = Q Q^T a                                          */
+/* The SVD of B gives the approximate singular triplets of a: Q U_B, S_B and */
+/* V_B.  Q B has the same singular values and right singular vectors as B,   */
+/* so a is replaced here by Q Q^T a (written to proj, rows x cols) and the   */
+/* caller takes the thin SVD of that, exactly as for the whole spike.        */
+/* ------------------------------------------------------------------------ */
+int orc_rsvd_project(int64_t rows, int cols, const double *a, int ell, int q, const double *omega,
+                     double *proj) {
+  if (rows < 1 || cols < 1 || ell < 1 || ell > cols || ell > rows || q < 0) return -1;
+  double *Y = (double *)calloc((size_t)(rows * ell), sizeof(double));
+  double *Z = (double *)calloc((size_t)cols * ell, sizeof(double));
+  double *H = (double *)calloc((size_t)(rows * ell), sizeof(double)); /* reflectors */
+  double *hv = (double *)calloc((size_t)ell, sizeof(double));         /* v^T v of each */
+  double *Q = (double *)calloc((size_t)(rows * ell), sizeof(double));
+  if (!Y || !Z || !H || !hv || !Q) return -100;
+  /* Y = a omega */
+  for (int64_t i = 0; i < rows; ++i)
+    for (int c = 0; c < ell; ++c) {
+      double acc = 0.0;
+      for (int b = 0; b < cols; ++b) acc += a[i * cols + b] * omega[b * ell + c];
+      Y[i * ell + c] = acc;
+    }
+  /* power steps: Z = a^T Y, Y = a Z */
+  for (int it = 0; it < q; ++it) {
+    for (int b = 0; b < cols; ++b)
+      for (int c = 0; c < ell; ++c) {
+        double acc = 0.0;
+        for (int64_t i = 0; i < rows; ++i) acc += a[i * cols + b] * Y[i * ell + c];
+        Z[b * ell + c] = acc;
+      }
+    for (int64_t i = 0; i < rows; ++i)
+      for (int c = 0; c < ell; ++c) {
+        double acc = 0.0;
+        for (int b = 0; b < cols; ++b) acc += a[i * cols + b] * Z[b * ell + c];
+        Y[i * ell + c] = acc;
+      }
+  }
+  /* Householder QR of Y: reflector c zeroes column c below the diagonal */
+  for (int c = 0; c < ell; ++c) {
+    double nrm = 0.0;
+    for (int64_t i = c; i < rows; ++i) nrm += Y[i * ell + c] * Y[i * ell + c];
+    nrm = sqrt(nrm);
+    hv[c] = 0.0;
+    if (nrm == 0.0) continue; /* column already zero: H_c = I */
+    double alpha = Y[c * ell + c] > 0 ? -nrm : nrm;
+    for (int64_t i = c; i < rows; ++i) H[i * ell + c] = Y[i * ell + c];
+    H[c * ell + c] -= alpha;
+    double vv = 0.0;
+    for (int64_t i = c; i < rows; ++i) vv += H[i * ell + c] * H[i * ell + c];
+    hv[c] = vv;
+    if (vv == 0.0) continue;
+    for (int cc = c; cc < ell; ++cc) {
+      double t = 0.0;
+      for (int64_t i = c; i < rows; ++i) t += H[i * ell + c] * Y[i * ell + cc];
+      t = 2.0 * t / vv;
+      for (int64_t i = c; i < rows; ++i) Y[i * ell + cc] -= t * H[i * ell + c];
+    }
+  }
+  /* Q = H_0 H_1 ... H_{ell-1} [I_ell; 0] (orthonormal columns in every case) */
+  for (int c = 0; c < ell; ++c) Q[c * ell + c] = 1.0;
+  for (int c = ell - 1; c >= 0; --c) {
+    if (hv[c] == 0.0) continue;
+    for (int cc = 0; cc < ell; ++cc) {
+      double t = 0.0;
+      for (int64_t i = c; i < rows; ++i) t += H[i * ell + c] * Q[i * ell + cc];
+      t = 2.0 * t / hv[c];
+      for (int64_t i = c; i < rows; ++i) Q[i * ell + cc] -= t * H[i * ell + c];
+    }
+  }
+  /* B = Q^T a (ell x cols, in Z's storage), proj = Q B */
+  for (int c = 0; c < ell; ++c)
+    for (int b = 0; b < cols; ++b) {
+      double acc = 0.0;
+      for (int64_t i = 0; i < rows; ++i) acc += Q[i * ell + c] * a[i * cols + b];
+      Z[c * cols + b] = acc;
+    }
+  for (int64_t i = 0; i < rows; ++i)
+    for (int b = 0; b < cols; ++b) {
+      double acc = 0.0;
+      for (int c = 0; c < ell; ++c) acc += Q[i * ell + c] * Z[c * cols + b];
+      proj[i * cols + b] = acc;
+    }
+  free(Y);
+  free(Z);
+  free(H);
+  free(hv);
+  free(Q);
+  return 0;
+}
+
+/* ------------------------------------------------------------------------ */
 /* Literal LR-SPIKE (paper: SPIKE partitioning, the DS factorization, the    */
 /* spikes, the reduced system, recovery; low-rank SVD representation of the  */
 /* spikes).                                                                  */
@@ -400,7 +497,7 @@ static void project_tip(int k, int r, const double *vr, double *tip) {
 
 /* Factorization stage.  Returns 0, >0 on a zero pivot, <0 on bad input. */
 static int plan_build(orc_plan *P, int64_t n, int k, const double *bands, int p,
-                      int r, int variant, int nthreads) {
+                      int r, int variant, int nthreads, int ell, int q, const double *omega) {
   memset(P, 0, sizeof(*P));
   if (n < 1 || k < 1 || p < 1 || r < 0 || r > k) return -1;
   P->n = n;
@@ -461,13 +558,21 @@ static int plan_build(orc_plan *P, int64_t n, int k, const double *bands, int p,
             sp[a * k + b] = Cj[a * k + b];
         }
       gb_solve(&P->A[j], k, sp);
+      if (omega && r < k) {
+        /* randomized SVD: the spike is replaced by its projection Q Q^T sp
+         * onto the sketched range, whose thin SVD below is that of B */
+        double *pr = (double *)malloc(sizeof(double) * (size_t)(nj * k));
+        if (orc_rsvd_project(nj, k, sp, ell, q, omega + ((size_t)j * 2 + which) * k * ell, pr)) bad |= 4;
+        memcpy(sp, pr, sizeof(double) * (size_t)(nj * k));
+        free(pr);
+      }
       double *top = (which == 0 ? P->Vt : P->Wt) + kk * j;
       double *bot = (which == 0 ? P->Vb : P->Wb) + kk * j;
       memcpy(top, sp, sizeof(double) * kk);
       memcpy(bot, sp + (nj - k) * k, sizeof(double) * kk);
       /* Rank-r truncation of the whole spike (low-rank SVD representation):
        * the tips of u~ Sigma~ v~ equal tip * Pi Pi^T, Pi = leading right
-       * singular vectors. */
+       * singular vectors (of Q Q^T sp with the randomized SVD). */
       orc_thin_svd(nj, k, sp, P->sv + (size_t)j * 2 * k + (size_t)which * k, vr);
       if (r < k) {
         project_tip(k, r, vr, top);
@@ -635,14 +740,20 @@ static void plan_solve_t(orc_plan *P, int m, const double *g, double *lam) {
  * solve-based recovery.
  * sv (nullable) receives the singular values of every spike, p x 2 x k
  * (V_j then W_j, descending; zeros for the absent V_{p-1} and W_0).
+ * orc_lrspike_rsvd: with omega (p x 2 x k x ell Gaussian test matrices, V_j
+ * then W_j of every partition) and r < k, every spike is truncated through
+ * the randomized SVD (orc_rsvd_project, ell columns, q power steps) instead
+ * of its exact SVD; sv then holds the singular values of Q Q^T spike.
  */
-int orc_lrspike(int64_t n, int k, const double *bands, int p, int r, int m,
-                const double *f, double *x, int transpose, double *sv, int nthreads,
-                int variant) {
+int orc_lrspike_rsvd(int64_t n, int k, const double *bands, int p, int r, int m,
+                     const double *f, double *x, int transpose, double *sv, int nthreads,
+                     int variant, int ell, int q, const double *omega) {
   if (m < 1) return -6;
   if (variant != 0 && variant != 1) return -12;
+  if (omega && (ell < 1 || ell > k)) return -13;
+  if (omega && q < 0) return -14;
   orc_plan P;
-  int rc = plan_build(&P, n, k, bands, p, r, variant, nthreads);
+  int rc = plan_build(&P, n, k, bands, p, r, variant, nthreads, ell, q, omega);
   if (rc) return rc;
   if (sv) memcpy(sv, P.sv, sizeof(double) * (size_t)p * 2 * k);
   if (transpose)
@@ -651,6 +762,12 @@ int orc_lrspike(int64_t n, int k, const double *bands, int p, int r, int m,
     plan_solve(&P, m, f, x);
   plan_free(&P);
   return 0;
+}
+
+int orc_lrspike(int64_t n, int k, const double *bands, int p, int r, int m,
+                const double *f, double *x, int transpose, double *sv, int nthreads,
+                int variant) {
+  return orc_lrspike_rsvd(n, k, bands, p, r, m, f, x, transpose, sv, nthreads, variant, 0, 0, NULL);
 }
 
 /*
@@ -681,7 +798,7 @@ int orc_bicgstab(int64_t n, int k, const double *bands, int p, int r, int varian
   if (m < 1 || max_it < 0) return -7;
   if (variant != 0 && variant != 1) return -6;
   orc_plan P;
-  int rc = plan_build(&P, n, k, bands, p, r, variant, nthreads);
+  int rc = plan_build(&P, n, k, bands, p, r, variant, nthreads, 0, 0, NULL);
   if (rc) return rc;
   size_t nm = (size_t)(n * m);
   double *rv = (double *)malloc(sizeof(double) * nm), *rh = (double *)malloc(sizeof(double) * nm);
@@ -756,7 +873,7 @@ int orc_bicgstab(int64_t n, int k, const double *bands, int p, int r, int varian
 /* The dense reduced system S~_red (order 2kp, row-major) at rank r. */
 int orc_reduced_dense(int64_t n, int k, const double *bands, int p, int r, double *S) {
   orc_plan P;
-  int rc = plan_build(&P, n, k, bands, p, r, 0, 1);
+  int rc = plan_build(&P, n, k, bands, p, r, 0, 1, 0, 0, NULL);
   if (rc) return rc;
   int64_t N = 2 * (int64_t)k * p;
   memset(S, 0, sizeof(double) * (size_t)(N * N));

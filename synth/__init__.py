@@ -79,3 +79,10 @@ def batched_systems(count=4096, seed=0):
         m = int(rng.integers(1, 33))
         out.append((n, k, k // 2, m, (seed, s)))
     return out
+
+
+def gaussian_test_matrices(p, k, ell, seed=0):
+    """Gaussian test matrices of the randomized spike SVD, shape (p, 2, k, ell):
+    [j, 0] for the spike V_j, [j, 1] for W_j, entries N(0, 1) from
+    default_rng([seed, 7])."""
+    return np.random.default_rng([seed, 7]).standard_normal((p, 2, k, ell))

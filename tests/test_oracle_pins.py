@@ -624,3 +624,111 @@ def test_bicgstab_converges_where_refinement_does_not():
         assert rel(xb, xs) < 1e-9
         true_res = np.linalg.norm(f - oracle.band_matvec(bands, xb), axis=0) / np.linalg.norm(f, axis=0)
         assert true_res.max() < 1e-12
+
+
+# ---------------------------------------------------------------- randomized SVD
+def _spectrum_matrix(rows, cols, sig, seed):
+    """rows x cols with singular values sig (descending) and random singular vectors."""
+    rng = np.random.default_rng(seed)
+    u, _ = np.linalg.qr(rng.standard_normal((rows, cols)))
+    v, _ = np.linalg.qr(rng.standard_normal((cols, cols)))
+    return (u * sig) @ v.T
+
+
+def test_rsvd_full_sketch_keeps_the_matrix():
+    """ell = cols: the test matrix is square and invertible, range(Y) = range(a)
+    and Q Q^T a = a."""
+    rng = np.random.default_rng(1)
+    a = _spectrum_matrix(400, 12, 0.3 ** np.arange(12), 2)
+    pr = oracle.rsvd_project(a, rng.standard_normal((12, 12)))
+    assert np.abs(pr - a).max() < 1e-12 * np.abs(a).max()
+
+
+@pytest.mark.parametrize("rank,ell,q", [(3, 5, 0), (6, 6, 0), (4, 8, 1)])
+def test_rsvd_exact_on_low_rank(rank, ell, q):
+    """rank(a) <= ell: the sketch spans range(a), so the projection is a itself."""
+    rng = np.random.default_rng(rank)
+    a = rng.standard_normal((300, rank)) @ rng.standard_normal((rank, 16))
+    pr = oracle.rsvd_project(a, rng.standard_normal((16, ell)), q=q)
+    assert np.abs(pr - a).max() < 1e-11 * np.abs(a).max()
+
+
+@pytest.mark.parametrize("seed", range(4))
+@pytest.mark.parametrize("decay", [0.5, 0.9])
+def test_rsvd_projection_properties_and_hmt_bound(seed, decay):
+    """Q Q^T a is an orthogonal projection of a onto an ell-dimensional space:
+    rank <= ell, a - proj orthogonal to proj, error >= sigma_{ell+1}
+    (Eckart-Young), and the Halko-Martinsson-Tropp bound
+    ||a - Q Q^T a|| <= (1 + 11 sqrt(kk + s) sqrt(min(m, n))) sigma_{kk+1}
+    for oversampling s >= 4 (failure probability 6 s^-s)."""
+    rows, cols, kk, s = 500, 24, 6, 4
+    sig = decay ** np.arange(cols)
+    a = _spectrum_matrix(rows, cols, sig, 10 + seed)
+    om = np.random.default_rng(100 + seed).standard_normal((cols, kk + s))
+    pr = oracle.rsvd_project(a, om)
+    sp = np.linalg.svd(pr, compute_uv=False)
+    assert sp[kk + s] < 1e-12 * sp[0]
+    assert np.abs(pr.T @ (a - pr)).max() < 1e-12 * sig[0] ** 2
+    err = np.linalg.norm(a - pr, 2)
+    assert err >= sig[kk + s] * (1 - 1e-9)
+    assert err <= (1 + 11 * np.sqrt(kk + s) * np.sqrt(min(rows, cols))) * sig[kk]
+
+
+def test_rsvd_power_steps_sharpen_a_flat_spectrum():
+    """With a slowly decaying spectrum each power step brings the error
+    closer to the optimum sigma_{ell+1}."""
+    sig = 1.0 / (1.0 + np.arange(32))
+    a = _spectrum_matrix(600, 32, sig, 5)
+    om = np.random.default_rng(6).standard_normal((32, 8))
+    errs = [np.linalg.norm(a - oracle.rsvd_project(a, om, q=q), 2) for q in (0, 1, 2)]
+    assert errs[2] < errs[1] < errs[0]
+    assert errs[2] < 1.5 * sig[8]
+
+
+def test_rsvd_lrspike_full_sketch_is_the_exact_truncation():
+    """ell = k: the randomized truncation is the exact rank-r truncation of the
+    whole spike (LR-SPIKE at rank r with its thin SVD)."""
+    n, k, p, r = 1200, 8, 4, 3
+    bands, f = synth.make_problem(n, k, 2, seed=3, rule="weak")
+    om = synth.gaussian_test_matrices(p, k, k, seed=1)
+    xe = oracle.lrspike(bands, f, p, r)
+    xr = oracle.lrspike_rsvd(bands, f, p, r, om)
+    assert rel(xr, xe) < 1e-10
+
+
+@pytest.mark.parametrize("k,r,ell,p", [(6, 2, 3, 4), (8, 3, 5, 3)])
+def test_rsvd_lrspike_exact_when_coupling_rank_le_ell(k, r, ell, p):
+    """Couplings of rank <= r <= ell: the spikes have rank <= r, the sketch
+    captures them whole and LR-SPIKE returns A^{-1} f."""
+    bands, f = synth.make_problem(100 * p, k, 2, seed=9, rule="strict")
+    bands = _low_rank_coupling(bands, p, r)
+    om = synth.gaussian_test_matrices(p, k, ell, seed=2)
+    assert rel(oracle.lrspike_rsvd(bands, f, p, r, om), oracle.band_solve(bands, f)) < 1e-12
+
+
+def test_rsvd_lrspike_between_exact_truncation_and_sketch_error():
+    """r < ell < k on a weakly dominant band: the randomized truncation stays
+    close to the exact one (within the tips' sketch error) and differs from it."""
+    n, k, p, r, ell = 2000, 12, 5, 4, 7
+    bands, f = synth.make_problem(n, k, 1, seed=11, rule="weak")
+    om = synth.gaussian_test_matrices(p, k, ell, seed=3)
+    xe, sve = oracle.lrspike(bands, f, p, r, return_sv=True)
+    xr, svr = oracle.lrspike_rsvd(bands, f, p, r, om, return_sv=True)
+    x0 = oracle.band_solve(bands, f)
+    d = rel(xr, xe)
+    assert 1e-14 < d < 10 * rel(xe, x0) + 1e-12
+    # the sketched spikes' leading singular values approach the exact ones
+    act = sve[:, :, 0] > 0
+    assert np.all(np.abs(svr[:, :, :r] - sve[:, :, :r])[act] <= 0.2 * sve[:, :, :r][act])
+
+
+@pytest.mark.parametrize("variant", ["full", "t"])
+def test_rsvd_lrspike_adjoint_dot_product(variant):
+    """<M^{-1} f, g> = <f, M^{-T} g> for the randomized operator too."""
+    n, k, p, r, ell = 900, 6, 3, 2, 4
+    bands, fg = synth.make_problem(n, k, 2, seed=12, rule="weak")
+    om = synth.gaussian_test_matrices(p, k, ell, seed=4)
+    f, g = fg[:, 0], fg[:, 1]
+    x = oracle.lrspike_rsvd(bands, f, p, r, om, variant=variant)
+    lam = oracle.lrspike_rsvd(bands, g, p, r, om, variant=variant, transpose=True)
+    assert abs(x @ g - f @ lam) < 1e-12 * np.linalg.norm(x) * np.linalg.norm(g)
