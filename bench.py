@@ -373,6 +373,10 @@ def main():
                     help="large: one n = 2^22 system (default); batched: the many-systems workload; "
                          "gradient: the n = 2^20 differentiation workload")
     ap.add_argument("--systems", type=int, default=4096, help="batched workload: number of systems")
+    ap.add_argument("--svd", default="exact", choices=["exact", "randomized"],
+                    help="spike truncation: exact (whole spike) or the randomized SVD")
+    ap.add_argument("--rsvd-ell", type=int, default=0, help="randomized SVD sketch columns (default 2r)")
+    ap.add_argument("--rsvd-power", type=int, default=0, help="randomized SVD power steps")
     ap.add_argument("--quiet", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -398,14 +402,19 @@ def main():
     bands = torch.from_numpy(bands_h).to(dev)
     f = torch.from_numpy(f_h).to(dev)
     del bands_h, f_h
-    nbytes = lr.workspace_bytes(n, k, p, r, args.precision, m)
+    svd_kw = {}
+    if args.svd == "randomized":
+        ell = args.rsvd_ell or min(k, 2 * r)
+        svd_kw = {"svd": "randomized", "rsvd_ell": ell, "rsvd_power": args.rsvd_power,
+                  "rsvd_omega": torch.from_numpy(synth.gaussian_test_matrices(p, k, ell, seed=0)).to(dev)}
+    nbytes = lr.workspace_bytes(n, k, p, r, args.precision, m, args.svd, svd_kw.get("rsvd_ell", 0))
     ws = torch.empty(nbytes, dtype=torch.uint8, device=dev)
     x = torch.empty_like(f)
     log(f"[bench] workspace {nbytes / 2**30:.2f} GiB")
 
     def step(profile):
         x.copy_(f)
-        plan = lr.Plan(bands, p, r, precision=args.precision, max_nrhs=m, workspace=ws, profile=profile)
+        plan = lr.Plan(bands, p, r, precision=args.precision, max_nrhs=m, workspace=ws, profile=profile, **svd_kw)
         plan.solve(x, inplace=True)
         return plan
 
@@ -449,7 +458,7 @@ def main():
     f0, f1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     f0.record(stream)
     for _ in range(args.steps):
-        plan = lr.Plan(bands, p, r, precision=args.precision, max_nrhs=m, workspace=ws)
+        plan = lr.Plan(bands, p, r, precision=args.precision, max_nrhs=m, workspace=ws, **svd_kw)
     f1.record(stream)
     torch.cuda.synchronize()
     ms_factor = f0.elapsed_time(f1) / args.steps
@@ -497,7 +506,7 @@ def main():
               for ph, t in (("factor", ms_factor), ("solve", ms_solve))}
 
     comp = None
-    if not args.no_refined and args.precision == "fp64":
+    if not args.no_refined and args.precision == "fp64" and args.svd == "exact":
         del plan, ws
         comp = refined_vs_fp64(lr, bands, f, x, lambda prec: lr.workspace_bytes(n, k, p, k, prec, m), p,
                                max(2, args.steps // 2), log)
@@ -516,8 +525,9 @@ def main():
         "vs_baseline": None,
         "dtype": "f64" if args.precision == "fp64" else "f32+f64",
         "data": "synthetic",
-        "config": {"workload": f"lrspike n={n} k={k} p={p} r={r} nrhs={m} weak-dominance {args.precision}",
-                   "n": n, "k": k, "p": p, "r": r, "nrhs": m, "precision": args.precision},
+        "config": {"workload": f"lrspike n={n} k={k} p={p} r={r} nrhs={m} weak-dominance {args.precision}"
+                               + (f" randomized-svd ell={svd_kw['rsvd_ell']} q={args.rsvd_power}" if svd_kw else ""),
+                   "n": n, "k": k, "p": p, "r": r, "nrhs": m, "precision": args.precision, "svd": args.svd},
         "roofline": roof,
         "cpu_baseline": cpu,
         "ms_per_step_without_launch_events": round(ms_step_plain, 4),

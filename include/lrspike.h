@@ -85,6 +85,19 @@ enum {
   LRSPIKE_ERR_WORKSPACE = 7         /* workspace missing or too small */
 };
 
+/* How a spike is truncated to rank r (section "SVD representation of the
+ * spikes"). */
+enum {
+  LRSPIKE_SVD_EXACT = 0,     /* rank-r truncation of the whole spike (its Gram's leading eigenvectors) */
+  LRSPIKE_SVD_RANDOMIZED = 1 /* the randomized SVD the paper uses (the proto-algorithm of Halko,
+                                Martinsson and Tropp): the spike is sketched with ell = rsvd_ell
+                                columns, Y = (V V^T)^q V Omega, by q + 1 block solves with 2 ell
+                                right-hand sides and as many adjoint ones; V is replaced by its
+                                projection Q Q^T V onto range(Y), which is then truncated like
+                                the whole spike.  Omega: Gaussian test matrices supplied by the
+                                caller.  Only at 0 < r < k; not for batched plans */
+};
+
 typedef struct {
   int32_t precision;     /* LRSPIKE_FP64 (default), LRSPIKE_FP32_REFINED or LRSPIKE_FP64_REFINED */
   int32_t max_refine;    /* refined precisions: max corrections (default 30).  The stopping rule
@@ -109,6 +122,15 @@ typedef struct {
   int32_t profile;       /* nonzero: time every kernel launch of this plan with a HIP
                             event pair on the plan's stream (see lrspike_profile_read) */
   int32_t variant;       /* LRSPIKE_VARIANT_FULL (default) or LRSPIKE_VARIANT_T */
+  int32_t svd;           /* LRSPIKE_SVD_EXACT (default) or LRSPIKE_SVD_RANDOMIZED */
+  int32_t rsvd_ell;      /* randomized SVD: sketch columns ell, r <= ell <= k (the paper oversamples
+                            by r/2 to r: ell = 1.5 r .. 2 r) */
+  int32_t rsvd_power;    /* randomized SVD: power steps q, 0..4 (2 + 2q passes over each spike) */
+  const double *rsvd_omega; /* randomized SVD: device array p x 2 x k x ell, row-major: the
+                            Gaussian test matrix (k x ell) of V_j, then that of W_j, for every
+                            partition j (those of V_{p-1} and W_0 are not read).  Borrowed:
+                            read by the factorization's kernels on the plan's stream, so it
+                            must stay valid until that work has completed */
 } lrspike_opts;
 
 /* Fill *opts with the defaults above (no workspace, null stream). */
@@ -120,6 +142,16 @@ void lrspike_default_opts(lrspike_opts *opts);
  */
 int lrspike_workspace_size(int64_t n, int32_t k, int32_t p, int32_t r,
                            int32_t precision, int32_t max_nrhs, size_t *bytes);
+
+/*
+ * The same for a full option set (precision, max_nrhs, variant and the spike
+ * truncation; the randomized SVD adds the n x 2 ell sketch and needs at least
+ * 2 ell solve columns).  lrspike_workspace_size equals this with the other
+ * options at their defaults.  Pure host computation.  Returns 0 or a negative
+ * argument code (-5: invalid options).
+ */
+int lrspike_workspace_size_opts(int64_t n, int32_t k, int32_t p, int32_t r, const lrspike_opts *opts,
+                                size_t *bytes);
 
 /*
  * Factorization stage (section "SPIKE partitioning", the DS factorization,
@@ -141,7 +173,8 @@ int lrspike_workspace_size(int64_t n, int32_t k, int32_t p, int32_t r,
  *          when p > 1
  *   r      retained singular values per spike (the paper's n_svd), 0 <= r <= k;
  *          with p > 1 the interface blocks need 2r <= 64 (2K <= 64 when r = k)
- *   opts   options; workspace required (see lrspike_workspace_size)
+ *   opts   options; workspace required (see lrspike_workspace_size, or
+ *          lrspike_workspace_size_opts with the randomized spike SVD)
  *   plan_out  receives a new plan (host object) on success
  */
 int lrspike_factor(int64_t n, int32_t k, const double *bands, int32_t p, int32_t r,

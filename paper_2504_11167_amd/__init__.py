@@ -29,6 +29,8 @@ _PRECISIONS = {"fp64": FP64, "fp32_refined": FP32_REFINED, "fp64_refined": FP64_
                "fp64_bicgstab": FP64_BICGSTAB, "fp32_bicgstab": FP32_BICGSTAB}
 VARIANT_FULL, VARIANT_T = 0, 1
 _VARIANTS = {"full": VARIANT_FULL, "t": VARIANT_T}
+SVD_EXACT, SVD_RANDOMIZED = 0, 1
+_SVDS = {"exact": SVD_EXACT, "randomized": SVD_RANDOMIZED}
 _ERRORS = {
     1: "ZERO_PIVOT", 2: "REDUCED_SINGULAR", 3: "NOT_CONVERGED", 4: "NONFINITE",
     5: "HIP_ERROR", 6: "NOT_SUPPORTED", 7: "WORKSPACE",
@@ -53,6 +55,10 @@ class _Opts(ctypes.Structure):
         ("max_nrhs", ctypes.c_int32),
         ("profile", ctypes.c_int32),
         ("variant", ctypes.c_int32),
+        ("svd", ctypes.c_int32),
+        ("rsvd_ell", ctypes.c_int32),
+        ("rsvd_power", ctypes.c_int32),
+        ("rsvd_omega", ctypes.c_void_p),
     ]
 
 
@@ -85,7 +91,7 @@ class _BatchDesc(ctypes.Structure):
 
 _lib = None
 SYMBOLS = (
-    "lrspike_default_opts", "lrspike_workspace_size", "lrspike_factor", "lrspike_solve",
+    "lrspike_default_opts", "lrspike_workspace_size", "lrspike_workspace_size_opts", "lrspike_factor", "lrspike_solve",
     "lrspike_solve_adjoint", "lrspike_band_grad", "lrspike_status", "lrspike_destroy",
     "lrspike_strerror", "lrspike_profile", "lrspike_profile_read", "lrspike_factor_batched",
     "lrspike_solve_batched", "lrspike_run_batched", "lrspike_batch_partitions", "lrspike_solve_noalloc",
@@ -110,6 +116,8 @@ def load_library():
     lib.lrspike_default_opts.argtypes = [ctypes.POINTER(_Opts)]
     lib.lrspike_default_opts.restype = None
     lib.lrspike_workspace_size.argtypes = [i64, i32, i32, i32, i32, i32, ctypes.POINTER(ctypes.c_size_t)]
+    lib.lrspike_workspace_size_opts.argtypes = [i64, i32, i32, i32, ctypes.POINTER(_Opts),
+                                                ctypes.POINTER(ctypes.c_size_t)]
     lib.lrspike_factor.argtypes = [i64, i32, P, i32, i32, ctypes.POINTER(_Opts), ctypes.POINTER(P)]
     lib.lrspike_solve.argtypes = [P, P, i32]
     lib.lrspike_solve_adjoint.argtypes = [P, P, i32]
@@ -141,10 +149,20 @@ def _check_vec(t, n, name):
         raise ValueError(f"{name} must be contiguous")
 
 
-def workspace_bytes(n, k, p, r, precision="fp64", max_nrhs=32):
+def workspace_bytes(n, k, p, r, precision="fp64", max_nrhs=32, svd="exact", rsvd_ell=0, variant="full"):
     lib = load_library()
     out = ctypes.c_size_t(0)
-    rc = lib.lrspike_workspace_size(n, k, p, r, _PRECISIONS[precision], max_nrhs, ctypes.byref(out))
+    if svd == "exact":
+        rc = lib.lrspike_workspace_size(n, k, p, r, _PRECISIONS[precision], max_nrhs, ctypes.byref(out))
+    else:
+        opts = _Opts()
+        lib.lrspike_default_opts(ctypes.byref(opts))
+        opts.precision = _PRECISIONS[precision]
+        opts.max_nrhs = max_nrhs
+        opts.variant = _VARIANTS[variant]
+        opts.svd = _SVDS[svd]
+        opts.rsvd_ell = rsvd_ell
+        rc = lib.lrspike_workspace_size_opts(n, k, p, r, ctypes.byref(opts), ctypes.byref(out))
     if rc:
         raise LRSpikeError(rc, "lrspike_workspace_size")
     return out.value
@@ -154,7 +172,12 @@ class Plan:
     """A factored LR-SPIKE plan: the factors live in a caller-owned workspace tensor."""
 
     def __init__(self, bands, p, r, precision="fp64", max_nrhs=32, max_refine=30, refine_tol=1e-13,
-                 workspace=None, profile=False, variant="full"):
+                 workspace=None, profile=False, variant="full", svd="exact", rsvd_ell=None, rsvd_power=0,
+                 rsvd_omega=None, rsvd_seed=0):
+        """svd="randomized" truncates the spikes through the randomized SVD with
+        rsvd_ell sketch columns (default min(k, 2r)) and rsvd_power power steps;
+        rsvd_omega, a float64 CUDA tensor of shape (p, 2, k, rsvd_ell), holds the
+        Gaussian test matrices (drawn here from rsvd_seed when not given)."""
         lib = load_library()
         if not isinstance(bands, torch.Tensor) or bands.device.type != "cuda" or bands.dtype != torch.float64:
             raise TypeError("bands must be a float64 CUDA tensor of shape (2k+1, n)")
@@ -167,7 +190,25 @@ class Plan:
         self.variant = variant
         self.max_nrhs = int(max_nrhs)
         self.bands = bands  # borrowed by the library for the plan's lifetime
-        nbytes = workspace_bytes(self.n, self.k, self.p, self.r, precision, self.max_nrhs)
+        self.svd = svd
+        ell = 0
+        self.rsvd_omega = None
+        if svd == "randomized":
+            ell = int(rsvd_ell) if rsvd_ell is not None else min(self.k, max(2 * self.r, 1))
+            if rsvd_omega is None:
+                gen = torch.Generator(device=bands.device)
+                gen.manual_seed(int(rsvd_seed))
+                rsvd_omega = torch.randn((self.p, 2, self.k, ell), dtype=torch.float64, device=bands.device,
+                                         generator=gen)
+            if (not isinstance(rsvd_omega, torch.Tensor) or rsvd_omega.device != bands.device or
+                    rsvd_omega.dtype != torch.float64 or tuple(rsvd_omega.shape) != (self.p, 2, self.k, ell) or
+                    not rsvd_omega.is_contiguous()):
+                raise ValueError(f"rsvd_omega must be a contiguous float64 tensor of shape "
+                                 f"({self.p}, 2, {self.k}, {ell}) on {bands.device}")
+            self.rsvd_omega = rsvd_omega  # read by the factorization's kernels
+        elif svd != "exact":
+            raise ValueError("svd must be 'exact' or 'randomized'")
+        nbytes = workspace_bytes(self.n, self.k, self.p, self.r, precision, self.max_nrhs, svd, ell, variant)
         if workspace is None:
             workspace = torch.empty(nbytes, dtype=torch.uint8, device=bands.device)
         elif workspace.dtype != torch.uint8 or workspace.numel() < nbytes or workspace.device != bands.device:
@@ -184,6 +225,10 @@ class Plan:
         opts.max_nrhs = self.max_nrhs
         opts.profile = 1 if profile else 0
         opts.variant = _VARIANTS[variant]
+        opts.svd = _SVDS[svd]
+        opts.rsvd_ell = ell
+        opts.rsvd_power = int(rsvd_power)
+        opts.rsvd_omega = self.rsvd_omega.data_ptr() if self.rsvd_omega is not None else None
         handle = ctypes.c_void_p()
         rc = lib.lrspike_factor(self.n, self.k, bands.data_ptr(), self.p, self.r, ctypes.byref(opts),
                                 ctypes.byref(handle))

@@ -24,6 +24,7 @@ struct RedArgs;
 #include "factor_wave.hip"
 #include "factor_lds.hip"
 #include "krylov.hip"
+#include "rsvd.hip"
 
 using namespace lrs;
 
@@ -53,6 +54,8 @@ struct lrspike_plan_s {
   int profiling;
   std::vector<std::pair<const char*, std::pair<hipEvent_t, hipEvent_t>>> prof;
   int wave = 1;                 // matrix-core wave sweeps for K >= 16 (else workgroup sweeps)
+  const double* rsvd_omega = nullptr;  // randomized spike SVD: Gaussian test matrices (device, borrowed)
+  int rsvd_power = 0;                  // its power steps
   BatchState* batch = nullptr;  // set for plans made by lrspike_factor_batched
 };
 
@@ -272,10 +275,68 @@ int launch(lrspike_plan P, const char* name, void (*kern)(KArgs...), dim3 grid, 
     if (rc_) return rc_;                                                  \
   } while (0)
 
+// Randomized spike SVD (kernels in rsvd.hip): q + 1 sketch passes, each a
+// block-diagonal solve of the sketch right-hand side followed by an adjoint
+// solve of which only the tips are kept; the last pass also forms the sketch
+// Gram.  The sweeps are the plan's own solve kernels (matrix-core waves for
+// K = 16, 32, with the workgroup kernels for partitions factored with
+// interchanges; workgroup kernels otherwise), run on the n x 2 ell sketch.
+template <typename T, int K>
+int run_rsvd(lrspike_plan P) {
+  const Layout& L = P->L;
+  const int w = 2 * L.ell;
+  RsvdArgs ra{P->bands, P->ws, L, P->rsvd_omega};
+  double* Y = reinterpret_cast<double*>(P->ws + L.ysk);
+  double* scr = reinterpret_cast<double*>(P->ws + L.scr);
+  SolveArgs sa{P->bands, P->ws, L, Y, Y, w, w, nullptr};
+  sa.block_only = 1;
+  const size_t bs = lds_sw<T, K>();
+  if (!set_lds((const void*)retrieve_kernel<T, K>, bs) || !set_lds((const void*)adj_dstage_kernel<T, K>, bs))
+    return LRSPIKE_ERR_NOT_SUPPORTED;
+  const bool rows31 = (int64_t)L.nbmax * L.K * w * 8 < ((int64_t)1 << 31);
+  const bool wv = K >= 16 && K <= 32 && P->wave && rows31;
+  const dim3 grid(L.p, (w + mc_of<K>() - 1) / mc_of<K>()), gw(L.p, (w + 15) / 16);
+  const dim3 grhs(L.p, (unsigned)std::min<int64_t>(64, ((int64_t)L.nbmax * K + 63) / 64));
+  for (int it = 0; it <= P->rsvd_power; ++it) {
+    LRS_LAUNCH("rsvd_rhs_kernel", rsvd_rhs_kernel, grhs, dim3(256), 0, ra);
+    // Y = A_j^{-1} (sketch right-hand side), in place
+    if (wv) {
+      if constexpr (K >= 16 && K <= 32) {
+        const size_t bw = (size_t)WaveSweep<T, K, 1>::total * sizeof(T) + 2 * K * sizeof(int);
+        LRS_LAUNCH("rsvd_solve", retrieve_wave_kernel<T, K, 1>, gw, dim3(64), bw, sa);
+      }
+    } else {
+      LRS_LAUNCH("rsvd_solve", retrieve_kernel<T, K>, grid, dim3(LRS_NT), bs, sa);
+    }
+    if (it == P->rsvd_power) LRS_LAUNCH("rsvd_gram_kernel", rsvd_gram_kernel, dim3(L.p, 2), dim3(256), 0, ra);
+    // tips of A_j^{-T} Y (the full result goes to the scratch)
+    SolveArgs sd = sa, sdf = sa;
+    sd.dst = sdf.dst = scr;
+    sd.block_only = sdf.block_only = 0;
+    sdf.only_flagged = 1;
+    if (wv) {
+      if constexpr (K >= 16 && K <= 32) {
+        LRS_LAUNCH("rsvd_adjoint", adj_dstage_wave_kernel<T, K>, gw, dim3(64), 0, sd);
+        LRS_LAUNCH("rsvd_adjoint_pivoting", adj_dstage_kernel<T, K>, grid, dim3(LRS_NT), bs, sdf);
+      }
+    } else {
+      LRS_LAUNCH("rsvd_adjoint", adj_dstage_kernel<T, K>, grid, dim3(LRS_NT), bs, sd);
+    }
+    LRS_LAUNCH("rsvd_vty_kernel", rsvd_vty_kernel, dim3(L.p, 2), dim3(256), 0, ra);
+    ra.om = reinterpret_cast<const double*>(P->ws + L.rmv);  // a power step sketches with V^T Y
+  }
+  const size_t bsm = rsvd_small_lds(L.ell, L.k);
+  if (!set_lds((const void*)rsvd_small_kernel, bsm)) return LRSPIKE_ERR_NOT_SUPPORTED;
+  LRS_LAUNCH("rsvd_small_kernel", rsvd_small_kernel, dim3(L.p, 2), dim3(256), bsm, ra);
+  return 0;
+}
+
 template <typename T, int K>
 int run_factor(lrspike_plan P) {
   const Layout& L = P->L;
   FactorArgs fa{P->bands, P->ws, L};
+  const bool rsvd = L.ell > 0 && L.r < L.K && L.p > 1;
+  int rc;
   size_t b1 = 0;
   if constexpr (K <= 32) {
     b1 = lds_p1<T, K>();
@@ -287,7 +348,8 @@ int run_factor(lrspike_plan P) {
     if (!set_lds((const void*)factor_lds_kernel<T, K>, bf) || !set_lds((const void*)spike_lds_kernel<T, K>, bs))
       return LRSPIKE_ERR_NOT_SUPPORTED;
     LRS_LAUNCH("factor_pass1", factor_lds_kernel<T, K>, dim3(L.p), dim3(LRS_NT), bf, fa);
-    LRS_LAUNCH("spike_fwd", spike_lds_kernel<T, K>, dim3(L.p, 2, K / SLds<T, K>::MS), dim3(LRS_NT), bs, fa);
+    if (!rsvd)
+      LRS_LAUNCH("spike_fwd", spike_lds_kernel<T, K>, dim3(L.p, 2, K / SLds<T, K>::MS), dim3(LRS_NT), bs, fa);
   } else if constexpr (K >= 16) {
     // one wave per partition without interchanges; partitions that need them
     // are flagged and refactored by the general kernel (a no-op elsewhere)
@@ -296,7 +358,7 @@ int run_factor(lrspike_plan P) {
     const size_t bw = (size_t)FWave<T, K>::total * sizeof(T);
     if (!set_lds((const void*)factor_wave_kernel<T, K>, bw)) return LRSPIKE_ERR_NOT_SUPPORTED;
     LRS_LAUNCH("factor_pass1", factor_wave_kernel<T, K>, dim3(L.p), dim3(64), bw, fa);
-    LRS_LAUNCH("spike_fwd", spike_wave_kernel<T, K>, dim3(L.p), dim3(64), 0, fa);
+    if (!rsvd) LRS_LAUNCH("spike_fwd", spike_wave_kernel<T, K>, dim3(L.p), dim3(64), 0, fa);
     fa.only_flagged = 1;
     LRS_LAUNCH("factor_pass1_pivoting", factor_pass1<T, K>, dim3(L.p), dim3(LRS_NT), b1, fa);
     fa.only_flagged = 0;
@@ -305,7 +367,10 @@ int run_factor(lrspike_plan P) {
   }
   (void)b1;
   RedArgs ra{P->ws, L, 0, 0, 0};
-  if (L.r < L.K) {
+  if (L.r < L.K && rsvd) {
+    // randomized SVD: Grams and tips of the sketched spikes Q Q^T V
+    if ((rc = run_rsvd<T, K>(P))) return rc;
+  } else if (L.r < L.K) {
     if constexpr (K == 64) {
       const size_t b2 = (size_t)4 * K * (K + 1) * sizeof(T);
       if (!set_lds((const void*)pass2_lds_kernel<T, K>, b2)) return LRSPIKE_ERR_NOT_SUPPORTED;
@@ -317,11 +382,13 @@ int run_factor(lrspike_plan P) {
       if (!set_lds((const void*)factor_pass2<T, K>, b2)) return LRSPIKE_ERR_NOT_SUPPORTED;
       LRS_LAUNCH("factor_pass2", factor_pass2<T, K>, dim3(L.p), dim3(LRS_NT), b2, fa);
     }
+  }
+  if (L.r < L.K) {
     if (L.r > 0) {
       const size_t be = (size_t)2 * K * (K + 1) * 8;
       if (!set_lds((const void*)eigen_kernel<K>, be)) return LRSPIKE_ERR_NOT_SUPPORTED;
       LRS_LAUNCH("eigen_kernel", eigen_kernel<K>, dim3(L.p, 2), dim3(LRS_NT), be, ra);
-      }
+    }
   } else {
     LRS_LAUNCH("identity_proj_kernel", identity_proj_kernel<K>, dim3(L.p), dim3(256), 0, ra);
   }
@@ -612,6 +679,18 @@ apply_fn pick_apply(int K) {
 }
 
 bool prec_valid(int prec) { return prec >= LRSPIKE_FP64 && prec <= LRSPIKE_FP32_BICGSTAB; }
+// Sketch columns of the randomized spike SVD for these options: 0 for the
+// exact truncation (also at r = k or r = 0, where nothing is truncated), -1
+// for invalid settings (an unknown svd code; at 0 < r < k, rsvd_ell outside
+// [r, k] or power steps outside [0, 4]).
+int svd_ell(const lrspike_opts* o, int k, int r) {
+  if (o->svd == LRSPIKE_SVD_EXACT) return 0;
+  if (o->svd != LRSPIKE_SVD_RANDOMIZED) return -1;
+  if (r == 0 || r >= k) return 0;
+  if (o->rsvd_ell < r || o->rsvd_ell > k || o->rsvd_power < 0 || o->rsvd_power > 4) return -1;
+  return o->rsvd_ell;
+}
+
 int prec_tsize(int prec) { return (prec == LRSPIKE_FP32_REFINED || prec == LRSPIKE_FP32_BICGSTAB) ? 4 : 8; }
 // 0 one application of M, 1 iterative refinement, 2 BiCGStab
 int prec_refined(int prec) {
@@ -718,6 +797,23 @@ int lrspike_workspace_size(int64_t n, int32_t k, int32_t p, int32_t r, int32_t p
   return 0;
 }
 
+int lrspike_workspace_size_opts(int64_t n, int32_t k, int32_t p, int32_t r, const lrspike_opts* opts,
+                                size_t* bytes) {
+  if (n < 1) return -1;
+  if (k < 1) return -2;
+  if (p < 1 || p > n) return -3;
+  if (r < 0 || r > k) return -4;
+  if (!opts || !prec_valid(opts->precision) || opts->max_nrhs < 1) return -5;
+  const int ell = svd_ell(opts, k, r);
+  if (ell < 0) return -5;
+  if (!bytes) return -6;
+  Layout L;
+  make_layout(L, n, k, p, r, prec_tsize(opts->precision), opts->max_nrhs, prec_refined(opts->precision),
+              opts->variant, nullptr, nullptr, 1, nullptr, ell);
+  *bytes = L.total;
+  return 0;
+}
+
 int lrspike_factor(int64_t n, int32_t k, const double* bands, int32_t p, int32_t r,
                    const lrspike_opts* opts, lrspike_plan* plan_out) {
   if (n < 1) return -1;
@@ -734,13 +830,16 @@ int lrspike_factor(int64_t n, int32_t k, const double* bands, int32_t p, int32_t
   if (!prec_valid(opts->precision)) return -6;
   if (opts->variant != LRSPIKE_VARIANT_FULL && opts->variant != LRSPIKE_VARIANT_T) return -6;
   if (opts->max_nrhs < 1) return -6;
+  const int ell = svd_ell(opts, k, r);
+  if (ell < 0) return -6;
+  if (ell > 0 && !is_device_ptr(opts->rsvd_omega)) return -6;
   if (prec_refined(opts->precision) == 2 && opts->max_nrhs > BICG_TPB) return -6;  // one thread per column
   if (K > 64) return LRSPIKE_ERR_NOT_SUPPORTED;
   // reduced-system blocks of order 2r are inverted in one workgroup's LDS
   if (p > 1 && 2 * ((r == k) ? K : r) > 64) return LRSPIKE_ERR_NOT_SUPPORTED;
   lrspike_plan P = new lrspike_plan_s();
   make_layout(P->L, n, k, p, r, prec_tsize(opts->precision), opts->max_nrhs, prec_refined(opts->precision),
-              opts->variant);
+              opts->variant, nullptr, nullptr, 1, nullptr, ell);
   if (!opts->workspace || opts->workspace_bytes < P->L.total || !is_device_ptr(opts->workspace)) {
     delete P;
     return LRSPIKE_ERR_WORKSPACE;
@@ -753,6 +852,8 @@ int lrspike_factor(int64_t n, int32_t k, const double* bands, int32_t p, int32_t
   P->bands = bands;
   P->ws = reinterpret_cast<char*>(opts->workspace);
   P->profiling = opts->profile ? 1 : 0;
+  P->rsvd_omega = ell > 0 ? opts->rsvd_omega : nullptr;
+  P->rsvd_power = ell > 0 ? opts->rsvd_power : 0;
   int rc = prec_refined(P->precision) ? alloc_refine_host(P) : 0;
   if (!rc) rc = launch(P, "state_init_kernel", state_init_kernel, dim3(1), dim3(64), 0,
                        reinterpret_cast<int*>(P->ws + P->L.latch));
@@ -919,6 +1020,7 @@ int lrspike_factor_batched(int32_t count, const lrspike_batch_desc* descs, const
   if (!opts) return -4;
   if (!plan_out) return -5;
   if (!prec_valid(opts->precision) || prec_refined(opts->precision) == 2) return -4;  // no BiCGStab for batches
+  if (opts->svd != LRSPIKE_SVD_EXACT) return -4;  // nor the randomized spike SVD
   for (int s = 0; s < count; ++s) {
     const lrspike_batch_desc& d = descs[s];
     if (d.n < 1 || d.k < 1 || d.r < 0 || d.r > d.k || d.nrhs < 1 || d.p < 0 || d.p > d.n || d.band_offset < 0 ||

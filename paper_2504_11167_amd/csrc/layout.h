@@ -16,6 +16,7 @@ struct Layout {
   int k, K, p, r, R2, nbmax, mmax, tsize;  // r: compressed rank (K when the user's r = k)
   int refined;  // iterative refinement around the solve (residual, correction and norm buffers)
   int variant;  // reduced system: 0 = the whole block-tridiagonal Z, 1 = its diagonal blocks only
+  int ell;      // randomized spike SVD: sketch columns per spike (0 = exact truncation of the whole spike)
   // systems a plan holds (1, or the systems of a batched group) and, per
   // partition, the system slot it belongs to (device; null = all in slot 0):
   // refinement norms are kept per (system, column)
@@ -43,6 +44,10 @@ struct Layout {
   // products [bblk][mmax][3] (bblk workgroups cover the rows)
   size_t bvec, bsc, bpart;
   int bblk;
+  // randomized spike SVD (ell > 0): sketch Y (n x 2 ell, the V_j sketch in
+  // columns [0, ell), W_j's in [ell, 2 ell)), its Grams Y^T Y [p][2][ell][ell]
+  // and the products V^T Y, W^T Y [p][2][k][ell]
+  size_t ysk, rgy, rmv;
   size_t npv;    // int32[p]: partition needs the interchanging factorization
   size_t latch;  // device state block (STATE_BYTES): error latch, diagnostics, refinement control
   size_t total;
@@ -84,10 +89,14 @@ inline int kernel_K(int k) {
 // refined: the plan iterates the solve: 1 = iterative refinement (residual and
 // correction buffers), 2 = BiCGStab (also its vectors, scalars and partials);
 // variant: 0 = LR-SPIKE with the whole reduced system, 1 = its truncated form;
-// nsys / psys: systems held and the partition -> system slot map (batches)
+// nsys / psys: systems held and the partition -> system slot map (batches);
+// ell: sketch columns of the randomized spike SVD (0: exact truncation), which
+// also needs 2 ell solve columns (the sketch passes run as solves)
 inline void make_layout(Layout& L, int64_t n, int k, int p, int r, int tsize, int mmax, int refined = 0,
                         int variant = 0, const int64_t* offs_host = nullptr, const int64_t* offs_dev = nullptr,
-                        int nsys = 1, const int* psys = nullptr) {
+                        int nsys = 1, const int* psys = nullptr, int ell = 0) {
+  if (ell > 0 && mmax < 2 * ell) mmax = 2 * ell;
+  L.ell = ell;
   L.n = n;
   L.offs = offs_dev;
   L.refined = refined;
@@ -133,6 +142,8 @@ inline void make_layout(Layout& L, int64_t n, int k, int p, int r, int tsize, in
   L.fac = take(nblk * L.rec * tsize);
   L.swx = take(nblk * 3 * (size_t)K * K * tsize);
   L.gmat = take(nblk * (size_t)K * K * tsize);
+  // (kept with the randomized SVD too: the interchanging factorization kernel
+  // still forms the spikes of the partitions it refactors)
   L.ymat = take(L.r < K ? nblk * 2 * (size_t)K * K * tsize : 0);
   L.ipiv = take(nblk * (size_t)K * 4);
   L.flag = take(nblk * 4);
@@ -159,6 +170,9 @@ inline void make_layout(Layout& L, int64_t n, int k, int p, int r, int tsize, in
   L.bvec = take(refined == 2 ? (size_t)7 * n * mmax * 8 : 0);
   L.bsc = take(refined == 2 ? (size_t)mmax * BICG_SCALARS * 8 : 0);
   L.bpart = take(refined == 2 ? (size_t)L.bblk * mmax * 3 * 8 : 0);
+  L.ysk = take(ell > 0 ? (size_t)n * 2 * ell * 8 : 0);
+  L.rgy = take(ell > 0 ? (size_t)p * 2 * ell * ell * 8 : 0);
+  L.rmv = take(ell > 0 ? (size_t)p * 2 * k * ell * 8 : 0);
   L.npv = take((size_t)p * 4);
   L.latch = take(STATE_BYTES);
   L.total = o;

@@ -1,0 +1,253 @@
+// Randomized SVD of the spikes (section "SVD representation of the spikes":
+// the proto-algorithm of Halko, Martinsson and Tropp, a few passes over the
+// spike, oversampled sketch).  For the spike V_j = A_j^{-1} [0; B_j] (and W_j
+// = A_j^{-1} [C_j; 0] alike) and a caller-drawn Gaussian Omega (k x ell):
+//   Y = (V V^T)^q V Omega:  solves with ell columns instead of k
+//       (V X = A_j^{-1} [0; B_j X]: a block-diagonal solve of a right-hand
+//        side that is nonzero in the coupling rows only),
+//   V^T Y = B_j^T (A_j^{-T} Y)_bottom:  an adjoint solve of which only the
+//       tips are kept,
+//   Q = Y_S R^{-1} with Y_S^T Y_S = R^T R (Cholesky of the Gram Y^T Y with
+//       diagonal pivoting; sketch directions whose residual norm falls below
+//       1e-6 of the largest column are dropped as numerically dependent),
+//   Q Q^T V = Y_S T with T = (Y_S^T Y_S)^{-1} (V^T Y_S)^T  (ell' x k).
+// The truncation then proceeds exactly as for the whole spike, on Q Q^T V:
+// its Gram (Q Q^T V)^T (Q Q^T V) = (V^T Y_S) T and its tips Y_{S,t} T, Y_{S,b} T
+// go to the Gram and tip slots, where the eigen-decomposition and the
+// projection of the exact path take them up.
+//
+// Column conventions: the oracle-style k columns of a spike map to the
+// K-padded spike columns b (V) and K - k + b (W), as in the spike sweeps.
+#pragma once
+#include "common.h"
+#include "layout.h"
+
+namespace lrs {
+
+struct RsvdArgs {
+  const double* bands;
+  char* ws;
+  Layout L;
+  const double* om;  // [p][2][k][ell]: Omega on the first pass, V^T Y (W^T Y) on a power step
+};
+
+template <typename T>
+__device__ inline T* rsw(char* ws, size_t off) {
+  return reinterpret_cast<T*>(ws + off);
+}
+
+// Sketch right-hand side, row-major n x 2 ell: rows of partition j carry
+// B_j Om_{j,V} in its last k rows (columns [0, ell)) and C_j Om_{j,W} in its
+// first k rows (columns [ell, 2 ell)); every other entry is zero.
+// Grid (p, chunks), rows of a partition in chunks of 64.
+__global__ __launch_bounds__(256) void rsvd_rhs_kernel(RsvdArgs a) {
+  const Layout& L = a.L;
+  const int j = blockIdx.x, ell = L.ell, w = 2 * ell, k = L.k;
+  const Geom g = part_geom(L, j, L.K);
+  double* Y = rsw<double>(a.ws, L.ysk);
+  const double* omv = a.om + ((size_t)j * 2 + 0) * k * ell;
+  const double* omw = a.om + ((size_t)j * 2 + 1) * k * ell;
+  constexpr int ROWS = 64;
+  for (int r0 = blockIdx.y * ROWS; r0 < g.nj; r0 += gridDim.y * ROWS)
+    for (int o = threadIdx.x; o < ROWS * w; o += blockDim.x) {
+      const int li = r0 + o / w, c = o % w;
+      if (li >= g.nj) continue;
+      const int64_t i = g.s + li;
+      double v = 0.0;
+      if (c < ell) {
+        if (j < L.p - 1 && li >= g.nj - k)
+          for (int b = 0; b < k; ++b) v += band_at(a.bands, L.n, k, i, g.s + g.nj + b) * omv[b * ell + c];
+      } else if (j > 0 && li < k) {
+        for (int b = 0; b < k; ++b) v += band_at(a.bands, L.n, k, i, g.s - k + b) * omw[b * ell + c - ell];
+      }
+      Y[i * w + c] = v;
+    }
+}
+
+// Gram Y_s^T Y_s of one partition's sketch (s = 0: V, 1: W), ell x ell,
+// accumulated over 64-row chunks staged in LDS.  Grid (p, 2), 256 threads.
+__global__ __launch_bounds__(256) void rsvd_gram_kernel(RsvdArgs a) {
+  constexpr int ROWS = 64, EMAX = 64 * 64 / 256;
+  __shared__ double ys[ROWS * 65];
+  const Layout& L = a.L;
+  const int j = blockIdx.x, s = blockIdx.y, ell = L.ell, w = 2 * ell, tid = threadIdx.x;
+  const Geom g = part_geom(L, j, L.K);
+  const double* Y = rsw<double>(a.ws, L.ysk) + (size_t)g.s * w + s * ell;
+  const int ne = ell * ell;
+  double acc[EMAX];
+#pragma unroll
+  for (int t = 0; t < EMAX; ++t) acc[t] = 0.0;
+  for (int r0 = 0; r0 < g.nj; r0 += ROWS) {
+    const int nr = min(ROWS, g.nj - r0);
+    for (int o = tid; o < ROWS * ell; o += blockDim.x) {
+      const int rr = o / ell, c = o % ell;
+      ys[rr * 65 + c] = rr < nr ? Y[(size_t)(r0 + rr) * w + c] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int t = 0; t < EMAX; ++t) {
+      const int e = tid + 256 * t;
+      if (e < ne) {
+        const int i = e / ell, c = e % ell;
+        double sacc = acc[t];
+        for (int rr = 0; rr < ROWS; ++rr) sacc += ys[rr * 65 + i] * ys[rr * 65 + c];
+        acc[t] = sacc;
+      }
+    }
+    __syncthreads();
+  }
+  double* G = rsw<double>(a.ws, L.rgy) + ((size_t)j * 2 + s) * ne;
+#pragma unroll
+  for (int t = 0; t < EMAX; ++t) {
+    const int e = tid + 256 * t;
+    if (e < ne) G[e] = acc[t];
+  }
+}
+
+// V^T Y = B_j^T nu_b and W^T Y = C_j^T nu_t from the adjoint solve's tips
+// nu = A_j^{-T} Y (tip buffer: first and last K real rows, row stride mmax),
+// k x ell each, to the [p][2][k][ell] buffer (zero for the absent V_{p-1},
+// W_0).  Grid (p, 2).
+__global__ __launch_bounds__(256) void rsvd_vty_kernel(RsvdArgs a) {
+  const Layout& L = a.L;
+  const int j = blockIdx.x, s = blockIdx.y, ell = L.ell, k = L.k, K = L.K;
+  const Geom g = part_geom(L, j, K);
+  const double* yt = rsw<double>(a.ws, L.ytip) + (size_t)j * 2 * K * L.mmax;
+  double* M = rsw<double>(a.ws, L.rmv) + ((size_t)j * 2 + s) * k * ell;
+  const bool present = s == 0 ? j < L.p - 1 : j > 0;
+  for (int o = threadIdx.x; o < k * ell; o += blockDim.x) {
+    const int b = o / ell, c = o % ell;
+    double v = 0.0;
+    if (present) {
+      if (s == 0) {  // B_j[a][b] = A[s_j + nj - K + a, s_j + nj + b], nu_b rows a, columns [0, ell)
+        const int64_t r0 = g.s + g.nj - K, c0 = g.s + g.nj;
+        for (int q = 0; q < K; ++q)
+          v += band_at(a.bands, L.n, k, r0 + q, c0 + b) * yt[((size_t)K + q) * L.mmax + c];
+      } else {       // C_j[a][b] = A[s_j + a, s_j - k + b], nu_t rows a, columns [ell, 2 ell)
+        for (int q = 0; q < K; ++q)
+          v += band_at(a.bands, L.n, k, g.s + q, g.s - k + b) * yt[(size_t)q * L.mmax + ell + c];
+      }
+    }
+    M[o] = v;
+  }
+}
+
+// Per (partition, spike): pivoted Cholesky of G = Y^T Y, T = G_SS^{-1} M_S^T,
+// then the Gram M_S T and the tips Y_{S,t/b} T of Q Q^T V into the Gram and
+// tip slots (K x K, padded columns).  Grid (p, 2), 256 threads; dynamic LDS
+// of rsvd_small_lds(ell, k) bytes.
+__host__ __device__ constexpr size_t rsvd_small_lds(int ell, int k) {
+  return ((size_t)ell * (ell + 1) + (size_t)ell * ell + (size_t)ell * (k + 1) + 64) * sizeof(double);
+}
+
+__global__ __launch_bounds__(256) void rsvd_small_kernel(RsvdArgs a) {
+  extern __shared__ __align__(16) double rs_lds[];
+  __shared__ int perm[64];
+  __shared__ int s_go, s_best;
+  __shared__ double s_dmax;
+  const Layout& L = a.L;
+  const int j = blockIdx.x, s = blockIdx.y, ell = L.ell, k = L.k, K = L.K, tid = threadIdx.x;
+  const int LG = ell + 1, LM = k + 1, w = 2 * ell;
+  double* G = rs_lds;          // ell x LG, the sketch Gram
+  double* R = G + ell * LG;    // ell x ell: R[t * ell + u], row t, pivot position u (upper triangle)
+  double* Tm = R + ell * ell;  // ell x LM: M_S^T, then Z = R^{-T} M_S^T, then T = R^{-1} Z
+  double* d = Tm + ell * LM;   // residual diagonal by sketch column
+  const Geom g = part_geom(L, j, K);
+  const double* Gg = rsw<double>(a.ws, L.rgy) + ((size_t)j * 2 + s) * ell * ell;
+  const double* M = rsw<double>(a.ws, L.rmv) + ((size_t)j * 2 + s) * k * ell;
+  const double* Y = rsw<double>(a.ws, L.ysk) + s * ell;
+  for (int o = tid; o < ell * ell; o += blockDim.x) {
+    G[(o / ell) * LG + o % ell] = Gg[o];
+    R[o] = 0.0;
+  }
+  if (tid < ell) perm[tid] = tid;
+  __syncthreads();
+  if (tid < ell) d[tid] = G[tid * LG + tid];
+  __syncthreads();
+  if (tid == 0) {
+    double dm = 0.0;
+    for (int i = 0; i < ell; ++i) dm = fmax(dm, d[i]);
+    s_dmax = dm;
+  }
+  __syncthreads();
+  int lp = 0;
+  for (int t = 0; t < ell; ++t) {
+    if (tid == 0) {
+      int best = t;
+      for (int u = t + 1; u < ell; ++u)
+        if (d[perm[u]] > d[perm[best]]) best = u;
+      s_go = d[perm[best]] > 1e-12 * s_dmax;  // false for a zero (absent) spike and for NaN
+      if (s_go) {
+        const int tp = perm[t];
+        perm[t] = perm[best];
+        perm[best] = tp;
+      }
+      s_best = best;
+    }
+    __syncthreads();
+    if (!s_go) break;
+    const int best = s_best;
+    if (best != t)  // the rows above t follow the column swap
+      for (int v = tid; v < t; v += blockDim.x) {
+        const double x = R[v * ell + t];
+        R[v * ell + t] = R[v * ell + best];
+        R[v * ell + best] = x;
+      }
+    __syncthreads();
+    const int pi = perm[t];
+    const double rt = sqrt(d[pi]);
+    for (int u = t + 1 + tid; u < ell; u += blockDim.x) {
+      const int i = perm[u];
+      double sum = G[pi * LG + i];
+      for (int v = 0; v < t; ++v) sum -= R[v * ell + t] * R[v * ell + u];
+      const double e = sum / rt;
+      R[t * ell + u] = e;
+      d[i] -= e * e;
+    }
+    if (tid == 0) R[t * ell + t] = rt;
+    __syncthreads();
+    lp = t + 1;
+  }
+  // T = (R^T R)^{-1} M_S^T, one column b per thread
+  for (int o = tid; o < lp * k; o += blockDim.x) {
+    const int u = o / k, b = o % k;
+    Tm[u * LM + b] = M[b * ell + perm[u]];
+  }
+  __syncthreads();
+  for (int b = tid; b < k; b += blockDim.x) {
+    for (int u = 0; u < lp; ++u) {  // R^T Z = M_S^T
+      double z = Tm[u * LM + b];
+      for (int v = 0; v < u; ++v) z -= R[v * ell + u] * Tm[v * LM + b];
+      Tm[u * LM + b] = z / R[u * ell + u];
+    }
+    for (int u = lp - 1; u >= 0; --u) {  // R T = Z
+      double z = Tm[u * LM + b];
+      for (int v = u + 1; v < lp; ++v) z -= R[u * ell + v] * Tm[v * LM + b];
+      Tm[u * LM + b] = z / R[u * ell + u];
+    }
+  }
+  __syncthreads();
+  // Gram of Q Q^T V: (V^T Y_S) T, and its tips Y_{S,t} T, Y_{S,b} T
+  const int cof = s == 0 ? 0 : K - k;  // padded column of spike column 0
+  double* gram = rsw<double>(a.ws, L.gram) + ((size_t)j * 2 + s) * K * K;
+  double* tt = rsw<double>(a.ws, L.tips) + ((size_t)j * 4 + 2 * s) * K * K;
+  double* tb = tt + (size_t)K * K;
+  for (int o = tid; o < K * K; o += blockDim.x) {
+    const int i = o / K, c = o % K, b1 = i - cof, b2 = c - cof;
+    double gv = 0.0, vt = 0.0, vb = 0.0;
+    if (b2 >= 0 && b2 < k) {
+      for (int u = 0; u < lp; ++u) {
+        const double tv = Tm[u * LM + b2];
+        const int col = perm[u];
+        if (b1 >= 0 && b1 < k) gv += M[b1 * ell + col] * tv;
+        vt += Y[(size_t)(g.s + i) * w + col] * tv;
+        vb += Y[(size_t)(g.s + g.nj - K + i) * w + col] * tv;
+      }
+    }
+    gram[o] = gv;
+    tt[o] = vt;
+    tb[o] = vb;
+  }
+}
+
+}  // namespace lrs

@@ -23,6 +23,7 @@ struct SolveArgs {
   int m;              // columns
   const int* gate;    // refinement: nonzero *gate = the iteration has stopped, the kernel is a no-op (null = always run)
   int only_flagged;   // workgroup adjoint kernels: only the partitions factored with interchanges
+  int block_only;     // retrieval kernels: x_j = A_j^{-1} f_j, no coupling terms (block-diagonal solve)
 };
 
 __device__ __forceinline__ bool gated(const int* gate) { return gate && *gate != 0; }
@@ -277,7 +278,8 @@ __global__ __launch_bounds__(LRS_NT) void retrieve_kernel(SolveArgs a) {
   T* Xn = lds + LD::oTmp;  // neighbour tip staging
   const int tid = threadIdx.x;
   const int k = L.k;
-  if (j > 0) {
+  const bool top = j > 0 && !a.block_only, bot = j < L.p - 1 && !a.block_only;
+  if (top) {
     interface_tip<T, K>(a, j - 1, false, c0, mc, Xn);  // x_{j-1,b}
     __syncthreads();
     // Ct = C_j x_{j-1,b}, C_j[i][l] = A[s_j + i, s_j - K + l]
@@ -289,7 +291,7 @@ __global__ __launch_bounds__(LRS_NT) void retrieve_kernel(SolveArgs a) {
     }
     __syncthreads();
   }
-  if (j < L.p - 1) {
+  if (bot) {
     interface_tip<T, K>(a, j + 1, true, c0, mc, Xn);  // x_{j+1,t}
     __syncthreads();
     // Cb = B_j x_{j+1,t}, B_j[i][l] = A[s_{j+1} - K + i, s_{j+1} + l]
@@ -302,7 +304,7 @@ __global__ __launch_bounds__(LRS_NT) void retrieve_kernel(SolveArgs a) {
     }
     __syncthreads();
   }
-  forward_pass<T, K, false>(a, g, j, c0, mc, lds, j > 0 ? Ct : nullptr, j < L.p - 1 ? Cb : nullptr, s_perm);
+  forward_pass<T, K, false>(a, g, j, c0, mc, lds, top ? Ct : nullptr, bot ? Cb : nullptr, s_perm);
   __syncthreads();
   backward_pass<T, K>(a, g, j, c0, mc, lds);
 }

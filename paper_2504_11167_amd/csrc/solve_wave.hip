@@ -572,7 +572,8 @@ __global__ __launch_bounds__(64) void retrieve_wave_kernel(SolveArgs a) {
       Xn[row * NC + c] = (T)v;
     }
   };
-  if (j > 0) {
+  const bool top = j > 0 && !a.block_only, bot = j < L.p - 1 && !a.block_only;
+  if (top) {
     tip(j - 1, false);  // x_{j-1,b}
     sync();
     for (int o = lane; o < K * mc; o += 64) {
@@ -583,7 +584,7 @@ __global__ __launch_bounds__(64) void retrieve_wave_kernel(SolveArgs a) {
     }
     sync();
   }
-  if (j < L.p - 1) {
+  if (bot) {
     tip(j + 1, true);  // x_{j+1,t}
     sync();
     const int64_t s1 = g.s + g.nj;
@@ -595,7 +596,7 @@ __global__ __launch_bounds__(64) void retrieve_wave_kernel(SolveArgs a) {
     }
     sync();
   }
-  fwd_wave<T, K, MCT, false>(a, g, j, c0, lds, j > 0 ? Ct : nullptr, j < L.p - 1 ? Cb : nullptr);
+  fwd_wave<T, K, MCT, false>(a, g, j, c0, lds, top ? Ct : nullptr, bot ? Cb : nullptr);
   bwd_wave<T, K, MCT>(a, g, j, c0);
 }
 

@@ -75,6 +75,29 @@ def test_workspace_size_grows_with_problem():
     assert d > a  # the refined plans hold the residual and the copy of f
 
 
+def test_randomized_svd_workspace_and_option_codes():
+    """The randomized spike SVD holds the n x 2 ell sketch (and at least 2 ell
+    solve columns) in the workspace instead of the spike sweeps' n x 2K
+    intermediate; ell outside [r, k], power steps outside [0, 4] and unknown
+    svd codes are argument errors (-5), while r = k or r = 0 (nothing
+    truncated) needs nothing extra."""
+    import paper_2504_11167_amd as lr
+    lib = lr.load_library()
+    n, k, p, r = 4096, 16, 4, 4
+    rs8 = lr.workspace_bytes(n, k, p, r, max_nrhs=2, svd="randomized", rsvd_ell=8)
+    rs12 = lr.workspace_bytes(n, k, p, r, max_nrhs=2, svd="randomized", rsvd_ell=12)
+    assert rs12 >= rs8 + n * 2 * 4 * 8
+    assert lr.workspace_bytes(n, k, p, k, max_nrhs=2, svd="randomized", rsvd_ell=8) == \
+        lr.workspace_bytes(n, k, p, k, max_nrhs=2)
+    o = lr._Opts()
+    lib.lrspike_default_opts(ctypes.byref(o))
+    out = ctypes.c_size_t(0)
+    for svd, ell, q, code in [(1, 8, 0, 0), (1, 3, 0, -5), (1, 17, 0, -5), (1, 8, 5, -5), (1, 8, -1, -5),
+                              (2, 8, 0, -5), (0, 99, 9, 0)]:
+        o.svd, o.rsvd_ell, o.rsvd_power = svd, ell, q
+        assert lib.lrspike_workspace_size_opts(n, k, p, r, ctypes.byref(o), ctypes.byref(out)) == code
+
+
 def test_factor_rejects_bad_sizes_before_gpu():
     import paper_2504_11167_amd as lr
     lib = lr.load_library()
