@@ -246,6 +246,22 @@ def test_batched_matches_per_system_oracle(gpu, precision):
             assert rel(xs, oracle.band_solve_refined(bl[s], fl[s])) <= 1e-11, s
 
 
+def test_batched_refinement_stops_per_system(gpu):
+    """FP32 factors + FP64 refinement in a batch whose systems share one group
+    but differ in scale by 1e6 (one band scaled up, so its solution is 1e6
+    smaller): the stopping rule holds per (system, column), so the small
+    solution reaches the same relative accuracy as its group-mates."""
+    bl, fl = _batch(6, 3, ks=(16,), nmax=2500, mmax=3)
+    bl[2] = bl[2] * 1e6
+    bands, rhs, descs = gpu.pack_systems(bl, fl)
+    plan = gpu.factor_batched(descs, to_dev(bands), precision="fp32_refined")
+    tr = to_dev(rhs)
+    plan.solve(tr)
+    plan.status()
+    for s, xs in enumerate(_unpack(tr.cpu().numpy(), descs)):
+        assert rel(xs, oracle.band_solve_refined(bl[s], fl[s])) <= 1e-11, s
+
+
 def test_batched_graph_replays_match_eager(gpu):
     """One HIP graph (factor + solve of every system) replayed several times,
     with eager solves and synchronizations in between, reproduces the eager
