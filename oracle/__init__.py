@@ -18,6 +18,9 @@ A plain C implementation of what the banded LR-SPIKE method computes
                       condition number (residual in long double).
 * ``bicgstab``        BiCGStab right-preconditioned by the LR-SPIKE operator,
                       the outer Krylov solver of the paper's experiments.
+* ``lrspike_iter``    LR-SPIKE-I and LR-SPIKE-OTF: the reduced system (its
+                      low-rank form, or the true one) solved by BiCGStab
+                      preconditioned by the LR-SPIKE-T system.
 * ``lrspike_rsvd``    R1 / R3 with the spikes truncated through the randomized
                       SVD (Halko-Martinsson-Tropp proto-algorithm, caller-drawn
                       Gaussian test matrices); ``rsvd_project`` is its range
@@ -59,6 +62,8 @@ def _load():
         lib.orc_lrspike.argtypes = [i64, i32, _D, i32, i32, i32, _D, _D, i32, _D, i32, i32]
         lib.orc_lrspike_rsvd.argtypes = [i64, i32, _D, i32, i32, i32, _D, _D, i32, _D, i32, i32, i32, i32, _D]
         lib.orc_rsvd_project.argtypes = [i64, i32, _D, i32, i32, _D, _D]
+        lib.orc_lrspike_iter.argtypes = [i64, i32, _D, i32, i32, i32, _D, _D, i32, ctypes.c_double, i32,
+                                         ctypes.POINTER(ctypes.c_int), _D, i32]
         lib.orc_reduced_dense.argtypes = [i64, i32, _D, i32, i32, _D]
         lib.orc_partition_spikes.argtypes = [i64, i32, _D, i32, i32, _D, _D]
         lib.orc_bicgstab.argtypes = [i64, i32, _D, i32, i32, i32, i32, _D, _D, ctypes.c_double, i32, i32,
@@ -171,6 +176,22 @@ def lrspike_rsvd(bands, f, p, r, omega, q=0, transpose=False, return_sv=False, t
     _check(rc, "lrspike_rsvd")
     x = x[:, 0] if flat else x
     return (x, sv) if return_sv else x
+
+
+def lrspike_iter(bands, f, p, r, kind="i", tol=1e-13, max_it=100, threads=0):
+    """LR-SPIKE-I (kind="i": S~_red) or LR-SPIKE-OTF (kind="otf": the true
+    S_red) solved by BiCGStab right-preconditioned by S~~_red at rank r, then
+    the solve-based recovery.  Returns (x, iters, relres) per column."""
+    bands, n, k = _band_args(bands)
+    f2, flat = _as2d(f)
+    m = f2.shape[1]
+    x = np.empty_like(f2)
+    iters = (ctypes.c_int * m)()
+    relres = np.zeros(m)
+    rc = _load().orc_lrspike_iter(n, k, _p(bands), p, r, m, _p(f2), _p(x), {"i": 0, "otf": 1}[kind], tol, max_it,
+                                  iters, _p(relres), threads)
+    _check(rc, "lrspike_iter")
+    return (x[:, 0] if flat else x), np.array(list(iters)), relres
 
 
 def rsvd_project(a, omega, q=0):

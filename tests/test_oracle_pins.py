@@ -732,3 +732,41 @@ def test_rsvd_lrspike_adjoint_dot_product(variant):
     x = oracle.lrspike_rsvd(bands, f, p, r, om, variant=variant)
     lam = oracle.lrspike_rsvd(bands, g, p, r, om, variant=variant, transpose=True)
     assert abs(x @ g - f @ lam) < 1e-12 * np.linalg.norm(x) * np.linalg.norm(g)
+
+
+# ------------------------------------------------ LR-SPIKE-I and LR-SPIKE-OTF
+@pytest.mark.parametrize("n,k,p,r,rule,theta", [(180, 8, 4, 3, "weak", 1.05), (200, 8, 4, 3, "theta", 0.3)])
+def test_lri_converges_to_the_direct_lrspike(n, k, p, r, rule, theta):
+    """LR-SPIKE-I solves the same S~_red as LR-SPIKE, iteratively: at
+    convergence the two agree, while the preconditioner's own one-shot answer
+    (LR-SPIKE-T) differs from both (short partitions keep the far tips)."""
+    bands, f = synth.make_problem(n, k, 2, seed=1, rule=rule, theta=theta)
+    xr = oracle.lrspike(bands, f, p, r)
+    xi, iters, relres = oracle.lrspike_iter(bands, f, p, r, "i", tol=1e-14)
+    assert np.all(iters >= 1) and np.all(relres <= 1e-14)
+    assert rel(xi, xr) <= 1e-12
+    assert rel(oracle.lrspike(bands, f, p, r, variant="t"), xr) > 1e-8
+
+
+def test_lri_without_iterations_is_lrspike_t():
+    """x_0 = S~~_red^{-1} y_red: with no iteration the result is LR-SPIKE-T's."""
+    bands, f = synth.make_problem(200, 8, 2, seed=1, rule="theta", theta=0.3)
+    x0, iters, _ = oracle.lrspike_iter(bands, f, 4, 3, "i", max_it=0)
+    assert np.all(iters == 0)
+    assert rel(x0, oracle.lrspike(bands, f, 4, 3, variant="t")) <= 1e-14
+
+
+@pytest.mark.parametrize("n,k,p,r,rule,theta", [(200, 8, 4, 3, "theta", 0.3), (240, 6, 5, 2, "weak", 1.05),
+                                                (4000, 16, 4, 4, "weak", 1.05), (1200, 16, 3, 4, "theta", 0.3)])
+def test_otf_converges_to_the_exact_solve(n, k, p, r, rule, theta):
+    """LR-SPIKE-OTF solves the true reduced system: for any r the result is
+    A^{-1} f to the inner tolerance (two backward-stable solves differ by
+    ~kappa u: 10x the oracle's own forward error, at least 1e-12), where the
+    rank-r one-shot operators are off by the truncation."""
+    bands, f = synth.make_problem(n, k, 2, seed=2, rule=rule, theta=theta)
+    x0 = oracle.band_solve(bands, f)
+    ref = oracle.band_solve_refined(bands, f)
+    xo, iters, relres = oracle.lrspike_iter(bands, f, p, r, "otf", tol=1e-14)
+    assert np.all(iters >= 2) and np.all(relres <= 1e-14)
+    assert rel(xo, ref) <= max(1e-12, 10 * rel(x0, ref))
+    assert rel(oracle.lrspike(bands, f, p, r), ref) > 1e-6
