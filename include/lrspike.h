@@ -64,11 +64,22 @@ enum {
  * Algorithms"). */
 enum {
   LRSPIKE_VARIANT_FULL = 0, /* the whole truncated reduced system S~_red, solved directly */
-  LRSPIKE_VARIANT_T = 1     /* LR-SPIKE-T: the truncated-SPIKE form of it, S~~_red (eqs.
+  LRSPIKE_VARIANT_T = 1,    /* LR-SPIKE-T: the truncated-SPIKE form of it, S~~_red (eqs.
                                truncated_redsys, red_sys_prec_mid_1/2): only the 2 x 2 interface
                                blocks [[I, V~_{j,b}], [W~_{j+1,t}, I]] are kept, solved
                                independently per interface (eqs. red_sys_1, red_sys_mid,
                                red_sys_3); the tips V~_{j,t}, W~_{j,b} are dropped */
+  LRSPIKE_VARIANT_I = 2,    /* LR-SPIKE-I: S~_red solved by BiCGStab right-preconditioned by
+                               S~~_red; at convergence the result equals LR-SPIKE's */
+  LRSPIKE_VARIANT_OTF = 3   /* LR-SPIKE-OTF: the true reduced system S_red (eq. spikered) solved
+                               by BiCGStab right-preconditioned by S~~_red, each product formed on
+                               the fly by partition solves (eqs. OTF-1/2), then the exact recovery
+                               of eqs. recovery1/2: x = A^{-1} rhs to the tolerance for any r.
+                               Variants I and OTF: FP64 plans with p >= 2, forward solves only
+                               (lrspike_solve_adjoint returns NOT_SUPPORTED), refine_tol and
+                               max_refine are the inner iteration's relative tolerance on the
+                               reduced residual and its iteration cap, non-convergence latches
+                               NOT_CONVERGED; not for batched plans */
 };
 
 enum {
@@ -121,7 +132,7 @@ typedef struct {
                             sizes the per-solve vectors inside the workspace */
   int32_t profile;       /* nonzero: time every kernel launch of this plan with a HIP
                             event pair on the plan's stream (see lrspike_profile_read) */
-  int32_t variant;       /* LRSPIKE_VARIANT_FULL (default) or LRSPIKE_VARIANT_T */
+  int32_t variant;       /* LRSPIKE_VARIANT_FULL (default), _T, _I or _OTF */
   int32_t svd;           /* LRSPIKE_SVD_EXACT (default) or LRSPIKE_SVD_RANDOMIZED */
   int32_t rsvd_ell;      /* randomized SVD: sketch columns ell, r <= ell <= k (the paper oversamples
                             by r/2 to r: ell = 1.5 r .. 2 r) */

@@ -27,8 +27,8 @@ __all__ = ["factor", "solve", "Plan", "BatchedPlan", "factor_batched", "pack_sys
 FP64, FP32_REFINED, FP64_REFINED, FP64_BICGSTAB, FP32_BICGSTAB = 0, 1, 2, 3, 4
 _PRECISIONS = {"fp64": FP64, "fp32_refined": FP32_REFINED, "fp64_refined": FP64_REFINED,
                "fp64_bicgstab": FP64_BICGSTAB, "fp32_bicgstab": FP32_BICGSTAB}
-VARIANT_FULL, VARIANT_T = 0, 1
-_VARIANTS = {"full": VARIANT_FULL, "t": VARIANT_T}
+VARIANT_FULL, VARIANT_T, VARIANT_I, VARIANT_OTF = 0, 1, 2, 3
+_VARIANTS = {"full": VARIANT_FULL, "t": VARIANT_T, "i": VARIANT_I, "otf": VARIANT_OTF}
 SVD_EXACT, SVD_RANDOMIZED = 0, 1
 _SVDS = {"exact": SVD_EXACT, "randomized": SVD_RANDOMIZED}
 _ERRORS = {
@@ -152,7 +152,7 @@ def _check_vec(t, n, name):
 def workspace_bytes(n, k, p, r, precision="fp64", max_nrhs=32, svd="exact", rsvd_ell=0, variant="full"):
     lib = load_library()
     out = ctypes.c_size_t(0)
-    if svd == "exact":
+    if svd == "exact" and variant in ("full", "t"):
         rc = lib.lrspike_workspace_size(n, k, p, r, _PRECISIONS[precision], max_nrhs, ctypes.byref(out))
     else:
         opts = _Opts()
@@ -319,7 +319,10 @@ def factor(bands, p, r, precision="fp64", max_nrhs=32, **kw):
     """Factor A (bands: (2k+1, n) float64 CUDA tensor) into p partitions at rank r.
     precision: "fp64" (one application of M_r^{-1}), "fp32_refined" / "fp64_refined" (iterative
     refinement preconditioned by M_r^{-1}) or "fp64_bicgstab" / "fp32_bicgstab" (BiCGStab
-    right-preconditioned by M_r^{-1}); variant: "full" (LR-SPIKE) or "t" (LR-SPIKE-T)."""
+    right-preconditioned by M_r^{-1}); variant: "full" (LR-SPIKE), "t" (LR-SPIKE-T), "i" (LR-SPIKE-I:
+    S~_red by BiCGStab preconditioned by LR-SPIKE-T's system) or "otf" (LR-SPIKE-OTF: the true
+    reduced system the same way, products by partition solves; the result is A^{-1} b); for "i"
+    and "otf" refine_tol / max_refine are the inner iteration's tolerance and cap."""
     return Plan(bands, p, r, precision=precision, max_nrhs=max_nrhs, **kw)
 
 

@@ -25,6 +25,7 @@ struct RedArgs;
 #include "factor_lds.hip"
 #include "krylov.hip"
 #include "rsvd.hip"
+#include "iter.hip"
 
 using namespace lrs;
 
@@ -637,6 +638,124 @@ int run_bicgstab(lrspike_plan P, double* rhs, int m, int transpose) {
   return 0;
 }
 
+// LR-SPIKE-I / LR-SPIKE-OTF solve (kernels in iter.hip): the D-stage gives
+// the reduced right-hand side y (interface tips), BiCGStab solves S x = y
+// (S = S~_red or S_red) right-preconditioned by S~~_red from x_0 = S~~_red^{-1} y,
+// with the device-side stopping rule of run_bicgstab (tolerance refine_tol on
+// ||y - S x|| / ||y|| per column, at most max_refine iterations), and the
+// retrieval recovers x_j from the solution tips.  Forward solves only.
+template <typename T, int K>
+int run_iter(lrspike_plan P, double* rhs, int m) {
+  const Layout& L = P->L;
+  hipStream_t st = P->stream;
+  const bool otf = L.variant == LRSPIKE_VARIANT_OTF;
+  int* state = reinterpret_cast<int*>(P->ws + L.latch);
+  const int* gate = state + S_STOP;
+  const int64_t NT = (int64_t)2 * K * L.p, vs = NT * L.mmax;
+  double* vec = reinterpret_cast<double*>(P->ws + L.itv);
+  double *b = vec, *x = vec + vs, *r = vec + 2 * vs, *rh = vec + 3 * vs, *pv = vec + 4 * vs, *vv = vec + 5 * vs,
+         *ph = vec + 6 * vs, *sv = vec + 7 * vs, *sh = vec + 8 * vs, *tv = vec + 9 * vs;
+  double* ytip = reinterpret_cast<double*>(P->ws + L.ytip);
+  double* F = reinterpret_cast<double*>(P->ws + L.scr);  // OTF: right-hand sides of the partition solves
+  BicgArgs ba{NT, m, L.mmax, L.iblk, reinterpret_cast<double*>(P->ws + L.isc),
+              reinterpret_cast<double*>(P->ws + L.ipart), gate, L.mmax};
+  IterArgs ia{P->bands, P->ws, L, m, gate};
+  hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(st, &cap) != hipSuccess) return LRSPIKE_ERR_HIP;
+  const bool capturing = cap != hipStreamCaptureStatusNone;
+  const dim3 gv(L.iblk), tb(BICG_TPB), gc(m), gi(L.NI, (m + IT_MC - 1) / IT_MC), gp(L.p, (m + IT_MC - 1) / IT_MC);
+  const size_t bpre = (size_t)2 * (K + L.R2) * IT_MC * 8, bmv = (size_t)2 * (L.r > 0 ? L.r : 1) * IT_MC * 8;
+  if (!set_lds((const void*)iter_precond_kernel<K>, bpre)) return LRSPIKE_ERR_NOT_SUPPORTED;
+  const dim3 gf(L.p, (unsigned)std::min<int64_t>(64, ((int64_t)L.nbmax * K + 63) / 64));
+  const bool rows31 = (int64_t)L.nbmax * L.K * m * 8 < ((int64_t)1 << 31);
+  const bool wv = K >= 16 && K <= 32 && P->wave && rows31;
+  const size_t bs = lds_sw<T, K>();
+  if (!set_lds((const void*)dstage_kernel<T, K>, bs) || !set_lds((const void*)retrieve_kernel<T, K>, bs))
+    return LRSPIKE_ERR_NOT_SUPPORTED;
+  // tips of A_j^{-1} src into the tip buffer (the D-stage kernels), gated
+  auto dstage = [&](double* src, int ld, const int* g) -> int {
+    SolveArgs sa{P->bands, P->ws, L, src, src, ld, m, g};
+    if (wv) {
+      if constexpr (K >= 16 && K <= 32) {
+        const size_t bw = (size_t)WaveSweep<T, K, 1>::total * sizeof(T) + 2 * K * sizeof(int);
+        LRS_LAUNCH("dstage_kernel", dstage_wave_kernel<T, K, 1>, dim3(L.p, (m + 15) / 16), dim3(64), bw, sa);
+      }
+    } else {
+      LRS_LAUNCH("dstage_kernel", dstage_kernel<T, K>, dim3(L.p, (m + mc_of<K>() - 1) / mc_of<K>()), dim3(LRS_NT),
+                 bs, sa);
+    }
+    return 0;
+  };
+  // y = S src, with the partial inner products of the step (mode 1 or 2 against w1)
+  auto matvec = [&](const double* src, double* y, const double* w1, int mode) -> int {
+    if (otf) {
+      LRS_LAUNCH("iter_otf_rhs_kernel", iter_otf_rhs_kernel<K>, gf, dim3(256), 0, ia, src, F, m);
+      int rc2 = dstage(F, m, gate);
+      if (rc2) return rc2;
+      LRS_LAUNCH("iter_finish_kernel", iter_finish_kernel, gv, tb, 0, ba, src, (const double*)ytip, y, w1, mode);
+    } else {
+      LRS_LAUNCH("iter_matvec_i_kernel", iter_matvec_i_kernel<K>, gp, dim3(256), bmv, ia, src, y);
+      LRS_LAUNCH("iter_finish_kernel", iter_finish_kernel, gv, tb, 0, ba, src, (const double*)nullptr, y, w1, mode);
+    }
+    return 0;
+  };
+  LRS_LAUNCH("refine_reset_kernel", refine_reset_kernel, dim3(1), dim3(256), 0, state,
+             reinterpret_cast<double*>(P->ws + L.norms), L.nsys * L.mmax);
+  // y_red = tips of D^{-1} f
+  int rc = dstage(rhs, m, nullptr);
+  if (rc) return rc;
+  LRS_LAUNCH("iter_copy_kernel", iter_copy_kernel, gv, tb, 0, ba, (const double*)ytip, b, 0);
+  // x_0 = S~~^{-1} b, r = b - S x_0
+  LRS_LAUNCH("iter_precond_kernel", iter_precond_kernel<K>, gi, dim3(256), bpre, ia, (const double*)b, x);
+  if ((rc = matvec(x, r, b, 1))) return rc;
+  LRS_LAUNCH("iter_copy_kernel", iter_copy_kernel, gv, tb, 0, ba, (const double*)b, r, 1);
+  LRS_LAUNCH("bicg_start_kernel", bicg_start_kernel, gv, tb, 0, ba, (const double*)b, (const double*)r, rh, pv, vv);
+  LRS_LAUNCH("bicg_reduce_kernel", bicg_reduce_kernel, gc, tb, 0, ba, 2, (int)BS_RR, (int)BS_BB, 0);
+  LRS_LAUNCH("bicg_init_kernel", bicg_init_kernel, dim3(1), dim3(BICG_TPB), 0, ba, state, P->refine_tol);
+  for (int it = 0; it < P->max_refine; ++it) {
+    LRS_LAUNCH("bicg_p_kernel", bicg_p_kernel, gv, tb, 0, ba, (const double*)r, pv, (const double*)vv, ph);
+    LRS_LAUNCH("iter_precond_kernel", iter_precond_kernel<K>, gi, dim3(256), bpre, ia, (const double*)ph, ph);
+    if ((rc = matvec(ph, vv, rh, 1))) return rc;
+    LRS_LAUNCH("bicg_reduce_kernel", bicg_reduce_kernel, gc, tb, 0, ba, 1, (int)BS_RV, 0, 0);
+    LRS_LAUNCH("bicg_s_kernel", bicg_s_kernel, gv, tb, 0, ba, (const double*)r, (const double*)vv, sv, sh);
+    LRS_LAUNCH("iter_precond_kernel", iter_precond_kernel<K>, gi, dim3(256), bpre, ia, (const double*)sh, sh);
+    if ((rc = matvec(sh, tv, sv, 2))) return rc;
+    LRS_LAUNCH("bicg_reduce_kernel", bicg_reduce_kernel, gc, tb, 0, ba, 2, (int)BS_TS, (int)BS_TT, 0);
+    LRS_LAUNCH("bicg_x_kernel", bicg_x_kernel, gv, tb, 0, ba, x, r, (const double*)rh, (const double*)ph,
+               (const double*)sv, (const double*)sh, (const double*)tv);
+    LRS_LAUNCH("bicg_reduce_kernel", bicg_reduce_kernel, gc, tb, 0, ba, 2, (int)BS_RHO_NEXT, (int)BS_RR, 0);
+    LRS_LAUNCH("bicg_ctl_kernel", bicg_ctl_kernel, dim3(1), dim3(BICG_TPB), 0, ba, state, P->refine_tol, it,
+               P->max_refine);
+    if (capturing) continue;
+    int* slot = P->hstate + 4 * (it & 1);
+    if (hipMemcpyAsync(slot, state + S_STOP, 4, hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipEventRecord(P->hev[it & 1], st) != hipSuccess)
+      return LRSPIKE_ERR_HIP;
+    if (it >= 1) {
+      if (hipEventSynchronize(P->hev[(it - 1) & 1]) != hipSuccess) return LRSPIKE_ERR_HIP;
+      if (P->hstate[4 * ((it - 1) & 1)] != 0) break;  // stopped: this iteration was a no-op
+    }
+  }
+  // recovery from the solution tips: tip buffer = x, compressed vector = 0
+  BicgArgs bu = ba;
+  bu.gate = nullptr;
+  LRS_LAUNCH("iter_copy_kernel", iter_copy_kernel, gv, tb, 0, bu, (const double*)x, ytip, 0);
+  if (L.NI > 0 && L.r > 0)
+    LRS_LAUNCH("iter_zero_zg_kernel", iter_zero_zg_kernel, dim3(64), dim3(256), 0,
+               reinterpret_cast<double*>(P->ws + L.zg), (size_t)L.NI * L.R2 * L.mmax);
+  SolveArgs sa{P->bands, P->ws, L, rhs, rhs, m, m, nullptr};
+  if (wv) {
+    if constexpr (K >= 16 && K <= 32) {
+      const size_t bw = (size_t)WaveSweep<T, K, 1>::total * sizeof(T) + 2 * K * sizeof(int);
+      LRS_LAUNCH("retrieve_kernel", retrieve_wave_kernel<T, K, 1>, dim3(L.p, (m + 15) / 16), dim3(64), bw, sa);
+    }
+  } else {
+    LRS_LAUNCH("retrieve_kernel", retrieve_kernel<T, K>, dim3(L.p, (m + mc_of<K>() - 1) / mc_of<K>()), dim3(LRS_NT),
+               bs, sa);
+  }
+  return 0;
+}
+
 typedef int (*factor_fn)(lrspike_plan);
 typedef int (*apply_fn)(lrspike_plan, double*, int, int);
 
@@ -828,7 +947,9 @@ int lrspike_factor(int64_t n, int32_t k, const double* bands, int32_t p, int32_t
   if (p > 1 && njmin < 2 * (int64_t)k) return -4;
   if (njmin < K) return -4;
   if (!prec_valid(opts->precision)) return -6;
-  if (opts->variant != LRSPIKE_VARIANT_FULL && opts->variant != LRSPIKE_VARIANT_T) return -6;
+  if (opts->variant < LRSPIKE_VARIANT_FULL || opts->variant > LRSPIKE_VARIANT_OTF) return -6;
+  // the iterative reduced solves: FP64 plans with at least one interface
+  if (opts->variant >= LRSPIKE_VARIANT_I && (opts->precision != LRSPIKE_FP64 || p < 2)) return -6;
   if (opts->max_nrhs < 1) return -6;
   const int ell = svd_ell(opts, k, r);
   if (ell < 0) return -6;
@@ -854,7 +975,7 @@ int lrspike_factor(int64_t n, int32_t k, const double* bands, int32_t p, int32_t
   P->profiling = opts->profile ? 1 : 0;
   P->rsvd_omega = ell > 0 ? opts->rsvd_omega : nullptr;
   P->rsvd_power = ell > 0 ? opts->rsvd_power : 0;
-  int rc = prec_refined(P->precision) ? alloc_refine_host(P) : 0;
+  int rc = (prec_refined(P->precision) || P->variant >= LRSPIKE_VARIANT_I) ? alloc_refine_host(P) : 0;
   if (!rc) rc = launch(P, "state_init_kernel", state_init_kernel, dim3(1), dim3(64), 0,
                        reinterpret_cast<int*>(P->ws + P->L.latch));
   factor_fn f = factor_for(P->precision, K);
@@ -871,6 +992,20 @@ static int solve_common(lrspike_plan P, double* rhs, int32_t nrhs, int transpose
   if (!P || P->batch) return -1;
   if (!is_device_ptr(rhs)) return -2;
   if (nrhs < 1 || nrhs > P->L.mmax) return -3;
+  if (P->variant >= LRSPIKE_VARIANT_I) {  // LR-SPIKE-I / -OTF: forward solves (FP64 plans)
+    if (transpose) return LRSPIKE_ERR_NOT_SUPPORTED;
+    if (nrhs > BICG_TPB) return -3;
+    switch (P->L.K) {
+      case 1: return run_iter<double, 1>(P, rhs, nrhs);
+      case 2: return run_iter<double, 2>(P, rhs, nrhs);
+      case 4: return run_iter<double, 4>(P, rhs, nrhs);
+      case 8: return run_iter<double, 8>(P, rhs, nrhs);
+      case 16: return run_iter<double, 16>(P, rhs, nrhs);
+      case 32: return run_iter<double, 32>(P, rhs, nrhs);
+      case 64: return run_iter<double, 64>(P, rhs, nrhs);
+    }
+    return LRSPIKE_ERR_NOT_SUPPORTED;
+  }
   apply_fn f = apply_for(P->precision, P->L.K);
   if (!f) return LRSPIKE_ERR_NOT_SUPPORTED;
   return f(P, rhs, nrhs, transpose);
@@ -1021,6 +1156,7 @@ int lrspike_factor_batched(int32_t count, const lrspike_batch_desc* descs, const
   if (!plan_out) return -5;
   if (!prec_valid(opts->precision) || prec_refined(opts->precision) == 2) return -4;  // no BiCGStab for batches
   if (opts->svd != LRSPIKE_SVD_EXACT) return -4;  // nor the randomized spike SVD
+  if (opts->variant >= LRSPIKE_VARIANT_I) return -4;  // nor the iterative reduced solves
   for (int s = 0; s < count; ++s) {
     const lrspike_batch_desc& d = descs[s];
     if (d.n < 1 || d.k < 1 || d.r < 0 || d.r > d.k || d.nrhs < 1 || d.p < 0 || d.p > d.n || d.band_offset < 0 ||

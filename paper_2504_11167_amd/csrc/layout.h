@@ -15,7 +15,8 @@ struct Layout {
   const int64_t* offs;
   int k, K, p, r, R2, nbmax, mmax, tsize;  // r: compressed rank (K when the user's r = k)
   int refined;  // iterative refinement around the solve (residual, correction and norm buffers)
-  int variant;  // reduced system: 0 = the whole block-tridiagonal Z, 1 = its diagonal blocks only
+  int variant;  // reduced system: 0 = the whole block-tridiagonal Z, 1 = its diagonal blocks only (LR-SPIKE-T),
+                // 2 = LR-SPIKE-I and 3 = LR-SPIKE-OTF (iterative, preconditioned by the variant-1 system)
   int ell;      // randomized spike SVD: sketch columns per spike (0 = exact truncation of the whole spike)
   // systems a plan holds (1, or the systems of a batched group) and, per
   // partition, the system slot it belongs to (device; null = all in slot 0):
@@ -48,6 +49,11 @@ struct Layout {
   // columns [0, ell), W_j's in [ell, 2 ell)), its Grams Y^T Y [p][2][ell][ell]
   // and the products V^T Y, W^T Y [p][2][k][ell]
   size_t ysk, rgy, rmv;
+  // iterative reduced solves (variant >= 2): ten tip vectors [p][2][K][mmax]
+  // (b, x, r, rh, p, v, ph, s, sh, t), per-column scalars [mmax][BICG_SCALARS]
+  // and partial inner products [iblk][mmax][3]
+  size_t itv, isc, ipart;
+  int iblk;
   size_t npv;    // int32[p]: partition needs the interchanging factorization
   size_t latch;  // device state block (STATE_BYTES): error latch, diagnostics, refinement control
   size_t total;
@@ -173,6 +179,14 @@ inline void make_layout(Layout& L, int64_t n, int k, int p, int r, int tsize, in
   L.ysk = take(ell > 0 ? (size_t)n * 2 * ell * 8 : 0);
   L.rgy = take(ell > 0 ? (size_t)p * 2 * ell * ell * 8 : 0);
   L.rmv = take(ell > 0 ? (size_t)p * 2 * k * ell * 8 : 0);
+  {
+    const int64_t rows = (int64_t)2 * K * p, blocks = (rows + 2047) / 2048;
+    L.iblk = (int)(blocks < 4096 ? blocks : 4096);
+    const bool it = variant >= 2;
+    L.itv = take(it ? (size_t)10 * rows * mmax * 8 : 0);
+    L.isc = take(it ? (size_t)mmax * BICG_SCALARS * 8 : 0);
+    L.ipart = take(it ? (size_t)L.iblk * mmax * 3 * 8 : 0);
+  }
   L.npv = take((size_t)p * 4);
   L.latch = take(STATE_BYTES);
   L.total = o;
