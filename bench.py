@@ -377,6 +377,8 @@ def main():
                     help="spike truncation: exact (whole spike) or the randomized SVD")
     ap.add_argument("--rsvd-ell", type=int, default=0, help="randomized SVD sketch columns (default 2r)")
     ap.add_argument("--rsvd-power", type=int, default=0, help="randomized SVD power steps")
+    ap.add_argument("--variant", default="full", choices=["full", "t", "i", "otf"],
+                    help="reduced system: LR-SPIKE (full), LR-SPIKE-T, -I or -OTF")
     ap.add_argument("--quiet", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -407,7 +409,8 @@ def main():
         ell = args.rsvd_ell or min(k, 2 * r)
         svd_kw = {"svd": "randomized", "rsvd_ell": ell, "rsvd_power": args.rsvd_power,
                   "rsvd_omega": torch.from_numpy(synth.gaussian_test_matrices(p, k, ell, seed=0)).to(dev)}
-    nbytes = lr.workspace_bytes(n, k, p, r, args.precision, m, args.svd, svd_kw.get("rsvd_ell", 0))
+    svd_kw["variant"] = args.variant
+    nbytes = lr.workspace_bytes(n, k, p, r, args.precision, m, args.svd, svd_kw.get("rsvd_ell", 0), args.variant)
     ws = torch.empty(nbytes, dtype=torch.uint8, device=dev)
     x = torch.empty_like(f)
     log(f"[bench] workspace {nbytes / 2**30:.2f} GiB")
@@ -506,7 +509,7 @@ def main():
               for ph, t in (("factor", ms_factor), ("solve", ms_solve))}
 
     comp = None
-    if not args.no_refined and args.precision == "fp64" and args.svd == "exact":
+    if not args.no_refined and args.precision == "fp64" and args.svd == "exact" and args.variant == "full":
         del plan, ws
         comp = refined_vs_fp64(lr, bands, f, x, lambda prec: lr.workspace_bytes(n, k, p, k, prec, m), p,
                                max(2, args.steps // 2), log)
@@ -526,8 +529,11 @@ def main():
         "dtype": "f64" if args.precision == "fp64" else "f32+f64",
         "data": "synthetic",
         "config": {"workload": f"lrspike n={n} k={k} p={p} r={r} nrhs={m} weak-dominance {args.precision}"
-                               + (f" randomized-svd ell={svd_kw['rsvd_ell']} q={args.rsvd_power}" if svd_kw else ""),
-                   "n": n, "k": k, "p": p, "r": r, "nrhs": m, "precision": args.precision, "svd": args.svd},
+                               + (f" randomized-svd ell={svd_kw['rsvd_ell']} q={args.rsvd_power}"
+                                  if args.svd == "randomized" else "")
+                               + (f" variant={args.variant}" if args.variant != "full" else ""),
+                   "n": n, "k": k, "p": p, "r": r, "nrhs": m, "precision": args.precision, "svd": args.svd,
+                   "variant": args.variant},
         "roofline": roof,
         "cpu_baseline": cpu,
         "ms_per_step_without_launch_events": round(ms_step_plain, 4),
@@ -536,6 +542,8 @@ def main():
         "refined_vs_fp64": comp,
         "kernels_ms_per_step": {kk: round(v[0] / args.steps, 4) for kk, v in sorted(kern.items(), key=lambda kv: -kv[1][0])},
         "swapped_blocks": info["swapped_blocks"],
+        "inner_iterations": info["refine_iters"] if args.variant in ("i", "otf") else None,
+        "rel_residual_vs_A": rel_residual(bands, x, f),
     }
     print(json.dumps(out))
 
