@@ -10,9 +10,9 @@
 //   Q = Y_S R^{-1} with Y_S^T Y_S = R^T R (Cholesky of the Gram Y^T Y with
 //       diagonal pivoting; sketch directions whose residual norm falls below
 //       1e-6 of the largest column are dropped as numerically dependent),
-//   Q Q^T V = Y_S T with T = (Y_S^T Y_S)^{-1} (V^T Y_S)^T  (ell' x k).
+//   B = Q^T V = R^{-T} (V^T Y_S)^T,  Q Q^T V = Y_S T with T = R^{-1} B  (ell' x k).
 // The truncation then proceeds exactly as for the whole spike, on Q Q^T V:
-// its Gram (Q Q^T V)^T (Q Q^T V) = (V^T Y_S) T and its tips Y_{S,t} T, Y_{S,b} T
+// its Gram (Q Q^T V)^T (Q Q^T V) = B^T B and its tips Y_{S,t} T, Y_{S,b} T
 // go to the Gram and tip slots, where the eigen-decomposition and the
 // projection of the exact path take them up.
 //
@@ -65,42 +65,61 @@ __global__ __launch_bounds__(256) void rsvd_rhs_kernel(RsvdArgs a) {
 }
 
 // Gram Y_s^T Y_s of one partition's sketch (s = 0: V, 1: W), ell x ell,
-// accumulated over 64-row chunks staged in LDS.  Grid (p, 2), 256 threads.
+// over 64-row chunks staged in LDS: thread t accumulates the 4 x 4 block
+// t mod nblk of the Gram (nblk = ceil(ell / 4)^2 <= 256) over every
+// (256 / nblk)-th row of a chunk, and the row groups are summed at the end.
+// Grid (p, 2), 256 threads.
 __global__ __launch_bounds__(256) void rsvd_gram_kernel(RsvdArgs a) {
-  constexpr int ROWS = 64, EMAX = 64 * 64 / 256;
-  __shared__ double ys[ROWS * 65];
+  constexpr int ROWS = 64, LP = 65;
+  __shared__ double ys[ROWS * LP];
   const Layout& L = a.L;
   const int j = blockIdx.x, s = blockIdx.y, ell = L.ell, w = 2 * ell, tid = threadIdx.x;
+  const int nbk = (ell + 3) / 4, nblk = nbk * nbk, groups = 256 / nblk;
+  const int blk = tid % nblk, grp = tid / nblk, bi = 4 * (blk / nbk), bj = 4 * (blk % nbk);
+  const bool active = grp < groups;
   const Geom g = part_geom(L, j, L.K);
   const double* Y = rsw<double>(a.ws, L.ysk) + (size_t)g.s * w + s * ell;
-  const int ne = ell * ell;
-  double acc[EMAX];
+  double acc[4][4];
 #pragma unroll
-  for (int t = 0; t < EMAX; ++t) acc[t] = 0.0;
+  for (int u = 0; u < 4; ++u)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) acc[u][v] = 0.0;
   for (int r0 = 0; r0 < g.nj; r0 += ROWS) {
     const int nr = min(ROWS, g.nj - r0);
-    for (int o = tid; o < ROWS * ell; o += blockDim.x) {
-      const int rr = o / ell, c = o % ell;
-      ys[rr * 65 + c] = rr < nr ? Y[(size_t)(r0 + rr) * w + c] : 0.0;
+    for (int o = tid; o < ROWS * 4 * nbk; o += blockDim.x) {
+      const int rr = o / (4 * nbk), c = o % (4 * nbk);
+      ys[rr * LP + c] = (rr < nr && c < ell) ? Y[(size_t)(r0 + rr) * w + c] : 0.0;
     }
     __syncthreads();
+    if (active)
+      for (int rr = grp; rr < ROWS; rr += groups) {
+        double x[4], y[4];
 #pragma unroll
-    for (int t = 0; t < EMAX; ++t) {
-      const int e = tid + 256 * t;
-      if (e < ne) {
-        const int i = e / ell, c = e % ell;
-        double sacc = acc[t];
-        for (int rr = 0; rr < ROWS; ++rr) sacc += ys[rr * 65 + i] * ys[rr * 65 + c];
-        acc[t] = sacc;
+        for (int u = 0; u < 4; ++u) {
+          x[u] = ys[rr * LP + bi + u];
+          y[u] = ys[rr * LP + bj + u];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) acc[u][v] = fma(x[u], y[v], acc[u][v]);
       }
-    }
     __syncthreads();
   }
-  double* G = rsw<double>(a.ws, L.rgy) + ((size_t)j * 2 + s) * ne;
+  // sum the row groups (fixed order) through the staging buffer
+  double* red = ys;  // groups x nblk x 16 <= 256 x 16 doubles
+  if (active)
 #pragma unroll
-  for (int t = 0; t < EMAX; ++t) {
-    const int e = tid + 256 * t;
-    if (e < ne) G[e] = acc[t];
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) red[(grp * nblk + blk) * 16 + u * 4 + v] = acc[u][v];
+  __syncthreads();
+  double* G = rsw<double>(a.ws, L.rgy) + ((size_t)j * 2 + s) * ell * ell;
+  for (int o = tid; o < nblk * 16; o += blockDim.x) {
+    const int bb = o / 16, e = o % 16, row = 4 * (bb / nbk) + e / 4, col = 4 * (bb % nbk) + e % 4;
+    double sum = 0.0;
+    for (int q = 0; q < groups; ++q) sum += red[(q * nblk + bb) * 16 + e];
+    if (row < ell && col < ell) G[row * ell + col] = sum;
   }
 }
 
@@ -132,9 +151,9 @@ __global__ __launch_bounds__(256) void rsvd_vty_kernel(RsvdArgs a) {
   }
 }
 
-// Per (partition, spike): pivoted Cholesky of G = Y^T Y, T = G_SS^{-1} M_S^T,
-// then the Gram M_S T and the tips Y_{S,t/b} T of Q Q^T V into the Gram and
-// tip slots (K x K, padded columns).  Grid (p, 2), 256 threads; dynamic LDS
+// Per (partition, spike): pivoted Cholesky Y_S^T Y_S = R^T R, B = Q^T V =
+// R^{-T} M_S^T and T = R^{-1} B, then the Gram B^T B and the tips Y_{S,t/b} T
+// of Q Q^T V into the Gram and tip slots (K x K, padded columns).  Grid (p, 2), 256 threads; dynamic LDS
 // of rsvd_small_lds(ell, k) bytes.
 __host__ __device__ constexpr size_t rsvd_small_lds(int ell, int k) {
   return ((size_t)ell * (ell + 1) + (size_t)ell * ell + (size_t)ell * (k + 1) + 64) * sizeof(double);
@@ -214,37 +233,44 @@ __global__ __launch_bounds__(256) void rsvd_small_kernel(RsvdArgs a) {
     Tm[u * LM + b] = M[b * ell + perm[u]];
   }
   __syncthreads();
-  for (int b = tid; b < k; b += blockDim.x) {
-    for (int u = 0; u < lp; ++u) {  // R^T Z = M_S^T
+  for (int b = tid; b < k; b += blockDim.x)
+    for (int u = 0; u < lp; ++u) {  // Z = R^{-T} M_S^T = Q^T V = B
       double z = Tm[u * LM + b];
       for (int v = 0; v < u; ++v) z -= R[v * ell + u] * Tm[v * LM + b];
       Tm[u * LM + b] = z / R[u * ell + u];
     }
-    for (int u = lp - 1; u >= 0; --u) {  // R T = Z
+  __syncthreads();
+  // Gram of Q Q^T V: B^T B (symmetric by construction, as the eigensolver needs)
+  const int cof = s == 0 ? 0 : K - k;  // padded column of spike column 0
+  double* gram = rsw<double>(a.ws, L.gram) + ((size_t)j * 2 + s) * K * K;
+  for (int o = tid; o < K * K; o += blockDim.x) {
+    const int b1 = o / K - cof, b2 = o % K - cof;
+    double gv = 0.0;
+    if (b1 >= 0 && b1 < k && b2 >= 0 && b2 < k)
+      for (int u = 0; u < lp; ++u) gv += Tm[u * LM + b1] * Tm[u * LM + b2];
+    gram[o] = gv;
+  }
+  __syncthreads();
+  for (int b = tid; b < k; b += blockDim.x)
+    for (int u = lp - 1; u >= 0; --u) {  // T = R^{-1} Z
       double z = Tm[u * LM + b];
       for (int v = u + 1; v < lp; ++v) z -= R[u * ell + v] * Tm[v * LM + b];
       Tm[u * LM + b] = z / R[u * ell + u];
     }
-  }
   __syncthreads();
-  // Gram of Q Q^T V: (V^T Y_S) T, and its tips Y_{S,t} T, Y_{S,b} T
-  const int cof = s == 0 ? 0 : K - k;  // padded column of spike column 0
-  double* gram = rsw<double>(a.ws, L.gram) + ((size_t)j * 2 + s) * K * K;
+  // tips of Q Q^T V: Y_{S,t} T, Y_{S,b} T
   double* tt = rsw<double>(a.ws, L.tips) + ((size_t)j * 4 + 2 * s) * K * K;
   double* tb = tt + (size_t)K * K;
   for (int o = tid; o < K * K; o += blockDim.x) {
-    const int i = o / K, c = o % K, b1 = i - cof, b2 = c - cof;
-    double gv = 0.0, vt = 0.0, vb = 0.0;
-    if (b2 >= 0 && b2 < k) {
+    const int i = o / K, b2 = o % K - cof;
+    double vt = 0.0, vb = 0.0;
+    if (b2 >= 0 && b2 < k)
       for (int u = 0; u < lp; ++u) {
         const double tv = Tm[u * LM + b2];
         const int col = perm[u];
-        if (b1 >= 0 && b1 < k) gv += M[b1 * ell + col] * tv;
         vt += Y[(size_t)(g.s + i) * w + col] * tv;
         vb += Y[(size_t)(g.s + g.nj - K + i) * w + col] * tv;
       }
-    }
-    gram[o] = gv;
     tt[o] = vt;
     tb[o] = vb;
   }
