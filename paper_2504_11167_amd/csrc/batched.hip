@@ -40,6 +40,7 @@ struct BatchGroup {
   BatchSys* sys_dev = nullptr;
   BatchChunk* chunks_dev = nullptr;
   int nchunks = 0;
+  size_t ws_cap = 0;         // bytes allocated at ws
 };
 
 struct BatchState {
@@ -90,24 +91,29 @@ __global__ void pack_rhs_kernel(const BatchSys* __restrict__ sys, const BatchChu
   }
 }
 
-static void free_group(BatchGroup& G) {
+// keep: the concatenated band, right-hand sides and workspace stay allocated
+// for the next build (the autotuner's candidates share them)
+static void free_group(BatchGroup& G, bool keep = false) {
   if (G.plan) {
     prof_clear(G.plan);
     free_refine_host(G.plan);
     delete G.plan;
   }
-  (void)hipFree(G.band);
-  (void)hipFree(G.rhs);
+  if (!keep) {
+    (void)hipFree(G.band);
+    (void)hipFree(G.rhs);
+    (void)hipFree(G.ws);
+    G.band = G.rhs = nullptr;
+    G.ws = nullptr;
+    G.ws_cap = 0;
+  }
   (void)hipFree(G.offs_dev);
   (void)hipFree(G.psys_dev);
   G.psys_dev = nullptr;
-  (void)hipFree(G.ws);
   (void)hipFree(G.sys_dev);
   (void)hipFree(G.chunks_dev);
   G.plan = nullptr;
-  G.band = G.rhs = nullptr;
   G.offs_dev = nullptr;
-  G.ws = nullptr;
   G.sys_dev = nullptr;
   G.chunks_dev = nullptr;
 }
@@ -123,8 +129,9 @@ static int sys_partitions(const lrspike_batch_desc& d, int64_t target) {
 }
 
 // (Re)build the group's partitioning, device tables, workspace and plan.
-static int build_group(BatchState& B, BatchGroup& G, int64_t target, int wave, const lrspike_opts* opts) {
-  free_group(G);
+static int build_group(BatchState& B, BatchGroup& G, int64_t target, int wave, const lrspike_opts* opts,
+                       bool keep = false) {
+  free_group(G, keep);
   G.target = target;
   G.wave = wave;
   G.offs.assign(1, 0);
@@ -153,8 +160,8 @@ static int build_group(BatchState& B, BatchGroup& G, int64_t target, int wave, c
       hipMalloc(&G.psys_dev, P * sizeof(int)) != hipSuccess ||
       hipMalloc(&G.sys_dev, st.size() * sizeof(BatchSys)) != hipSuccess ||
       hipMalloc(&G.chunks_dev, ch.size() * sizeof(BatchChunk)) != hipSuccess ||
-      hipMalloc(&G.band, (size_t)(2 * G.k + 1) * G.N * 8) != hipSuccess ||
-      hipMalloc(&G.rhs, (size_t)G.N * G.mb * 8) != hipSuccess)
+      (!G.band && hipMalloc(&G.band, (size_t)(2 * G.k + 1) * G.N * 8) != hipSuccess) ||
+      (!G.rhs && hipMalloc(&G.rhs, (size_t)G.N * G.mb * 8) != hipSuccess))
     return LRSPIKE_ERR_HIP;
   if (hipMemcpy(G.offs_dev, G.offs.data(), (P + 1) * sizeof(int64_t), hipMemcpyHostToDevice) != hipSuccess ||
       hipMemcpy(G.psys_dev, pslot.data(), P * sizeof(int), hipMemcpyHostToDevice) != hipSuccess ||
@@ -165,7 +172,13 @@ static int build_group(BatchState& B, BatchGroup& G, int64_t target, int wave, c
   G.plan = Q;
   make_layout(Q->L, G.N, G.k, P, G.r, prec_tsize(B.precision), G.mb, prec_refined(B.precision), 0, G.offs.data(),
               G.offs_dev, (int)G.sys.size(), G.psys_dev);
-  if (hipMalloc(&G.ws, Q->L.total) != hipSuccess) return LRSPIKE_ERR_HIP;
+  if (G.ws_cap < Q->L.total) {
+    (void)hipFree(G.ws);
+    G.ws = nullptr;
+    G.ws_cap = 0;
+    if (hipMalloc(&G.ws, Q->L.total) != hipSuccess) return LRSPIKE_ERR_HIP;
+    G.ws_cap = Q->L.total;
+  }
   if (prec_refined(B.precision) && alloc_refine_host(Q)) return LRSPIKE_ERR_HIP;
   Q->precision = B.precision;
   Q->max_refine = opts->max_refine > 0 ? opts->max_refine : 30;
@@ -222,7 +235,7 @@ static int autotune(BatchState& B, const lrspike_opts* opts) {
     for (int64_t t : targets) {
       if (t < std::max(2 * G.k, K)) continue;
       for (int w : waves) {
-        if ((rc = build_group(B, G, t, w, opts))) break;
+        if ((rc = build_group(B, G, t, w, opts, true))) break;
         if (hipMemsetAsync(G.rhs, 0, (size_t)G.N * G.mb * 8, st) != hipSuccess) { rc = LRSPIKE_ERR_HIP; break; }
         float ms = 0.f;
         for (int rep = 0; rep < 2 && !rc; ++rep) {  // the first repetition warms up
