@@ -7,7 +7,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "liblrspike.so")
 SOURCES = ["api.hip"]
 DEPS = ["api.hip", "batched.hip", "common.h", "layout.h", "sweep.h", "factor.hip", "factor_wave.hip", "factor_lds.hip", "solve.hip",
-        "solve_wave.hip", "reduced.hip", "krylov.hip", "rsvd.hip", "iter.hip"]
+        "solve_wave.hip", "reduced.hip", "krylov.hip", "rsvd.hip", "iter.hip", "sweep64.hip"]
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
     # no packed FP32 instructions anywhere in the device code

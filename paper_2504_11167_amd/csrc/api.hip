@@ -21,6 +21,7 @@ struct RedArgs;
 #include "factor.hip"
 #include "reduced.hip"
 #include "solve.hip"
+#include "sweep64.hip"
 #include "factor_wave.hip"
 #include "factor_lds.hip"
 #include "krylov.hip"
@@ -306,6 +307,8 @@ int run_rsvd(lrspike_plan P) {
         const size_t bw = (size_t)WaveSweep<T, K, 1>::total * sizeof(T) + 2 * K * sizeof(int);
         LRS_LAUNCH("rsvd_solve", retrieve_wave_kernel<T, K, 1>, gw, dim3(64), bw, sa);
       }
+    } else if (K == 64 && std::is_same<T, double>::value && P->wave) {
+      LRS_LAUNCH("rsvd_solve", retrieve64_kernel, dim3(L.p, (w + 15) / 16), dim3(256), 0, sa);
     } else {
       LRS_LAUNCH("rsvd_solve", retrieve_kernel<T, K>, grid, dim3(LRS_NT), bs, sa);
     }
@@ -480,6 +483,14 @@ int run_apply(lrspike_plan P, double* rhs, int m, int transpose, const int* gate
       }
       LRS_LAUNCH("retrieve_kernel", retrieve_wave_kernel<T, K, 1>, gw, dim3(64), bw, sa);
     }
+  } else if (!transpose && K == 64 && std::is_same<T, double>::value && P->wave) {
+    // K = 64 on the matrix cores: four waves per (partition, 16 columns)
+    const dim3 g64(L.p, (m + 15) / 16);
+    if (L.p > 1) {
+      LRS_LAUNCH("dstage_kernel", dstage64_kernel, g64, dim3(256), 0, sa);
+      if ((rc = run_reduced<K>(P, m, 0, gate))) return rc;
+    }
+    LRS_LAUNCH("retrieve_kernel", retrieve64_kernel, g64, dim3(256), 0, sa);
   } else if (!transpose) {
     if (!set_lds((const void*)dstage_kernel<T, K>, bs) || !set_lds((const void*)retrieve_kernel<T, K>, bs))
       return LRSPIKE_ERR_NOT_SUPPORTED;
@@ -680,6 +691,8 @@ int run_iter(lrspike_plan P, double* rhs, int m) {
         const size_t bw = (size_t)WaveSweep<T, K, 1>::total * sizeof(T) + 2 * K * sizeof(int);
         LRS_LAUNCH("dstage_kernel", dstage_wave_kernel<T, K, 1>, dim3(L.p, (m + 15) / 16), dim3(64), bw, sa);
       }
+    } else if (K == 64 && std::is_same<T, double>::value && P->wave) {
+      LRS_LAUNCH("dstage_kernel", dstage64_kernel, dim3(L.p, (m + 15) / 16), dim3(256), 0, sa);
     } else {
       LRS_LAUNCH("dstage_kernel", dstage_kernel<T, K>, dim3(L.p, (m + mc_of<K>() - 1) / mc_of<K>()), dim3(LRS_NT),
                  bs, sa);
@@ -749,6 +762,8 @@ int run_iter(lrspike_plan P, double* rhs, int m) {
       const size_t bw = (size_t)WaveSweep<T, K, 1>::total * sizeof(T) + 2 * K * sizeof(int);
       LRS_LAUNCH("retrieve_kernel", retrieve_wave_kernel<T, K, 1>, dim3(L.p, (m + 15) / 16), dim3(64), bw, sa);
     }
+  } else if (K == 64 && std::is_same<T, double>::value && P->wave) {
+    LRS_LAUNCH("retrieve_kernel", retrieve64_kernel, dim3(L.p, (m + 15) / 16), dim3(256), 0, sa);
   } else {
     LRS_LAUNCH("retrieve_kernel", retrieve_kernel<T, K>, dim3(L.p, (m + mc_of<K>() - 1) / mc_of<K>()), dim3(LRS_NT),
                bs, sa);

@@ -1,0 +1,241 @@
+// Solve sweeps at K = 64 on the matrix cores: one workgroup of four waves per
+// (partition, 16 right-hand-side columns), wave t owning row tile t (rows
+// 16t .. 16t+15) of every 64-row block.  A 64-row block no longer fits one
+// wave's registers with its prefetch (the K <= 32 sweeps keep the whole block
+// in one wave), so each wave reads only its row tile's fragments of the factor
+// records (one coalesced 64-lane load per fragment, as stored) and the waves
+// exchange the 64 x 16 right-hand-side strips through LDS in accumulator
+// layout: a product's accumulator tile is, lane for lane, the B operand of the
+// next product, so wave t writes its tile and every wave reads all four.
+// Partitions at K = 64 are factored without interchanges, so the sweeps are
+// those of A_j = L U:
+//   forward  z_b = L11^{-1} r_b,  r_{b+1} -= L21 z_b  (D-stage: y_t += G_b^T z_b,
+//            y_b = U11^{-1} z_last; retrieval: z_b written for the back-sweep)
+//   backward x_b = U11^{-1} (z_b - U12 x_{b+1})
+// with the record blocks LP = [L11^{-1} strictly lower | L21 upper] and
+// UP = [U11^{-1} upper | U12 strictly lower] + UD = diag(U12).
+#pragma once
+#include "common.h"
+#include "layout.h"
+
+namespace lrs {
+
+struct Sw64 {
+  static constexpr int K = 64, RT = 4, KS = 16;
+  // LDS: two strips (accumulator layout: tile, lane, element) and the two
+  // correction blocks of the retrieval (64 x 17 each)
+  static constexpr int STRIP = RT * 64 * 4;
+  static constexpr int oA = 0, oB = STRIP, oCt = 2 * STRIP, oCb = oCt + K * 17, total = oCb + K * 17;
+};
+
+using V64 = AccVec<double>::type;
+
+// own tile -> LDS strip, barrier, all four tiles <- LDS strip
+__device__ __forceinline__ void sw64_exchange(double* buf, const V64& own, int t, V64 (&all)[4]) {
+  const int lane = threadIdx.x & 63;
+  *reinterpret_cast<V64*>(buf + ((size_t)t * 64 + lane) * 4) = own;
+  __syncthreads();
+#pragma unroll
+  for (int u = 0; u < 4; ++u) all[u] = *reinterpret_cast<const V64*>(buf + ((size_t)u * 64 + lane) * 4);
+}
+
+// out (+)= sign * A(row tile t) * S with A's fragments fr[step] (step = k-step
+// of the 64 columns); kind: 0 L11^{-1} (strict lower + unit diagonal),
+// 1 L21 (upper incl. diagonal), 2 U11^{-1} (upper incl. diagonal), 3 U12's
+// strictly lower part, 9 full
+template <int KIND>
+__device__ __forceinline__ void sw64_mul(const double (&fr)[16], int t, const V64 (&S)[4], V64& out, double sign) {
+  const int lane = threadIdx.x & 63, i = 16 * t + (lane & 15);
+#pragma unroll
+  for (int step = 0; step < 16; ++step) {
+    const int ct = step >> 2;
+    if ((KIND == 0 || KIND == 3) && ct > t) continue;  // lower: zero right of the row tile
+    if ((KIND == 1 || KIND == 2) && ct < t) continue;  // upper: zero left of the row tile
+    const int kk = frag_k<double>(step, lane >> 4);
+    double a = fr[step];
+    if (KIND == 0) a = i > kk ? a : (i == kk ? 1.0 : 0.0);
+    if (KIND == 1 || KIND == 2) a = i <= kk ? a : 0.0;
+    if (KIND == 3) a = i > kk ? a : 0.0;
+    out = mfma_step(sign * a, S[ct][step & 3], out);
+  }
+}
+
+__device__ __forceinline__ void sw64_frags(double (&fr)[16], const double* blk, int t) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int step = 0; step < 16; ++step) fr[step] = blk[(size_t)(t * 16 + step) * 64 + lane];
+}
+
+// Right-hand-side tile t of block b: rows b K + 16 t + acc_row(lane, v) - pad
+// of the partition (zero on the padding rows and outside the chunk's
+// columns), minus the retrieval's corrections (Ct on the first K real rows,
+// Cb on the last K; pitch 17) when given.
+__device__ __forceinline__ V64 sw64_rhs(const SolveArgs& a, const Geom& g, int b, int t, int c0, int mc,
+                                        const double* Ct, const double* Cb) {
+  const int lane = threadIdx.x & 63, col = lane & 15;
+  V64 r;
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int lr = b * 64 + 16 * t + acc_row<double>(lane, v) - g.pad;
+    double x = 0.0;
+    if (lr >= 0 && lr < g.nj && col < mc) {
+      x = a.src[(g.s + lr) * (int64_t)a.ld + c0 + col];
+      if (Ct && lr < 64) x -= Ct[lr * 17 + col];
+      if (Cb && lr >= g.nj - 64) x -= Cb[(lr - (g.nj - 64)) * 17 + col];
+    }
+    r[v] = x;
+  }
+  return r;
+}
+
+__device__ __forceinline__ void sw64_store(const SolveArgs& a, const Geom& g, int b, int t, int c0, int mc,
+                                           const V64& x) {
+  const int lane = threadIdx.x & 63, col = lane & 15;
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int lr = b * 64 + 16 * t + acc_row<double>(lane, v) - g.pad;
+    if (lr >= 0 && lr < g.nj && col < mc) a.dst[(g.s + lr) * (int64_t)a.ld + c0 + col] = x[v];
+  }
+}
+
+// Forward sweep of partition j, columns [c0, c0 + mc).
+template <bool DSTAGE>
+__device__ void sw64_forward(const SolveArgs& a, const Geom& g, int j, int c0, int mc, double* lds, const double* Ct,
+                             const double* Cb) {
+  const Layout& L = a.L;
+  const int t = threadIdx.x >> 6, lane = threadIdx.x & 63, nb = g.nb;
+  const double* fac = wsp<double>(a.ws, L.fac) + (size_t)j * L.nbmax * L.rec;
+  const double* gm = wsp<double>(a.ws, L.gmat) + (size_t)j * L.nbmax * 64 * 64;
+  double lp[16], lpn[16], gt[16], gtn[16];
+  sw64_frags(lp, fac, t);
+  if (DSTAGE) sw64_frags(gt, gm, t);
+  V64 r = sw64_rhs(a, g, 0, t, c0, mc, Ct, Cb), acc = V64{0, 0, 0, 0}, z, S[4], Z[4];
+  for (int b = 0; b < nb; ++b) {
+    const bool last = b == nb - 1;
+    const int bn = last ? b : b + 1;  // (clamped: the prefetch is unconditional)
+    sw64_frags(lpn, fac + (size_t)bn * L.rec, t);
+    if (DSTAGE) sw64_frags(gtn, gm + (size_t)bn * 64 * 64, t);
+    V64 rn = sw64_rhs(a, g, bn, t, c0, mc, Ct, Cb);
+    sw64_exchange(lds + Sw64::oA, r, t, S);
+    z = V64{0, 0, 0, 0};
+    sw64_mul<0>(lp, t, S, z, 1.0);
+    sw64_exchange(lds + Sw64::oB, z, t, Z);
+    if (!last) sw64_mul<1>(lp, t, Z, rn, -1.0);
+    if (DSTAGE)
+      sw64_mul<9>(gt, t, Z, acc, 1.0);
+    else
+      sw64_store(a, g, b, t, c0, mc, z);
+    if (DSTAGE && last) {  // y_b = U11^{-1} z_last
+      double up[16];
+      sw64_frags(up, fac + (size_t)b * L.rec + 64 * 64, t);
+      V64 yb = V64{0, 0, 0, 0};
+      sw64_mul<2>(up, t, Z, yb, 1.0);
+      double* ytip = wsp<double>(a.ws, L.ytip) + (size_t)j * 2 * 64 * L.mmax;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int row = 16 * t + acc_row<double>(lane, v), col = lane & 15;
+        if (col < mc) {
+          ytip[(size_t)row * L.mmax + c0 + col] = acc[v];
+          ytip[(size_t)(64 + row) * L.mmax + c0 + col] = yb[v];
+        }
+      }
+    }
+    r = rn;
+#pragma unroll
+    for (int s = 0; s < 16; ++s) {
+      lp[s] = lpn[s];
+      if (DSTAGE) gt[s] = gtn[s];
+    }
+  }
+}
+
+// Backward sweep over a.dst (z in, x out), blocks from the last to the first.
+__device__ void sw64_backward(const SolveArgs& a, const Geom& g, int j, int c0, int mc, double* lds) {
+  const Layout& L = a.L;
+  const int t = threadIdx.x >> 6, lane = threadIdx.x & 63, nb = g.nb;
+  const double* fac = wsp<double>(a.ws, L.fac) + (size_t)j * L.nbmax * L.rec;
+  SolveArgs ad = a;
+  ad.src = a.dst;
+  double up[16], upn[16];
+  V64 ud, udn;
+  auto load_ud = [&](int b, V64& d) {
+    const double* u = fac + (size_t)b * L.rec + 2 * 64 * 64;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) d[v] = u[16 * t + acc_row<double>(lane, v)];
+  };
+  sw64_frags(up, fac + (size_t)(nb - 1) * L.rec + 64 * 64, t);
+  load_ud(nb - 1, ud);
+  V64 zt = sw64_rhs(ad, g, nb - 1, t, c0, mc, nullptr, nullptr), X[4], Y[4];
+  for (int q = 0; q < 4; ++q) X[q] = V64{0, 0, 0, 0};
+  for (int b = nb - 1; b >= 0; --b) {
+    const int bn = b > 0 ? b - 1 : 0;
+    sw64_frags(upn, fac + (size_t)bn * L.rec + 64 * 64, t);
+    load_ud(bn, udn);
+    V64 ztn = sw64_rhs(ad, g, bn, t, c0, mc, nullptr, nullptr);
+    if (b < nb - 1) {  // z_b - U12 x_{b+1}, U12 = strictly lower part of UP + diag(UD)
+      sw64_mul<3>(up, t, X, zt, -1.0);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) zt[v] -= ud[v] * X[t][v];
+    }
+    sw64_exchange(lds + Sw64::oA, zt, t, Y);
+    V64 x = V64{0, 0, 0, 0};
+    sw64_mul<2>(up, t, Y, x, 1.0);
+    sw64_store(a, g, b, t, c0, mc, x);
+    sw64_exchange(lds + Sw64::oB, x, t, X);
+    zt = ztn;
+    ud = udn;
+#pragma unroll
+    for (int s = 0; s < 16; ++s) up[s] = upn[s];
+  }
+}
+
+// D-stage at K = 64: tips of A_j^{-1} f_j.  Grid (p, column chunks of 16), 256 threads.
+__global__ __launch_bounds__(256) void dstage64_kernel(SolveArgs a) {
+  if (gated(a.gate)) return;
+  __shared__ __align__(16) double lds[Sw64::total];
+  const int j = blockIdx.x, c0 = blockIdx.y * 16, mc = min(16, a.m - c0);
+  const Geom g = part_geom(a.L, j, 64);
+  sw64_forward<true>(a, g, j, c0, mc, lds, nullptr, nullptr);
+}
+
+// Retrieval at K = 64: x_j = A_j^{-1} (f_j - [C_j x_{j-1,b}; 0; B_j x_{j+1,t}])
+// in place (block-diagonal solve with block_only).  Grid (p, column chunks of 16).
+__global__ __launch_bounds__(256) void retrieve64_kernel(SolveArgs a) {
+  if (gated(a.gate)) return;
+  __shared__ __align__(16) double lds[Sw64::total];
+  const Layout& L = a.L;
+  const int j = blockIdx.x, c0 = blockIdx.y * 16, mc = min(16, a.m - c0), k = L.k;
+  const Geom g = part_geom(L, j, 64);
+  double* Ct = lds + Sw64::oCt;
+  double* Cb = lds + Sw64::oCb;
+  double* Xn = lds + Sw64::oA;  // neighbour tip staging (the strips are not in use yet)
+  const bool top = j > 0 && !a.block_only, bot = j < L.p - 1 && !a.block_only;
+  if (top) {
+    interface_tip<double, 64>(a, j - 1, false, c0, mc, Xn);  // x_{j-1,b}, pitch 17
+    __syncthreads();
+    for (int o = threadIdx.x; o < 64 * mc; o += blockDim.x) {
+      const int i = o / mc, c = o % mc;
+      double s = 0.0;
+      for (int l = 0; l < 64; ++l) s += band_at(a.bands, L.n, k, g.s + i, g.s - 64 + l) * Xn[l * 17 + c];
+      Ct[i * 17 + c] = s;
+    }
+    __syncthreads();
+  }
+  if (bot) {
+    interface_tip<double, 64>(a, j + 1, true, c0, mc, Xn);  // x_{j+1,t}
+    __syncthreads();
+    const int64_t s1 = g.s + g.nj;
+    for (int o = threadIdx.x; o < 64 * mc; o += blockDim.x) {
+      const int i = o / mc, c = o % mc;
+      double s = 0.0;
+      for (int l = 0; l < 64; ++l) s += band_at(a.bands, L.n, k, s1 - 64 + i, s1 + l) * Xn[l * 17 + c];
+      Cb[i * 17 + c] = s;
+    }
+    __syncthreads();
+  }
+  sw64_forward<false>(a, g, j, c0, mc, lds, top ? Ct : nullptr, bot ? Cb : nullptr);
+  __syncthreads();  // z of the whole chunk written (each wave stored its own rows)
+  sw64_backward(a, g, j, c0, mc, lds);
+}
+
+}  // namespace lrs
