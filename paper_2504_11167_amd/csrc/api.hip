@@ -323,6 +323,8 @@ int run_rsvd(lrspike_plan P) {
         LRS_LAUNCH("rsvd_adjoint", adj_dstage_wave_kernel<T, K>, gw, dim3(64), 0, sd);
         LRS_LAUNCH("rsvd_adjoint_pivoting", adj_dstage_kernel<T, K>, grid, dim3(LRS_NT), bs, sdf);
       }
+    } else if (K == 64 && std::is_same<T, double>::value && P->wave) {
+      LRS_LAUNCH("rsvd_adjoint", adj_dstage64_kernel, dim3(L.p, (w + 15) / 16), dim3(256), 0, sd);
     } else {
       LRS_LAUNCH("rsvd_adjoint", adj_dstage_kernel<T, K>, grid, dim3(LRS_NT), bs, sd);
     }
@@ -519,6 +521,16 @@ int run_apply(lrspike_plan P, double* rhs, int m, int transpose, const int* gate
       LRS_LAUNCH("adj_retrieve_kernel", adj_retrieve_wave_kernel<T, K>, gw, dim3(64), bw, sa);
       LRS_LAUNCH("adj_retrieve_pivoting", adj_retrieve_kernel<T, K>, grid, dim3(LRS_NT), bs, sf);
     }
+  } else if (K == 64 && std::is_same<T, double>::value && P->wave) {
+    // K = 64 adjoint on the matrix cores
+    const dim3 g64(L.p, (m + 15) / 16);
+    if (L.p > 1) {
+      SolveArgs sd = sa;
+      sd.dst = reinterpret_cast<double*>(P->ws + L.scr);
+      LRS_LAUNCH("adj_dstage_kernel", adj_dstage64_kernel, g64, dim3(256), 0, sd);
+      if ((rc = run_reduced<K>(P, m, 1, gate))) return rc;
+    }
+    LRS_LAUNCH("adj_retrieve_kernel", adj_retrieve64_kernel, g64, dim3(256), 0, sa);
   } else {
     if (!set_lds((const void*)adj_dstage_kernel<T, K>, bs) || !set_lds((const void*)adj_retrieve_kernel<T, K>, bs))
       return LRSPIKE_ERR_NOT_SUPPORTED;

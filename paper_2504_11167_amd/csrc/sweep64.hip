@@ -238,4 +238,172 @@ __global__ __launch_bounds__(256) void retrieve64_kernel(SolveArgs a) {
   sw64_backward(a, g, j, c0, mc, lds);
 }
 
+// ------------------------------------------------------------------ adjoint
+// A_j^{-T} = L^{-T} U^{-T}: the transposed sweeps on fragments gathered
+// transposed from the records (element (i, kk) of row tile t read at the
+// stored position of (kk, i)).  kind 5: lower incl. diagonal of the gather
+// ((U11^{-1})^T from UP, L21^T from LP), 7: strictly upper (U12^T from UP; its
+// diagonal UD applies elementwise), 4: strictly upper with a unit diagonal
+// ((L11^{-1})^T from LP).
+__device__ __forceinline__ void sw64_tfrags(double (&fr)[16], const double* blk, int t) {
+  const int lane = threadIdx.x & 63, i = 16 * t + (lane & 15);
+#pragma unroll
+  for (int step = 0; step < 16; ++step) fr[step] = blk[fidx<double, 64>(frag_k<double>(step, lane >> 4), i)];
+}
+
+template <int KIND>
+__device__ __forceinline__ void sw64_tmul(const double (&fr)[16], int t, const V64 (&S)[4], V64& out, double sign) {
+  const int lane = threadIdx.x & 63, i = 16 * t + (lane & 15);
+#pragma unroll
+  for (int step = 0; step < 16; ++step) {
+    const int ct = step >> 2;
+    if (KIND == 5 && ct > t) continue;
+    if ((KIND == 7 || KIND == 4) && ct < t) continue;
+    const int kk = frag_k<double>(step, lane >> 4);
+    double a = fr[step];
+    if (KIND == 5) a = i >= kk ? a : 0.0;
+    if (KIND == 7) a = i < kk ? a : 0.0;
+    if (KIND == 4) a = i < kk ? a : (i == kk ? 1.0 : 0.0);
+    out = mfma_step(sign * a, S[ct][step & 3], out);
+  }
+}
+
+// Transposed forward (U^T, top to bottom): W_b = U11^{-T} R_b, R_{b+1} -= U12^T W_b;
+// W written to a.dst.
+__device__ void sw64_tforward(const SolveArgs& a, const Geom& g, int j, int c0, int mc, double* lds,
+                              const double* Ct, const double* Cb) {
+  const Layout& L = a.L;
+  const int t = threadIdx.x >> 6, lane = threadIdx.x & 63, nb = g.nb;
+  const double* fac = wsp<double>(a.ws, L.fac) + (size_t)j * L.nbmax * L.rec;
+  double up[16], upn[16];
+  V64 ud, udn;
+  auto load_ud = [&](int b, V64& d) {
+    const double* u = fac + (size_t)b * L.rec + 2 * 64 * 64;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) d[v] = u[16 * t + acc_row<double>(lane, v)];
+  };
+  sw64_tfrags(up, fac + 64 * 64, t);
+  load_ud(0, ud);
+  V64 r = sw64_rhs(a, g, 0, t, c0, mc, Ct, Cb), S[4], Wf[4];
+  for (int b = 0; b < nb; ++b) {
+    const bool last = b == nb - 1;
+    const int bn = last ? b : b + 1;
+    sw64_tfrags(upn, fac + (size_t)bn * L.rec + 64 * 64, t);
+    load_ud(bn, udn);
+    V64 rn = sw64_rhs(a, g, bn, t, c0, mc, Ct, Cb);
+    sw64_exchange(lds + Sw64::oA, r, t, S);
+    V64 w = V64{0, 0, 0, 0};
+    sw64_tmul<5>(up, t, S, w, 1.0);
+    sw64_exchange(lds + Sw64::oB, w, t, Wf);
+    if (!last) {
+      sw64_tmul<7>(up, t, Wf, rn, -1.0);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) rn[v] -= ud[v] * w[v];
+    }
+    sw64_store(a, g, b, t, c0, mc, w);
+    r = rn;
+    ud = udn;
+#pragma unroll
+    for (int s2 = 0; s2 < 16; ++s2) up[s2] = upn[s2];
+  }
+}
+
+// Transposed backward (L^T, bottom to top) over a.dst: u_b = L11^{-T}(W_b -
+// L21^T u_{b+1}).  TIPS: u is not stored; its first and last K real rows go to
+// the tip buffer.
+template <bool TIPS>
+__device__ void sw64_tbackward(const SolveArgs& a, const Geom& g, int j, int c0, int mc, double* lds) {
+  const Layout& L = a.L;
+  const int t = threadIdx.x >> 6, lane = threadIdx.x & 63, nb = g.nb;
+  const double* fac = wsp<double>(a.ws, L.fac) + (size_t)j * L.nbmax * L.rec;
+  double* yt = wsp<double>(a.ws, L.ytip) + (size_t)j * 2 * 64 * L.mmax;
+  SolveArgs ad = a;
+  ad.src = a.dst;
+  double lp[16], lpn[16];
+  sw64_tfrags(lp, fac + (size_t)(nb - 1) * L.rec, t);
+  V64 zt = sw64_rhs(ad, g, nb - 1, t, c0, mc, nullptr, nullptr), U1[4], Zf[4];
+  for (int q = 0; q < 4; ++q) U1[q] = V64{0, 0, 0, 0};
+  for (int b = nb - 1; b >= 0; --b) {
+    const int bn = b > 0 ? b - 1 : 0;
+    sw64_tfrags(lpn, fac + (size_t)bn * L.rec, t);
+    V64 ztn = sw64_rhs(ad, g, bn, t, c0, mc, nullptr, nullptr);
+    if (b < nb - 1) sw64_tmul<5>(lp, t, U1, zt, -1.0);  // W_b - L21^T u_{b+1}
+    sw64_exchange(lds + Sw64::oA, zt, t, Zf);
+    V64 u = V64{0, 0, 0, 0};
+    sw64_tmul<4>(lp, t, Zf, u, 1.0);
+    if (TIPS) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int lr = b * 64 + 16 * t + acc_row<double>(lane, v) - g.pad, col = lane & 15;
+        if (lr >= 0 && col < mc) {
+          if (lr < 64) yt[(size_t)lr * L.mmax + c0 + col] = u[v];
+          if (lr >= g.nj - 64) yt[(size_t)(64 + lr - (g.nj - 64)) * L.mmax + c0 + col] = u[v];
+        }
+      }
+    } else {
+      sw64_store(a, g, b, t, c0, mc, u);
+    }
+    sw64_exchange(lds + Sw64::oB, u, t, U1);
+    zt = ztn;
+#pragma unroll
+    for (int s2 = 0; s2 < 16; ++s2) lp[s2] = lpn[s2];
+  }
+}
+
+// Adjoint D-stage at K = 64: nu_j = A_j^{-T} g_j (W into a.dst), tips to the tip buffer.
+__global__ __launch_bounds__(256) void adj_dstage64_kernel(SolveArgs a) {
+  if (gated(a.gate)) return;
+  __shared__ __align__(16) double lds[Sw64::total];
+  const int j = blockIdx.x, c0 = blockIdx.y * 16, mc = min(16, a.m - c0);
+  const Geom g = part_geom(a.L, j, 64);
+  sw64_tforward(a, g, j, c0, mc, lds, nullptr, nullptr);
+  __syncthreads();
+  sw64_tbackward<true>(a, g, j, c0, mc, lds);
+}
+
+// Adjoint recovery at K = 64: lambda_j = A_j^{-T}(g_j - [w_{j,t}; 0; w_{j,b}]) in place,
+//   w_{j,t} = B_{j-1}^T nu_{j-1,b} - Pi_{j-1} u_a(j-1)      (j >= 1)
+//   w_{j,b} = C_{j+1}^T nu_{j+1,t} - Psi_{j+1} u_c(j+1)      (j <= p-2).
+__global__ __launch_bounds__(256) void adj_retrieve64_kernel(SolveArgs a) {
+  if (gated(a.gate)) return;
+  __shared__ __align__(16) double lds[Sw64::total];
+  const Layout& L = a.L;
+  const int j = blockIdx.x, c0 = blockIdx.y * 16, mc = min(16, a.m - c0), k = L.k, r = L.r;
+  const Geom g = part_geom(L, j, 64);
+  double* Ct = lds + Sw64::oCt;
+  double* Cb = lds + Sw64::oCb;
+  const double* ytip = wsp<double>(a.ws, L.ytip);
+  const double* proj = wsp<double>(a.ws, L.proj);
+  const double* zg = wsp<double>(a.ws, L.zg);
+  if (j > 0) {
+    const double* nub = ytip + ((size_t)(j - 1) * 2 + 1) * 64 * L.mmax;
+    const double* Pi = proj + (size_t)(j - 1) * 2 * 64 * r;
+    const double* ua = zg + (size_t)(j - 1) * L.R2 * L.mmax;
+    for (int o = threadIdx.x; o < 64 * mc; o += blockDim.x) {
+      const int i = o / mc, c = o % mc;
+      double s = 0.0;
+      for (int l = 0; l < 64; ++l) s += band_at(a.bands, L.n, k, g.s - 64 + l, g.s + i) * nub[l * L.mmax + c0 + c];
+      for (int q = 0; q < r; ++q) s -= Pi[i * r + q] * ua[q * L.mmax + c0 + c];
+      Ct[i * 17 + c] = s;
+    }
+  }
+  if (j < L.p - 1) {
+    const double* nut = ytip + ((size_t)(j + 1) * 2 + 0) * 64 * L.mmax;
+    const double* Psi = proj + ((size_t)(j + 1) * 2 + 1) * 64 * r;
+    const double* uc = zg + ((size_t)j * L.R2 + r) * L.mmax;
+    const int64_t s1 = g.s + g.nj;
+    for (int o = threadIdx.x; o < 64 * mc; o += blockDim.x) {
+      const int i = o / mc, c = o % mc;
+      double s = 0.0;
+      for (int l = 0; l < 64; ++l) s += band_at(a.bands, L.n, k, s1 + l, s1 - 64 + i) * nut[l * L.mmax + c0 + c];
+      for (int q = 0; q < r; ++q) s -= Psi[i * r + q] * uc[q * L.mmax + c0 + c];
+      Cb[i * 17 + c] = s;
+    }
+  }
+  __syncthreads();
+  sw64_tforward(a, g, j, c0, mc, lds, j > 0 ? Ct : nullptr, j < L.p - 1 ? Cb : nullptr);
+  __syncthreads();
+  sw64_tbackward<false>(a, g, j, c0, mc, lds);
+}
+
 }  // namespace lrs
