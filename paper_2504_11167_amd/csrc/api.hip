@@ -354,8 +354,12 @@ int run_factor(lrspike_plan P) {
     if (!set_lds((const void*)factor_lds_kernel<T, K>, bf) || !set_lds((const void*)spike_lds_kernel<T, K>, bs))
       return LRSPIKE_ERR_NOT_SUPPORTED;
     LRS_LAUNCH("factor_pass1", factor_lds_kernel<T, K>, dim3(L.p), dim3(LRS_NT), bf, fa);
-    if (!rsvd)
-      LRS_LAUNCH("spike_fwd", spike_lds_kernel<T, K>, dim3(L.p, 2, K / SLds<T, K>::MS), dim3(LRS_NT), bs, fa);
+    if (!rsvd) {
+      if constexpr (std::is_same<T, double>::value)
+        LRS_LAUNCH("spike_fwd", spike64_kernel, dim3(L.p, 4, 2), dim3(256), 0, fa);
+      else
+        LRS_LAUNCH("spike_fwd", spike_lds_kernel<T, K>, dim3(L.p, 2, K / SLds<T, K>::MS), dim3(LRS_NT), bs, fa);
+    }
   } else if constexpr (K >= 16) {
     // one wave per partition without interchanges; partitions that need them
     // are flagged and refactored by the general kernel (a no-op elsewhere)
@@ -377,7 +381,9 @@ int run_factor(lrspike_plan P) {
     // randomized SVD: Grams and tips of the sketched spikes Q Q^T V
     if ((rc = run_rsvd<T, K>(P))) return rc;
   } else if (L.r < L.K) {
-    if constexpr (K == 64) {
+    if constexpr (K == 64 && std::is_same<T, double>::value) {
+      LRS_LAUNCH("factor_pass2", pass2_64_kernel, dim3(L.p, 2), dim3(256), 0, fa);
+    } else if constexpr (K == 64) {
       const size_t b2 = (size_t)4 * K * (K + 1) * sizeof(T);
       if (!set_lds((const void*)pass2_lds_kernel<T, K>, b2)) return LRSPIKE_ERR_NOT_SUPPORTED;
       LRS_LAUNCH("factor_pass2", pass2_lds_kernel<T, K>, dim3(L.p, 2), dim3(LRS_NT), b2, fa);

@@ -26,9 +26,20 @@ namespace lrs {
 // and the B fragment B(4s + lane / 16, 16ct + lane mod 16).  TRI skips the
 // 16 x 16 tiles a triangular operand leaves zero: 1 A lower, 2 A upper,
 // 3 B upper, 4 B lower.
+// The thread index is re-read opaquely at every call, so that the operand
+// addresses are formed next to their use instead of being hoisted out of the
+// callers' block loops (where they would occupy registers for the whole loop);
+// the wave index is made uniform, so the triangular skips are scalar branches.
+__device__ __forceinline__ void lds_lane_wave(int& lane, int& w) {
+  int t = threadIdx.x;
+  asm volatile("" : "+v"(t));
+  lane = t & 63;
+  w = __builtin_amdgcn_readfirstlane(t >> 6);
+}
 template <typename T, int TRI, typename FA, typename FB>
 __device__ __forceinline__ void mm64(typename AccVec<T>::type (&acc)[4], FA a, FB b) {
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  int lane, w;
+  lds_lane_wave(lane, w);
   const int i = 16 * w + (lane & 15), kq = lane >> 4, jl = lane & 15;
 #pragma unroll
   for (int s = 0; s < 16; ++s) {
@@ -47,7 +58,8 @@ __device__ __forceinline__ void mm64(typename AccVec<T>::type (&acc)[4], FA a, F
 // mm32: C (32 x 32) += A B, wave w owns the 16 x 16 tile (w / 2, w mod 2).
 template <typename T, typename FA, typename FB>
 __device__ __forceinline__ void mm32(typename AccVec<T>::type& acc, FA a, FB b) {
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  int lane, w;
+  lds_lane_wave(lane, w);
   const int i = 16 * (w >> 1) + (lane & 15), j = 16 * (w & 1) + (lane & 15), kq = lane >> 4;
 #pragma unroll
   for (int s = 0; s < 8; ++s) {
@@ -108,15 +120,17 @@ __global__ __launch_bounds__(LRS_NT) void factor_lds_kernel(FactorArgs a) {
     constexpr int NI = (2 * K - 1 + 3) / 4;
     int i = tid & 63;  // opaque: keeps the per-diagonal addresses from being hoisted out of the block loop
     asm volatile("" : "+v"(i));
-    const int w = tid >> 6;
+    const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int lr = R * K + i - g.pad;
     T vals[NI];
 #pragma unroll
     for (int t = 0; t < NI; ++t) {
+      // bitwise conjunction: a select of the index, not a branch per load
       const int e = w + 4 * t - (K - 1), c = i + e, lc = C * K + c - g.pad, d = lc - lr;
-      const bool inb = e <= K - 1 && c >= 0 && c < K && lr >= 0 && lr < g.nj && lc >= 0 && lc < g.nj &&
-                       d >= -k && d <= k;
-      vals[t] = (T)a.bands[inb ? (int64_t)(d + k) * L.n + g.s + lr : 0];
+      const bool inb = (e <= K - 1) & (c >= 0) & (c < K) & (lr >= 0) & (lr < g.nj) & (lc >= 0) & (lc < g.nj) &
+                       (d >= -k) & (d <= k);
+      const int64_t idx = (int64_t)(d + k) * L.n + g.s + lr;
+      vals[t] = (T)a.bands[inb ? idx : 0];
     }
     T am = T(0);
 #pragma unroll
@@ -134,6 +148,9 @@ __global__ __launch_bounds__(LRS_NT) void factor_lds_kernel(FactorArgs a) {
   for (int o = tid; o < K * K; o += LRS_NT) Gp[(o / K) * PT + o % K] = T(0);
   if (tid == 0) s_bad = 0;
   for (int b = 0; b < nb; ++b) {
+    // the thread index re-read opaquely per block (see lds_lane_wave)
+    int tid = threadIdx.x;
+    asm volatile("" : "+v"(tid));
     const bool last = (b == nb - 1);
     if (!last) {
       load_block(P + K * PT, b + 1, b);
@@ -217,7 +234,7 @@ __global__ __launch_bounds__(LRS_NT) void factor_lds_kernel(FactorArgs a) {
       };
       auto blk = [&](int r0, int c0, int i, int l) -> T { return P[(r0 + i) * PT + c0 + l]; };
       using AV = typename AccVec<T>::type;
-      const int w = tid >> 6;
+      const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
       // 32 x 32 results: element v of wave w's tile at (row, col) of the quadrant
       auto put32 = [&](const AV& acc, int r0, int c0, T sg) {
 #pragma unroll
@@ -303,7 +320,7 @@ __global__ __launch_bounds__(LRS_NT) void factor_lds_kernel(FactorArgs a) {
       return r <= l ? x : T(0);
     };
     using AV = typename AccVec<T>::type;
-    const int lane = tid & 63, w = tid >> 6;
+    const int lane = tid & 63, w = __builtin_amdgcn_readfirstlane(tid >> 6);
     // (row, col) of element v of accumulator tile ct
     auto each = [&](auto&& fn) {
 #pragma unroll

@@ -238,6 +238,221 @@ __global__ __launch_bounds__(256) void retrieve64_kernel(SolveArgs a) {
   sw64_backward(a, g, j, c0, mc, lds);
 }
 
+// ------------------------------------------------------------------ spikes
+// The spikes at K = 64 in the same layout (four waves, wave t owning row tile
+// t, fragments read from the records).  Forward, grid (p, 4 groups of 16 spike
+// columns, 2 spikes):
+//   W (spike 0): rhs [C_j; 0], nonzero in the first K real rows only, swept
+//     forward; W_t = sum_b G_b^T z_b, W_b = U11^{-1} z_last;
+//   V (spike 1): rhs [0; B_j], the last block only: z = L11^{-1} B_j there,
+//     V_t = G_last^T z, V_b = U11^{-1} z;
+// z_b goes to the Y array (row-major, both spikes side by side) for the Gram
+// back-sweeps when r < K.  Tips: V_t, V_b, W_t, W_b (K x K each, row-major).
+__global__ __launch_bounds__(256) void spike64_kernel(FactorArgs a) {
+  __shared__ __align__(16) double lds[2 * Sw64::STRIP];
+  const Layout& L = a.L;
+  const int j = blockIdx.x, c0 = blockIdx.y * 16, spike = blockIdx.z, k = L.k;
+  const int t = threadIdx.x >> 6, lane = threadIdx.x & 63, col = lane & 15;
+  const Geom g = part_geom(L, j, 64);
+  const int nb = g.nb;
+  const double* fac = wsp<double>(a.ws, L.fac) + (size_t)j * L.nbmax * L.rec;
+  const double* gm = wsp<double>(a.ws, L.gmat) + (size_t)j * L.nbmax * 64 * 64;
+  double* ym = L.r < 64 ? wsp<double>(a.ws, L.ymat) + (size_t)j * L.nbmax * 2 * 64 * 64 : nullptr;
+  double* tips = wsp<double>(a.ws, L.tips) + (size_t)j * 4 * 64 * 64;
+  // right-hand-side tile t of block b (the coupling blocks of the band)
+  auto rhs = [&](int b) {
+    V64 r = V64{0, 0, 0, 0};
+    const bool nz = spike == 0 ? (j > 0 && b * 64 - g.pad < 64) : (j < L.p - 1 && b == nb - 1);
+    if (nz) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int lr = b * 64 + 16 * t + acc_row<double>(lane, v) - g.pad;
+        if (lr >= 0 && lr < g.nj)
+          r[v] = spike == 0 ? (lr < 64 ? band_at(a.bands, L.n, k, g.s + lr, g.s - 64 + c0 + col) : 0.0)
+                            : band_at(a.bands, L.n, k, g.s + lr, g.s + g.nj + c0 + col);
+      }
+    }
+    return r;
+  };
+  auto store_y = [&](int b, const V64& z) {
+    if (!ym) return;
+#pragma unroll
+    for (int v = 0; v < 4; ++v)
+      ym[(size_t)b * 2 * 64 * 64 + (16 * t + acc_row<double>(lane, v)) * 128 + spike * 64 + c0 + col] = z[v];
+  };
+  // tips (which, which + 1) = (top, bottom); the last block's U11^{-1} z gives the bottom
+  auto finish = [&](int b, const V64 (&Z)[4], const V64& top, int which) {
+    double up[16];
+    sw64_frags(up, fac + (size_t)b * L.rec + 64 * 64, t);
+    V64 yb = V64{0, 0, 0, 0};
+    sw64_mul<2>(up, t, Z, yb, 1.0);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int row = 16 * t + acc_row<double>(lane, v);
+      tips[(size_t)which * 64 * 64 + row * 64 + c0 + col] = top[v];
+      tips[(size_t)(which + 1) * 64 * 64 + row * 64 + c0 + col] = yb[v];
+    }
+  };
+  double lp[16], gt[16];
+  V64 S[4], Z[4], acc = V64{0, 0, 0, 0};
+  if (spike == 1) {
+    const int b = nb - 1;
+    sw64_frags(lp, fac + (size_t)b * L.rec, t);
+    sw64_frags(gt, gm + (size_t)b * 64 * 64, t);
+    sw64_exchange(lds + Sw64::oA, rhs(b), t, S);
+    V64 z = V64{0, 0, 0, 0};
+    sw64_mul<0>(lp, t, S, z, 1.0);
+    sw64_exchange(lds + Sw64::oB, z, t, Z);
+    sw64_mul<9>(gt, t, Z, acc, 1.0);
+    store_y(b, z);
+    finish(b, Z, acc, 0);
+    return;
+  }
+  double lpn[16], gtn[16];
+  sw64_frags(lp, fac, t);
+  sw64_frags(gt, gm, t);
+  V64 r = rhs(0);
+  for (int b = 0; b < nb; ++b) {
+    const bool last = b == nb - 1;
+    const int bn = last ? b : b + 1;  // (clamped: the prefetch is unconditional)
+    sw64_frags(lpn, fac + (size_t)bn * L.rec, t);
+    sw64_frags(gtn, gm + (size_t)bn * 64 * 64, t);
+    V64 rn = rhs(bn);
+    sw64_exchange(lds + Sw64::oA, r, t, S);
+    V64 z = V64{0, 0, 0, 0};
+    sw64_mul<0>(lp, t, S, z, 1.0);
+    sw64_exchange(lds + Sw64::oB, z, t, Z);
+    if (!last) sw64_mul<1>(lp, t, Z, rn, -1.0);
+    sw64_mul<9>(gt, t, Z, acc, 1.0);
+    store_y(b, z);
+    if (last) finish(b, Z, acc, 2);
+    r = rn;
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      lp[q] = lpn[q];
+      gt[q] = gtn[q];
+    }
+  }
+}
+
+// Gram back-sweeps at K = 64 (r < K), one workgroup per (partition, spike),
+// all 64 spike columns:  z_b = U11^{-1} (Y_b - U12 z_{b+1}),  Gram += z_b^T z_b
+// (V's forward result is zero above the last block).  Wave t forms row tile t
+// of each product from its fragments of the records; the 64 x 64 operands
+// live in LDS as 16 accumulator tiles (tile (u, c): rows 16u.., columns 16c..),
+// and both the B operand of a product and the transposed A operand of the Gram
+// are, lane for lane, element (step mod 4) of tile (step / 4, c).
+struct P64 {
+  static constexpr int TILE = 64 * 4, MAT = 16 * TILE;
+  static constexpr int oT = 0, oZ = MAT, total = 2 * MAT;
+};
+
+__device__ __forceinline__ const double* p64_tile(const double* m, int u, int c) {
+  return m + (size_t)(u * 4 + c) * P64::TILE;
+}
+
+// out[c] (+)= sign * A(row tile t) * M(:, column tile c) for the four column
+// tiles; A's fragments fr[step] masked as in sw64_mul (kinds 2 and 3)
+template <int KIND>
+__device__ __forceinline__ void p64_mul(const double (&fr)[16], int t, const double* M, V64 (&out)[4], double sign) {
+  const int lane = threadIdx.x & 63, i = 16 * t + (lane & 15);
+#pragma unroll
+  for (int step = 0; step < 16; ++step) {
+    const int ct = step >> 2;
+    if (KIND == 3 && ct > t) continue;
+    if (KIND == 2 && ct < t) continue;
+    const int kk = frag_k<double>(step, lane >> 4);
+    double av = fr[step];
+    if (KIND == 2) av = i <= kk ? av : 0.0;
+    if (KIND == 3) av = i > kk ? av : 0.0;
+    av *= sign;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) out[c] = mfma_step(av, p64_tile(M, ct, c)[lane * 4 + (step & 3)], out[c]);
+  }
+}
+
+__device__ __forceinline__ void p64_put(double* M, int t, const V64 (&x)[4]) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int c = 0; c < 4; ++c) *reinterpret_cast<V64*>(M + (size_t)(t * 4 + c) * P64::TILE + lane * 4) = x[c];
+}
+
+__global__ __launch_bounds__(256) void pass2_64_kernel(FactorArgs a) {
+  __shared__ __align__(16) double lds[P64::total];
+  double* Tm = lds + P64::oT;
+  double* Zm = lds + P64::oZ;
+  const Layout& L = a.L;
+  const int j = blockIdx.x, spike = blockIdx.y;
+  const int t = threadIdx.x >> 6, lane = threadIdx.x & 63, col = lane & 15;
+  const Geom g = part_geom(L, j, 64);
+  const int nb = g.nb;
+  const double* fac = wsp<double>(a.ws, L.fac) + (size_t)j * L.nbmax * L.rec;
+  const double* ym = wsp<double>(a.ws, L.ymat) + (size_t)j * L.nbmax * 2 * 64 * 64;
+  const int coff = spike == 0 ? 0 : 64;
+  auto load_y = [&](int b, V64 (&y)[4]) {
+    const bool nz = spike == 0 || b == nb - 1;
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+#pragma unroll
+      for (int v = 0; v < 4; ++v)
+        y[c][v] = nz ? ym[(size_t)b * 2 * 64 * 64 + (16 * t + acc_row<double>(lane, v)) * 128 + coff + 16 * c + col] : 0.0;
+  };
+  auto load_ud = [&](int b, V64& d) {
+    const double* u = fac + (size_t)b * L.rec + 2 * 64 * 64;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) d[v] = u[16 * t + acc_row<double>(lane, v)];
+  };
+  double up[16], upn[16];
+  V64 y[4], yn[4], ud, udn, zo[4], gr[4];
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    gr[c] = V64{0, 0, 0, 0};
+    zo[c] = V64{0, 0, 0, 0};
+  }
+  sw64_frags(up, fac + (size_t)(nb - 1) * L.rec + 64 * 64, t);
+  load_ud(nb - 1, ud);
+  load_y(nb - 1, y);
+  for (int b = nb - 1; b >= 0; --b) {
+    const int bn = b > 0 ? b - 1 : 0;  // (clamped: the prefetch is unconditional)
+    sw64_frags(upn, fac + (size_t)bn * L.rec + 64 * 64, t);
+    load_ud(bn, udn);
+    load_y(bn, yn);
+    // Tm = Y_b - U12 z_{b+1}: strictly lower part of UP plus the diagonal UD
+    if (b < nb - 1) {
+      p64_mul<3>(up, t, Zm, y, -1.0);
+#pragma unroll
+      for (int c = 0; c < 4; ++c)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) y[c][v] -= ud[v] * zo[c][v];
+    }
+    p64_put(Tm, t, y);
+    __syncthreads();
+    // z_b = U11^{-1} Tm
+#pragma unroll
+    for (int c = 0; c < 4; ++c) zo[c] = V64{0, 0, 0, 0};
+    p64_mul<2>(up, t, Tm, zo, 1.0);
+    p64_put(Zm, t, zo);
+    __syncthreads();
+    // Gram row tile t += (z_b^T)(tile t) z_b
+#pragma unroll
+    for (int step = 0; step < 16; ++step) {
+      const double av = p64_tile(Zm, step >> 2, t)[lane * 4 + (step & 3)];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) gr[c] = mfma_step(av, p64_tile(Zm, step >> 2, c)[lane * 4 + (step & 3)], gr[c]);
+    }
+#pragma unroll
+    for (int c = 0; c < 4; ++c) y[c] = yn[c];
+    ud = udn;
+#pragma unroll
+    for (int q = 0; q < 16; ++q) up[q] = upn[q];
+  }
+  double* gram = wsp<double>(a.ws, L.gram) + ((size_t)j * 2 + (spike == 0 ? 1 : 0)) * 64 * 64;
+#pragma unroll
+  for (int c = 0; c < 4; ++c)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) gram[(16 * t + acc_row<double>(lane, v)) * 64 + 16 * c + col] = gr[c][v];
+}
+
 // ------------------------------------------------------------------ adjoint
 // A_j^{-T} = L^{-T} U^{-T}: the transposed sweeps on fragments gathered
 // transposed from the records (element (i, kk) of row tile t read at the
