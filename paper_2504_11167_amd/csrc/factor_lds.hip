@@ -112,30 +112,39 @@ __global__ __launch_bounds__(LRS_NT) void factor_lds_kernel(FactorArgs a) {
     return (T)a.bands[(int64_t)(d + k) * L.n + g.s + lr];
   };
   (void)Aj;
-  // K x K block (rows of block R, columns of block C) into dst (pitch PT).
-  // Lane = block row, so a wave reads one diagonal segment (coalesced); the
-  // waves take every fourth diagonal offset e = c - i; every load is issued
-  // (from a clamped, always valid address) before any store.
-  auto load_block = [&](T* dst, int R, int C) {
-    constexpr int NI = (2 * K - 1 + 3) / 4;
+  // K x K block (rows of block R, columns of block C) into dst (pitch PT)
+  // by the last NW waves of the workgroup (fetched into registers, then put).  Lane = block row, so a wave reads
+  // one diagonal segment (coalesced); the waves take every NW-th diagonal
+  // offset e = c - i; every load is issued (from a clamped, always valid
+  // address) before any store.
+  auto block_fetch = [&](auto& vals, int R, int C, auto nw) {
+    constexpr int NW = decltype(nw)::value;
+    constexpr int NI = (2 * K - 1 + NW - 1) / NW;
     int i = tid & 63;  // opaque: keeps the per-diagonal addresses from being hoisted out of the block loop
     asm volatile("" : "+v"(i));
-    const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int w = __builtin_amdgcn_readfirstlane(tid >> 6) - (LRS_NT / 64 - NW);
     const int lr = R * K + i - g.pad;
-    T vals[NI];
 #pragma unroll
     for (int t = 0; t < NI; ++t) {
       // bitwise conjunction: a select of the index, not a branch per load
-      const int e = w + 4 * t - (K - 1), c = i + e, lc = C * K + c - g.pad, d = lc - lr;
+      const int e = w + NW * t - (K - 1), c = i + e, lc = C * K + c - g.pad, d = lc - lr;
       const bool inb = (e <= K - 1) & (c >= 0) & (c < K) & (lr >= 0) & (lr < g.nj) & (lc >= 0) & (lc < g.nj) &
                        (d >= -k) & (d <= k);
       const int64_t idx = (int64_t)(d + k) * L.n + g.s + lr;
       vals[t] = (T)a.bands[inb ? idx : 0];
     }
+  };
+  auto block_put = [&](T* dst, const auto& vals, int R, int C, auto nw) {
+    constexpr int NW = decltype(nw)::value;
+    constexpr int NI = (2 * K - 1 + NW - 1) / NW;
+    int i = tid & 63;
+    asm volatile("" : "+v"(i));
+    const int w = __builtin_amdgcn_readfirstlane(tid >> 6) - (LRS_NT / 64 - NW);
+    const int lr = R * K + i - g.pad;
     T am = T(0);
 #pragma unroll
     for (int t = 0; t < NI; ++t) {
-      const int e = w + 4 * t - (K - 1), c = i + e, lc = C * K + c - g.pad, d = lc - lr;
+      const int e = w + NW * t - (K - 1), c = i + e, lc = C * K + c - g.pad, d = lc - lr;
       const bool inb = e <= K - 1 && c >= 0 && c < K && lr >= 0 && lr < g.nj && lc >= 0 && lc < g.nj &&
                        d >= -k && d <= k;
       const bool ident = (lr < 0 || lc < 0) && lr == lc;
@@ -144,19 +153,22 @@ __global__ __launch_bounds__(LRS_NT) void factor_lds_kernel(FactorArgs a) {
     }
     s_amax[tid] = fmax(s_amax[tid], (double)am);
   };
-  load_block(P, 0, 0);
+  auto load_block = [&](T* dst, int R, int C, auto nw) {
+    T vals[(2 * K - 1 + decltype(nw)::value - 1) / decltype(nw)::value];
+    block_fetch(vals, R, C, nw);
+    block_put(dst, vals, R, C, nw);
+  };
+  using W4 = std::integral_constant<int, LRS_NT / 64>;
+  using W3 = std::integral_constant<int, LRS_NT / 64 - 1>;
+  load_block(P, 0, 0, W4{});
   for (int o = tid; o < K * K; o += LRS_NT) Gp[(o / K) * PT + o % K] = T(0);
   if (tid == 0) s_bad = 0;
+  __syncthreads();
   for (int b = 0; b < nb; ++b) {
     // the thread index re-read opaquely per block (see lds_lane_wave)
     int tid = threadIdx.x;
     asm volatile("" : "+v"(tid));
     const bool last = (b == nb - 1);
-    if (!last) {
-      load_block(P + K * PT, b + 1, b);
-      load_block(U, b, b + 1);
-    }
-    __syncthreads();
     // ---- the diagonal block D (panel top) as 2 x 2 blocks of H = K/2 columns:
     //   [D11; D21] = [L1; L2'] U1 by the register elimination of one wave
     //   (lane = row, no interchanges), with L1^{-1} riding along and U1^{-1}
@@ -242,7 +254,14 @@ __global__ __launch_bounds__(LRS_NT) void factor_lds_kernel(FactorArgs a) {
           P[(r0 + 16 * (w >> 1) + acc_row<T>(lane, v)) * PT + c0 + 16 * (w & 1) + (lane & 15)] = sg * acc[v];
       };
       AV a1, a2;
-      if (tid < 64) reg_lu(0, K);
+      // wave 0 factors the left half of the panel top while the other waves
+      // bring in Lo_{b+1} (panel bottom) and Up_b (free since the last block)
+      if (tid < 64)
+        reg_lu(0, K);
+      else if (!last) {
+        load_block(P + K * PT, b + 1, b, W3{});
+        load_block(U, b, b + 1, W3{});
+      }
       __syncthreads();
       // U1' = L1^{-1} D12 (in place)
       a1 = AV{0, 0, 0, 0};
@@ -362,11 +381,13 @@ __global__ __launch_bounds__(LRS_NT) void factor_lds_kernel(FactorArgs a) {
       each([&](int ct, int v, int row, int col) { Gp[row * PT + col] = -acc[ct][v]; });
     }
     // ---- records: LP = L11^{-1} strict lower | L21 upper;  UP = U11^{-1} upper | U12 strict lower; UD
+    // (written in storage order: coalesced stores)
     T* rec = fac + (size_t)b * L.rec;
     for (int o = tid; o < K * K; o += LRS_NT) {
-      const int i = o / K, c = o % K, f = fidx<T, K>(i, c);
-      rec[f] = (i > c) ? P[i * PT + c] : (last ? T(0) : P[(K + i) * PT + c]);
-      rec[K * K + f] = (i <= c) ? P[i * PT + c] : (last ? T(0) : U[i * PT + c]);
+      int i, c;
+      fidx_inv<T, K>(o, i, c);
+      rec[o] = (i > c) ? P[i * PT + c] : (last ? T(0) : P[(K + i) * PT + c]);
+      rec[K * K + o] = (i <= c) ? P[i * PT + c] : (last ? T(0) : U[i * PT + c]);
     }
     if (tid < K) {
       rec[2 * K * K + tid] = last ? T(0) : U[tid * PT + tid];
@@ -382,7 +403,7 @@ __global__ __launch_bounds__(LRS_NT) void factor_lds_kernel(FactorArgs a) {
         return r <= l ? x : T(0);
       },
                  [&](int l, int c) { return U[l * PT + c]; });
-      load_block(P, b + 1, b + 1);  // D_{b+1} (the panel top is free once the records are out)
+      load_block(P, b + 1, b + 1, W4{});  // D_{b+1} (the panel top is free once the records are out)
       __syncthreads();
       each([&](int ct, int v, int row, int col) { P[row * PT + col] -= acc[ct][v]; });
       __syncthreads();
