@@ -377,7 +377,7 @@ __device__ __forceinline__ void p64_put(double* M, int t, const V64 (&x)[4]) {
   for (int c = 0; c < 4; ++c) *reinterpret_cast<V64*>(M + (size_t)(t * 4 + c) * P64::TILE + lane * 4) = x[c];
 }
 
-__global__ __launch_bounds__(256) void pass2_64_kernel(FactorArgs a) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void pass2_64_kernel(FactorArgs a) {
   __shared__ __align__(16) double lds[P64::total];
   double* Tm = lds + P64::oT;
   double* Zm = lds + P64::oZ;
@@ -402,21 +402,19 @@ __global__ __launch_bounds__(256) void pass2_64_kernel(FactorArgs a) {
 #pragma unroll
     for (int v = 0; v < 4; ++v) d[v] = u[16 * t + acc_row<double>(lane, v)];
   };
-  double up[16], upn[16];
-  V64 y[4], yn[4], ud, udn, zo[4], gr[4];
+  double up[16];
+  V64 y[4], ud, zo[4], gr[4];
 #pragma unroll
   for (int c = 0; c < 4; ++c) {
     gr[c] = V64{0, 0, 0, 0};
     zo[c] = V64{0, 0, 0, 0};
   }
-  sw64_frags(up, fac + (size_t)(nb - 1) * L.rec + 64 * 64, t);
-  load_ud(nb - 1, ud);
-  load_y(nb - 1, y);
   for (int b = nb - 1; b >= 0; --b) {
-    const int bn = b > 0 ? b - 1 : 0;  // (clamped: the prefetch is unconditional)
-    sw64_frags(upn, fac + (size_t)bn * L.rec + 64 * 64, t);
-    load_ud(bn, udn);
-    load_y(bn, yn);
+    // no prefetch: at two waves per SIMD (at most 256 registers, no spills)
+    // the two workgroups of a CU hide each other's load latency
+    sw64_frags(up, fac + (size_t)b * L.rec + 64 * 64, t);
+    load_ud(b, ud);
+    load_y(b, y);
     // Tm = Y_b - U12 z_{b+1}: strictly lower part of UP plus the diagonal UD
     if (b < nb - 1) {
       p64_mul<3>(up, t, Zm, y, -1.0);
@@ -440,11 +438,6 @@ __global__ __launch_bounds__(256) void pass2_64_kernel(FactorArgs a) {
 #pragma unroll
       for (int c = 0; c < 4; ++c) gr[c] = mfma_step(av, p64_tile(Zm, step >> 2, c)[lane * 4 + (step & 3)], gr[c]);
     }
-#pragma unroll
-    for (int c = 0; c < 4; ++c) y[c] = yn[c];
-    ud = udn;
-#pragma unroll
-    for (int q = 0; q < 16; ++q) up[q] = upn[q];
   }
   double* gram = wsp<double>(a.ws, L.gram) + ((size_t)j * 2 + (spike == 0 ? 1 : 0)) * 64 * 64;
 #pragma unroll
