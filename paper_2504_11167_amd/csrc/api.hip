@@ -337,6 +337,28 @@ int run_rsvd(lrspike_plan P) {
   return 0;
 }
 
+// The randomized truncation's small eigenproblem: R_h R_h^T of order KE (a
+// power of two <= 64) per (partition, spike), eigenvectors written at re.L.proj.
+template <int KE>
+static int eigen_small_t(lrspike_plan P, const RedArgs& re) {
+  const size_t be = (size_t)2 * KE * (KE + 1) * 8;
+  if (!set_lds((const void*)eigen_kernel<KE>, be)) return LRSPIKE_ERR_NOT_SUPPORTED;
+  LRS_LAUNCH("eigen_kernel", eigen_kernel<KE>, dim3(P->L.p, 2), dim3(LRS_NT), be, re);
+  return 0;
+}
+static int eigen_small(lrspike_plan P, int KE, const RedArgs& re) {
+  switch (KE) {
+    case 1: return eigen_small_t<1>(P, re);
+    case 2: return eigen_small_t<2>(P, re);
+    case 4: return eigen_small_t<4>(P, re);
+    case 8: return eigen_small_t<8>(P, re);
+    case 16: return eigen_small_t<16>(P, re);
+    case 32: return eigen_small_t<32>(P, re);
+    case 64: return eigen_small_t<64>(P, re);
+    default: return LRSPIKE_ERR_NOT_SUPPORTED;
+  }
+}
+
 template <typename T, int K>
 int run_factor(lrspike_plan P) {
   const Layout& L = P->L;
@@ -396,7 +418,15 @@ int run_factor(lrspike_plan P) {
     }
   }
   if (L.r < L.K) {
-    if (L.r > 0) {
+    if (L.r > 0 && rsvd) {
+      // eigenvectors W of R_h R_h^T over the sketch (no longer needed), then Pi = Q_b W
+      RedArgs re = ra;
+      re.L.proj = L.ysk;
+      if ((rc = eigen_small(P, rsvd_ke(L.ell), re))) return rc;
+      RsvdArgs rl{P->bands, P->ws, L, nullptr};
+      LRS_LAUNCH("rsvd_lift_kernel", rsvd_lift_kernel, dim3(L.p, 2), dim3(256), 0, rl,
+                 reinterpret_cast<const double*>(P->ws + L.ysk));
+    } else if (L.r > 0) {
       const size_t be = (size_t)2 * K * (K + 1) * 8;
       if (!set_lds((const void*)eigen_kernel<K>, be)) return LRSPIKE_ERR_NOT_SUPPORTED;
       LRS_LAUNCH("eigen_kernel", eigen_kernel<K>, dim3(L.p, 2), dim3(LRS_NT), be, ra);

@@ -11,10 +11,12 @@
 //       diagonal pivoting; sketch directions whose residual norm falls below
 //       1e-6 of the largest column are dropped as numerically dependent),
 //   B = Q^T V = R^{-T} (V^T Y_S)^T,  Q Q^T V = Y_S T with T = R^{-1} B  (ell' x k).
-// The truncation then proceeds exactly as for the whole spike, on Q Q^T V:
-// its Gram (Q Q^T V)^T (Q Q^T V) = B^T B and its tips Y_{S,t} T, Y_{S,b} T
-// go to the Gram and tip slots, where the eigen-decomposition and the
-// projection of the exact path take them up.
+// The truncation then proceeds as for the whole spike, on Q Q^T V: its tips
+// Y_{S,t} T, Y_{S,b} T go to the tip slots; its Gram (Q Q^T V)^T (Q Q^T V) =
+// B^T B has rank ell' only, so instead of that K x K matrix (whose K - ell'
+// zero eigenvalues would only slow the Jacobi sweeps) the eigensolver takes
+// R_h R_h^T from the thin QR B^T = Q_b R_h (ell' x ell'), and the right
+// singular vectors of B are Q_b times its eigenvectors (rsvd_lift_kernel).
 //
 // Column conventions: the oracle-style k columns of a spike map to the
 // K-padded spike columns b (V) and K - k + b (W), as in the spike sweeps.
@@ -151,12 +153,18 @@ __global__ __launch_bounds__(256) void rsvd_vty_kernel(RsvdArgs a) {
   }
 }
 
+// Order of the small eigenproblem: the smallest power of two >= ell.
+__host__ __device__ constexpr int rsvd_ke(int ell) { return ell <= 1 ? 1 : (ell <= 2 ? 2 : (ell <= 4 ? 4 : (ell <= 8 ? 8 : (ell <= 16 ? 16 : (ell <= 32 ? 32 : 64))))); }
+
 // Per (partition, spike): pivoted Cholesky Y_S^T Y_S = R^T R, B = Q^T V =
-// R^{-T} M_S^T and T = R^{-1} B, then the Gram B^T B and the tips Y_{S,t/b} T
-// of Q Q^T V into the Gram and tip slots (K x K, padded columns).  Grid (p, 2), 256 threads; dynamic LDS
-// of rsvd_small_lds(ell, k) bytes.
+// R^{-T} M_S^T and T = R^{-1} B; the thin QR B^T = Q_b R_h by Gram-Schmidt
+// with reorthogonalization (Q_b, k x ell, over the consumed V^T Y slot;
+// R_h R_h^T, KE x KE with KE = rsvd_ke(ell), zero-padded, into the Gram
+// slot), and the tips Y_{S,t/b} T of Q Q^T V into the tip slots (K x K,
+// padded columns).  Grid (p, 2), 256 threads; dynamic LDS of
+// rsvd_small_lds(ell, k) bytes.
 __host__ __device__ constexpr size_t rsvd_small_lds(int ell, int k) {
-  return ((size_t)ell * (ell + 1) + (size_t)ell * ell + (size_t)ell * (k + 1) + 64) * sizeof(double);
+  return ((size_t)ell * (ell + 1) + (size_t)ell * ell + 2 * (size_t)ell * (k + 1) + 64 + 64) * sizeof(double);
 }
 
 __global__ __launch_bounds__(256) void rsvd_small_kernel(RsvdArgs a) {
@@ -171,6 +179,10 @@ __global__ __launch_bounds__(256) void rsvd_small_kernel(RsvdArgs a) {
   double* R = G + ell * LG;    // ell x ell: R[t * ell + u], row t, pivot position u (upper triangle)
   double* Tm = R + ell * ell;  // ell x LM: M_S^T, then Z = R^{-T} M_S^T, then T = R^{-1} Z
   double* d = Tm + ell * LM;   // residual diagonal by sketch column
+  double* Qb = d + 64;         // ell x LM: rows of Q_b^T (orthonormal rows spanning those of B)
+  double* Rh = G;              // ell x ell: R_h[v * ell + u] (upper triangle; over G, free after the Cholesky)
+  double* cf = Qb + ell * LM;  // 64 Gram-Schmidt coefficients
+  __shared__ double s_inv, s_bn;
   const Geom g = part_geom(L, j, K);
   const double* Gg = rsw<double>(a.ws, L.rgy) + ((size_t)j * 2 + s) * ell * ell;
   const double* M = rsw<double>(a.ws, L.rmv) + ((size_t)j * 2 + s) * k * ell;
@@ -240,15 +252,66 @@ __global__ __launch_bounds__(256) void rsvd_small_kernel(RsvdArgs a) {
       Tm[u * LM + b] = z / R[u * ell + u];
     }
   __syncthreads();
-  // Gram of Q Q^T V: B^T B (symmetric by construction, as the eigensolver needs)
-  const int cof = s == 0 ? 0 : K - k;  // padded column of spike column 0
-  double* gram = rsw<double>(a.ws, L.gram) + ((size_t)j * 2 + s) * K * K;
-  for (int o = tid; o < K * K; o += blockDim.x) {
-    const int b1 = o / K - cof, b2 = o % K - cof;
-    double gv = 0.0;
-    if (b1 >= 0 && b1 < k && b2 >= 0 && b2 < k)
-      for (int u = 0; u < lp; ++u) gv += Tm[u * LM + b1] * Tm[u * LM + b2];
-    gram[o] = gv;
+  // thin QR of B^T: Gram-Schmidt over the rows b_u of B, each projection
+  // pass done twice; a row whose remaining norm falls below 1e-13 of the
+  // largest row norm is dependent and leaves a zero row of Q_b^T
+  for (int o = tid; o < ell * ell; o += blockDim.x) Rh[o] = 0.0;
+  if (tid == 0) {
+    double bm = 0.0;
+    for (int u = 0; u < lp; ++u) {
+      double nn = 0.0;
+      for (int b = 0; b < k; ++b) nn += Tm[u * LM + b] * Tm[u * LM + b];
+      bm = fmax(bm, nn);
+    }
+    s_bn = sqrt(bm);
+  }
+  for (int u = 0; u < lp; ++u) {
+    for (int b = tid; b < k; b += blockDim.x) Qb[u * LM + b] = Tm[u * LM + b];
+    for (int pass = 0; pass < 2; ++pass) {
+      __syncthreads();
+      for (int v = tid; v < u; v += blockDim.x) {
+        double c = 0.0;
+        for (int b = 0; b < k; ++b) c += Qb[v * LM + b] * Qb[u * LM + b];
+        cf[v] = c;
+      }
+      __syncthreads();
+      for (int b = tid; b < k; b += blockDim.x) {
+        double x = Qb[u * LM + b];
+        for (int v = 0; v < u; ++v) x -= cf[v] * Qb[v * LM + b];
+        Qb[u * LM + b] = x;
+      }
+      for (int v = tid; v < u; v += blockDim.x) Rh[v * ell + u] += cf[v];
+    }
+    __syncthreads();
+    if (tid == 0) {
+      double nn = 0.0;
+      for (int b = 0; b < k; ++b) nn += Qb[u * LM + b] * Qb[u * LM + b];
+      const double nr = sqrt(nn);
+      const bool ok = nr > 1e-13 * s_bn;
+      Rh[u * ell + u] = ok ? nr : 0.0;
+      s_inv = ok ? 1.0 / nr : 0.0;
+    }
+    __syncthreads();
+    for (int b = tid; b < k; b += blockDim.x) Qb[u * LM + b] *= s_inv;
+  }
+  __syncthreads();
+  // R_h R_h^T (the nonzero eigenvalues of B^T B), zero-padded to KE x KE,
+  // and Q_b (k x ell, row b = spike column b) over M, which is consumed
+  {
+    const int KE = rsvd_ke(ell);
+    double* gram = rsw<double>(a.ws, L.gram) + ((size_t)j * 2 + s) * KE * KE;
+    for (int o = tid; o < KE * KE; o += blockDim.x) {
+      const int u1 = o / KE, u2 = o % KE;
+      double gv = 0.0;
+      if (u1 < lp && u2 < lp)
+        for (int u = max(u1, u2); u < lp; ++u) gv += Rh[u1 * ell + u] * Rh[u2 * ell + u];
+      gram[o] = gv;
+    }
+    double* qm = rsw<double>(a.ws, L.rmv) + ((size_t)j * 2 + s) * k * ell;
+    for (int o = tid; o < k * ell; o += blockDim.x) {
+      const int b = o / ell, u = o % ell;
+      qm[o] = u < lp ? Qb[u * LM + b] : 0.0;
+    }
   }
   __syncthreads();
   for (int b = tid; b < k; b += blockDim.x)
@@ -259,6 +322,7 @@ __global__ __launch_bounds__(256) void rsvd_small_kernel(RsvdArgs a) {
     }
   __syncthreads();
   // tips of Q Q^T V: Y_{S,t} T, Y_{S,b} T
+  const int cof = s == 0 ? 0 : K - k;  // padded column of spike column 0
   double* tt = rsw<double>(a.ws, L.tips) + ((size_t)j * 4 + 2 * s) * K * K;
   double* tb = tt + (size_t)K * K;
   for (int o = tid; o < K * K; o += blockDim.x) {
@@ -273,6 +337,26 @@ __global__ __launch_bounds__(256) void rsvd_small_kernel(RsvdArgs a) {
       }
     tt[o] = vt;
     tb[o] = vb;
+  }
+}
+
+// Projectors of the randomized truncation: Pi (K x r, padded rows) = Q_b W,
+// W (KE x r) the eigenvectors of R_h R_h^T for the r largest eigenvalues
+// (written by the eigensolver at W, KE x r per (partition, spike)); rows
+// outside the spike's k columns are zero.  Grid (p, 2), 256 threads.
+__global__ __launch_bounds__(256) void rsvd_lift_kernel(RsvdArgs a, const double* W) {
+  const Layout& L = a.L;
+  const int j = blockIdx.x, s = blockIdx.y, ell = L.ell, k = L.k, K = L.K, r = L.r, KE = rsvd_ke(ell);
+  const int cof = s == 0 ? 0 : K - k;
+  const double* qm = rsw<double>(a.ws, L.rmv) + ((size_t)j * 2 + s) * k * ell;
+  const double* w = W + ((size_t)j * 2 + s) * KE * r;
+  double* pi = rsw<double>(a.ws, L.proj) + ((size_t)j * 2 + s) * K * r;
+  for (int o = threadIdx.x; o < K * r; o += blockDim.x) {
+    const int i = o / r, q = o % r, b = i - cof;
+    double v = 0.0;
+    if (b >= 0 && b < k)
+      for (int u = 0; u < ell; ++u) v += qm[b * ell + u] * w[u * r + q];
+    pi[o] = v;
   }
 }
 
