@@ -54,7 +54,7 @@ __device__ inline T* rws(char* ws, size_t off) {
 // the eigenvectors of the r largest eigenvalues as the columns of Pi (K x r).
 // Launched with LRS_NT threads.
 template <int K>
-__global__ __launch_bounds__(LRS_NT) void eigen_kernel(RedArgs a) {
+__global__ __launch_bounds__(LRS_NT) __attribute__((aligned(4096))) void eigen_kernel(RedArgs a) {
   constexpr int LD = K + 1;
   constexpr int KE = (K % 2) ? K + 1 : K;  // players in the tournament
   extern __shared__ __align__(16) double eig_lds[];  // G and V, K x LD each (dynamic: 66.5 KB at K = 64)

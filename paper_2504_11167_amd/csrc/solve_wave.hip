@@ -518,7 +518,7 @@ __device__ void bwd_wave(const SolveArgs& a, const Geom& g, int j, int c0) {
 }
 
 template <typename T, int K, int MCT>
-__global__ __launch_bounds__(64) void dstage_wave_kernel(SolveArgs a) {
+__global__ __launch_bounds__(64) __attribute__((aligned(4096))) void dstage_wave_kernel(SolveArgs a) {
   if (gated(a.gate)) return;
   extern __shared__ __align__(16) unsigned char lds_raw[];
   T* lds = reinterpret_cast<T*>(lds_raw);
@@ -528,7 +528,7 @@ __global__ __launch_bounds__(64) void dstage_wave_kernel(SolveArgs a) {
 }
 
 template <typename T, int K, int MCT>
-__global__ __launch_bounds__(64) void retrieve_wave_kernel(SolveArgs a) {
+__global__ __launch_bounds__(64) __attribute__((aligned(4096))) void retrieve_wave_kernel(SolveArgs a) {
   if (gated(a.gate)) return;
   using W = WaveSweep<T, K, MCT>;
   constexpr int NC = W::NC;
@@ -732,7 +732,7 @@ __device__ void tbwd_wave(const SolveArgs& a, const Geom& g, int j, int c0) {
 // W into a.dst, then L^T sweep), tips nu_t, nu_b to the tip buffer.
 // Partitions factored with interchanges are left to adj_dstage_kernel.
 template <typename T, int K>
-__global__ __launch_bounds__(64) void adj_dstage_wave_kernel(SolveArgs a) {
+__global__ __launch_bounds__(64) __attribute__((aligned(4096))) void adj_dstage_wave_kernel(SolveArgs a) {
   if (gated(a.gate)) return;
   const int j = blockIdx.x, c0 = blockIdx.y * 16;
   if (wsp<int>(a.ws, a.L.npv)[j]) return;
@@ -747,7 +747,7 @@ __global__ __launch_bounds__(64) void adj_dstage_wave_kernel(SolveArgs a) {
 //   w_{j,b} = C_{j+1}^T nu_{j+1,t} - Psi_{j+1} u_c(j+1)      (j <= p-2)
 // (u = Z^{-T} L^T h in the compressed vector); LR-SPIKE-T needs no change here.
 template <typename T, int K>
-__global__ __launch_bounds__(64) void adj_retrieve_wave_kernel(SolveArgs a) {
+__global__ __launch_bounds__(64) __attribute__((aligned(4096))) void adj_retrieve_wave_kernel(SolveArgs a) {
   if (gated(a.gate)) return;
   using W = WaveSweep<T, K, 1>;
   constexpr int NC = W::NC;
@@ -913,7 +913,7 @@ __device__ void pass2_wave_impl(const FactorArgs& a, const Geom& g, int j, int s
 // The interchange flags are read only for partitions factored with
 // interchanges (a compile-time variant: elsewhere they are all zero).
 template <typename T, int K>
-__global__ __launch_bounds__(64) void pass2_wave_kernel(FactorArgs a) {
+__global__ __launch_bounds__(64) __attribute__((aligned(4096))) void pass2_wave_kernel(FactorArgs a) {
   const int j = blockIdx.x, spike = blockIdx.y;
   const Geom g = part_geom(a.L, j, K);
   if (wsT<int>(a.ws, a.L.npv)[j] != 0)
