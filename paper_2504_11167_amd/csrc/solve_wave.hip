@@ -805,7 +805,10 @@ __device__ void pass2_wave_impl(const FactorArgs& a, const Geom& g, int j, int s
   constexpr int MCT = K / 16;
   using W = WaveSweep<T, K, MCT>;
   using V = typename W::V;
-  constexpr int NF = W::RT * W::KS, PD = sweep_pd<K, MCT>(), NS = PD + 1;
+  // no prefetch at K = 32: the kernel then fits two waves per SIMD (the grid
+  // has a wave per partition and spike, twice the SIMDs at p = 1024), and the
+  // second wave hides the loads of the first (0.84 -> 0.72 ms at n = 2^22)
+  constexpr int NF = W::RT * W::KS, PD = (K == 32 ? 0 : sweep_pd<K, MCT>()), NS = PD + 1;
   const Layout& L = a.L;
   const int lane = threadIdx.x & 63, nb = g.nb;
   const T* fac = wsT<T>(a.ws, L.fac) + (size_t)j * L.nbmax * L.rec;
@@ -913,7 +916,7 @@ __device__ void pass2_wave_impl(const FactorArgs& a, const Geom& g, int j, int s
 // The interchange flags are read only for partitions factored with
 // interchanges (a compile-time variant: elsewhere they are all zero).
 template <typename T, int K>
-__global__ __launch_bounds__(64) __attribute__((aligned(4096))) void pass2_wave_kernel(FactorArgs a) {
+__global__ __launch_bounds__(64) __attribute__((aligned(4096))) __attribute__((amdgpu_waves_per_eu(2))) void pass2_wave_kernel(FactorArgs a) {
   const int j = blockIdx.x, spike = blockIdx.y;
   const Geom g = part_geom(a.L, j, K);
   if (wsT<int>(a.ws, a.L.npv)[j] != 0)
